@@ -1,0 +1,185 @@
+/*
+ * prgd.h -- C ABI of the MI355X (gfx950) library for low-TT-rank tensor
+ * completion by preconditioned Riemannian gradient descent (PRGD).
+ *
+ * Method: Bian, Cai, Zhang & Zhang, "Fast and Provable Tensor-Train Format
+ * Tensor Completion via Preconditioned Riemannian Gradient Descent".
+ *
+ *   Problem (section 1, completion model): find T of TT rank r minimising
+ *     f(T) = 1/2 <T - T*, P_Omega(T - T*)>, given the entries y_j of T* (plus
+ *     noise) at the observed multi-indices x^(j) in Omega.
+ *   TT format (section 2.1): T(x) = T_1(x_1,:) T_2(:,x_2,:) ... T_m(:,x_m),
+ *     core T_k of shape r_{k-1} x n_k x r_k with r_0 = r_m = 1.
+ *   Iteration (Algorithm 2, trimming skipped as section 3.2.2 allows):
+ *     G_l = P_Omega(T_l - T*); metric weights G_{l,i} = eps I +
+ *     diag(M_i(G_l) M_i(G_l)^T) (section 3.2.1); direction
+ *     xi = P~_T W^{-1} G_l (Lemma 3); W_l = T_l - alpha_l xi;
+ *     T_{l+1} = TT-SVD_r(W_l) (Algorithm 1).
+ *
+ * Conventions shared by every call
+ *   - All integers are int32 unless stated; sizes that can exceed 2^31 are int64.
+ *   - Cores are passed "packed": core k = 1..m as a row-major array of shape
+ *     (r_{k-1}, n_k, r_k) (index (a, x, b) -> a*n_k*r_k + x*r_k + b), the m cores
+ *     concatenated in order; prgd_cores_numel() gives the total length.
+ *   - Multi-indices are 0-based, structure of arrays: indices[k*N + j] is the
+ *     mode-(k+1) index of sample j, 0 <= indices[k*N+j] < n_k.
+ *   - Host pointers are read only during the call that receives them; the
+ *     library copies what it keeps.  Device pointers (mem_device = 1) must be
+ *     device memory of the current HIP device, readable for the duration of
+ *     the call.
+ *   - Return codes: prgd_status values below.  No exception crosses the ABI.
+ *     A negative code leaves output buffers unspecified; prgd_last_error()
+ *     returns a thread-local message for the last failing call.
+ *   - A solver handle must not be used from two threads at once.
+ *   - Limits of this build: order m in [2, 32]; TT ranks <= 16; mode sizes
+ *     in [1, 2^31); N in [1, 2^31).
+ */
+#ifndef PRGD_H
+#define PRGD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t prgd_status;
+
+#define PRGD_OK              0   /* success; for prgd_run: stopping rule met          */
+#define PRGD_NOT_CONVERGED   1   /* max_iter reached; cores are the last iterate      */
+#define PRGD_PENDING         2   /* server: request not finished yet                  */
+#define PRGD_EINVAL         -1   /* invalid shape, rank, index, value, tolerance       */
+#define PRGD_EDUPLICATE     -2   /* a multi-index occurs twice in Omega               */
+#define PRGD_ENOMEM         -3   /* host or device allocation failed / over budget    */
+#define PRGD_EDEVICE        -4   /* HIP runtime error                                  */
+#define PRGD_EBREAKDOWN     -5   /* non-positive-definite Gram, non-finite residual,   */
+                                 /* or rank-deficient truncation                       */
+#define PRGD_ESTATE         -6   /* null or destroyed handle, wrong call order         */
+#define PRGD_ENOTSUP        -7   /* outside the limits of this build                   */
+
+/* precision */
+#define PRGD_PREC_FP64   0   /* every step in float64                                        */
+#define PRGD_PREC_MIXED  1   /* sampled pass (evaluation, residual, weights, gradient
+                                scatter) in float32 with float32 accumulation; Grams,
+                                factorisations, retraction and stopping test in float64     */
+/* step policy (section 3.2.2 and Theorem 1) */
+#define PRGD_STEP_THEORY 0   /* alpha_l = step * eps_l^{1/2} / p, p = N / (n_1...n_m);
+                                Theorem 1 uses step = 1.001                                 */
+#define PRGD_STEP_CONST  1   /* alpha_l = step for every l; requires eps_fixed > 0          */
+/* stopping rule, tested with tolerance tol */
+#define PRGD_STOP_RESIDUAL 0 /* ||P_Omega(T_l) - y||_2 / ||y||_2 <= tol, tested on T_l      */
+#define PRGD_STOP_CHANGE   1 /* ||T_{l+1} - T_l||_F <= tol * max(1, ||T_l||_F)
+                                (section 5.1, noise experiment)                             */
+#define PRGD_STOP_ERROR    2 /* ||T_{l+1} - T*||_F / ||T*||_F <= tol; needs truth_cores     */
+#define PRGD_STOP_NONE     3 /* run exactly max_iter iterations                             */
+
+typedef struct prgd_solver_s *prgd_solver;
+
+typedef struct {
+  int32_t order;               /* m >= 2                                                   */
+  const int32_t *mode_sizes;   /* host [m], n_k >= 1                                       */
+  const int32_t *tt_ranks;     /* host [m+1], r_0 = r_m = 1, 1 <= r_k <=
+                                  min(n_1...n_k, n_{k+1}...n_m), r_k <= 16                 */
+  int64_t n_obs;               /* N = |Omega| >= 1; multi-indices must be distinct         */
+  const int32_t *indices;      /* [m*N] SoA multi-indices (host or device, see mem_device) */
+  const void *values;          /* [N] observed values y_j, float64 or float32              */
+  int32_t values_fp64;         /* 1: values are double; 0: float                           */
+  int32_t mem_device;          /* 1: indices and values are device pointers                */
+  const double *init_cores;    /* host, packed T_0 (required; any TT of ranks tt_ranks)    */
+  const double *truth_cores;   /* host, packed T* or NULL; enables STOP_ERROR and the
+                                  relative error in reports                                */
+  int32_t precision;           /* PRGD_PREC_*                                              */
+  int32_t step_policy;         /* PRGD_STEP_*                                              */
+  double step;                 /* step constant c (THEORY) or step alpha (CONST), > 0      */
+  double eps_fixed;            /* > 0: fixed eps in G_{l,i}; <= 0: eps_l = ||G_l||_vee^2,
+                                  the largest squared mode-slice norm of G_l (Appendix B)  */
+  int32_t stop_rule;           /* PRGD_STOP_*                                              */
+  double tol;                  /* >= 0                                                     */
+  int32_t max_iter;            /* >= 0                                                     */
+  int32_t sort_mode;           /* mode (0-based) by which Omega is grouped on the device;
+                                  -1 chooses the mode with the largest r_{k-1} r_k         */
+  void *stream;                /* hipStream_t to run on; NULL: a stream owned by the solver */
+} prgd_desc;
+
+/* One row of the per-iteration record kept on the device. */
+typedef struct {
+  int32_t iter;                /* l: the record describes the step T_l -> T_{l+1}          */
+  int32_t flags;               /* bit0: rel_change valid, bit1: rel_error valid            */
+  double rel_residual;         /* ||P_Omega T_l - y|| / ||y||                               */
+  double rel_change;           /* ||T_{l+1} - T_l|| / max(1, ||T_l||)                       */
+  double rel_error;            /* ||T_{l+1} - T*|| / ||T*||                                 */
+  double eps;                  /* eps_l used in the metric                                  */
+  double alpha;                /* alpha_l                                                   */
+} prgd_iter_info;
+
+typedef struct {
+  int32_t iterations;          /* completed iterations l                                    */
+  int32_t status;              /* PRGD_OK / PRGD_NOT_CONVERGED / negative error             */
+  double rel_residual;         /* of the returned iterate's last evaluated residual         */
+  double rel_change;           /* last computed relative change (NaN if never)             */
+  double rel_error;            /* relative error of the returned iterate (NaN if no truth) */
+  double seconds;              /* device-synchronised wall time of the iteration loop      */
+} prgd_report;
+
+/* Total length of the packed cores for shape n[m] and ranks r[m+1] (-1 if invalid). */
+int64_t prgd_cores_numel(int32_t m, const int32_t *n, const int32_t *r);
+
+/* Validate the problem on the host, copy it to the device, group Omega by
+   sort_mode, left-orthogonalise T_0 and prepare the iteration.  Validation
+   (shapes, ranks, index ranges, duplicate multi-indices, finite values) runs
+   before any GPU work.  On success *out owns all device memory of the solve. */
+prgd_status prgd_create(const prgd_desc *desc, prgd_solver *out);
+
+/* Enqueue exactly `iters` iterations (fewer if the stopping rule fires or
+   max_iter is reached: later iterations become no-ops on the device) without
+   synchronising.  Returns PRGD_OK once enqueued. */
+prgd_status prgd_iterate(prgd_solver s, int32_t iters);
+
+/* Wait for the solver's stream. */
+prgd_status prgd_sync(prgd_solver s);
+
+/* Iterate until the stopping rule holds or max_iter iterations, then fill
+   *report (may be NULL).  Returns PRGD_OK, PRGD_NOT_CONVERGED or an error. */
+prgd_status prgd_run(prgd_solver s, prgd_report *report);
+
+/* Current state without iterating (synchronises). */
+prgd_status prgd_get_report(prgd_solver s, prgd_report *report);
+
+/* Copy the current iterate, packed, into host memory out[cap].  Cores 1..m-1
+   are left-orthogonal after any completed iteration. */
+prgd_status prgd_get_cores(prgd_solver s, double *out, int64_t cap);
+
+/* Copy up to cap per-iteration records into out; *count receives the number
+   of records written (one per completed or stopped iteration). */
+prgd_status prgd_get_history(prgd_solver s, prgd_iter_info *out, int32_t cap, int32_t *count);
+
+/* Hot path in isolation (rows a1-a3 of the iteration): evaluate the current
+   iterate on Omega, form the residual R_j = T_l(x^(j)) - y_j, and return
+   (host arrays, any may be NULL)
+     grad[numel]   packed like the cores: df/dT_k(:,x,:) = sum_{j: x_k=x} R_j
+                   T^{<=k-1}(x^(j))^T T^{>=k+1}(x^(j))^T  (chain rule on the TT format)
+     slice_sq[sum n_k]  s_k(x) = sum_{j: x_k = x} R_j^2, mode after mode
+                   (squared row norms of the mode unfoldings of G_l, section 3.2.1)
+     res_sq        sum_j R_j^2.
+   Arithmetic follows the solver's precision.  Does not advance the iteration. */
+prgd_status prgd_sampled_pass(prgd_solver s, double *grad, double *slice_sq, double *res_sq);
+
+/* Evaluate a TT (section 2.1, TT format) at N multi-indices on the GPU:
+   out[j] = T(x^(j)).  cores: host packed float64; indices: SoA [m*N]
+   (device if mem_device, else host); out: float64 [N] in the same memory
+   kind as indices.  stream: hipStream_t or NULL (default stream); the call
+   returns after the result is written. */
+prgd_status prgd_eval(int32_t m, const int32_t *n, const int32_t *r, const double *cores,
+                      int64_t n_obs, const int32_t *indices, double *out, int32_t mem_device,
+                      void *stream);
+
+prgd_status prgd_destroy(prgd_solver s);
+
+const char *prgd_status_str(prgd_status st);
+const char *prgd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PRGD_H */

@@ -1,0 +1,351 @@
+"""ctypes binding of libprgd.so (include/prgd.h).  Argument marshalling only.
+
+Every function named ``prgd_*`` here calls the C entry point of the same name;
+all arithmetic of the method runs in the library's HIP kernels.  Importing
+this module loads the library and raises if it has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprgd.so")
+
+OK, NOT_CONVERGED, PENDING = 0, 1, 2
+EINVAL, EDUPLICATE, ENOMEM, EDEVICE, EBREAKDOWN, ESTATE, ENOTSUP = -1, -2, -3, -4, -5, -6, -7
+PREC = {"fp64": 0, "mixed": 1}
+STEP = {"theory": 0, "const": 1}
+STOP = {"residual": 0, "change": 1, "error": 2, "none": 3}
+
+
+class PrgdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{status}: {msg}")
+        self.status = status
+
+
+class prgd_desc(C.Structure):
+    _fields_ = [
+        ("order", C.c_int32),
+        ("mode_sizes", C.POINTER(C.c_int32)),
+        ("tt_ranks", C.POINTER(C.c_int32)),
+        ("n_obs", C.c_int64),
+        ("indices", C.c_void_p),
+        ("values", C.c_void_p),
+        ("values_fp64", C.c_int32),
+        ("mem_device", C.c_int32),
+        ("init_cores", C.POINTER(C.c_double)),
+        ("truth_cores", C.POINTER(C.c_double)),
+        ("precision", C.c_int32),
+        ("step_policy", C.c_int32),
+        ("step", C.c_double),
+        ("eps_fixed", C.c_double),
+        ("stop_rule", C.c_int32),
+        ("tol", C.c_double),
+        ("max_iter", C.c_int32),
+        ("sort_mode", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
+class prgd_iter_info(C.Structure):
+    _fields_ = [
+        ("iter", C.c_int32),
+        ("flags", C.c_int32),
+        ("rel_residual", C.c_double),
+        ("rel_change", C.c_double),
+        ("rel_error", C.c_double),
+        ("eps", C.c_double),
+        ("alpha", C.c_double),
+    ]
+
+
+class prgd_report(C.Structure):
+    _fields_ = [
+        ("iterations", C.c_int32),
+        ("status", C.c_int32),
+        ("rel_residual", C.c_double),
+        ("rel_change", C.c_double),
+        ("rel_error", C.c_double),
+        ("seconds", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2501_13385_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    i32p = C.POINTER(C.c_int32)
+    sig = {
+        "prgd_cores_numel": (i64, [i32, i32p, i32p]),
+        "prgd_create": (i32, [C.POINTER(prgd_desc), C.POINTER(vp)]),
+        "prgd_iterate": (i32, [vp, i32]),
+        "prgd_sync": (i32, [vp]),
+        "prgd_run": (i32, [vp, C.POINTER(prgd_report)]),
+        "prgd_get_report": (i32, [vp, C.POINTER(prgd_report)]),
+        "prgd_get_cores": (i32, [vp, dp, i64]),
+        "prgd_get_history": (i32, [vp, C.POINTER(prgd_iter_info), i32, i32p]),
+        "prgd_sampled_pass": (i32, [vp, dp, dp, dp]),
+        "prgd_eval": (i32, [i32, i32p, i32p, dp, i64, vp, vp, i32, vp]),
+        "prgd_destroy": (i32, [vp]),
+        "prgd_status_str": (C.c_char_p, [i32]),
+        "prgd_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> List[str]:
+    return [n for n in ("prgd_cores_numel", "prgd_create", "prgd_iterate", "prgd_sync", "prgd_run",
+                        "prgd_get_report", "prgd_get_cores", "prgd_get_history", "prgd_sampled_pass",
+                        "prgd_eval", "prgd_destroy", "prgd_status_str", "prgd_last_error")]
+
+
+def _check(st: int, allow=(OK,)) -> int:
+    if st in allow:
+        return st
+    lib = load()
+    raise PrgdError(st, f"{lib.prgd_status_str(st).decode()}: {lib.prgd_last_error().decode()}")
+
+
+def _i32arr(v: Sequence[int]):
+    a = (C.c_int32 * len(v))(*[int(x) for x in v])
+    return a
+
+
+def pack(cores: Sequence[np.ndarray]) -> np.ndarray:
+    """Packed layout of include/prgd.h: each core (r_{k-1}, n_k, r_k) in C order, concatenated."""
+    return np.ascontiguousarray(np.concatenate([np.ascontiguousarray(c, dtype=np.float64).ravel() for c in cores]))
+
+
+def unpack(flat: np.ndarray, shape: Sequence[int], ranks: Sequence[int]) -> List[np.ndarray]:
+    out, p = [], 0
+    for k in range(len(shape)):
+        sz = ranks[k] * shape[k] * ranks[k + 1]
+        out.append(flat[p:p + sz].reshape(ranks[k], shape[k], ranks[k + 1]).copy())
+        p += sz
+    return out
+
+
+def prgd_cores_numel(shape: Sequence[int], ranks: Sequence[int]) -> int:
+    return int(load().prgd_cores_numel(len(shape), _i32arr(shape), _i32arr(ranks)))
+
+
+def prgd_status_str(st: int) -> str:
+    return load().prgd_status_str(st).decode()
+
+
+def prgd_last_error() -> str:
+    return load().prgd_last_error().decode()
+
+
+def _ptr_of(a):
+    """Device pointer of a torch tensor, or host pointer of a numpy array."""
+    if hasattr(a, "data_ptr"):
+        return int(a.data_ptr()), True
+    return a.ctypes.data, False
+
+
+def prgd_create(shape, ranks, indices, values, init_cores, *, truth_cores=None, precision="fp64",
+                step_policy="theory", step=1.0, eps_fixed=0.0, stop_rule="residual", tol=1e-10,
+                max_iter=500, sort_mode=-1, stream=None):
+    """Create a solver.  ``indices`` (m, N) int32 and ``values`` (N,) float64/float32 are numpy
+    arrays (host) or torch CUDA tensors (device).  Returns an opaque handle (int)."""
+    lib = load()
+    m = len(shape)
+    keep = []
+    if hasattr(indices, "data_ptr"):
+        assert indices.is_contiguous() and values.is_contiguous()
+        n_obs = int(indices.shape[1])
+        vfp64 = 1 if str(values.dtype) == "torch.float64" else 0
+        ip, _ = _ptr_of(indices)
+        vp_, _ = _ptr_of(values)
+        mem_device = 1
+    else:
+        indices = np.ascontiguousarray(indices, dtype=np.int32)
+        values = np.ascontiguousarray(values)
+        if values.dtype not in (np.float64, np.float32):
+            values = values.astype(np.float64)
+        keep += [indices, values]
+        n_obs = int(indices.shape[1])
+        vfp64 = 1 if values.dtype == np.float64 else 0
+        ip, vp_ = indices.ctypes.data, values.ctypes.data
+        mem_device = 0
+    init = pack(init_cores)
+    keep.append(init)
+    truth = pack(truth_cores) if truth_cores is not None else None
+    if truth is not None:
+        keep.append(truth)
+    ns, rs = _i32arr(shape), _i32arr(ranks)
+    d = prgd_desc()
+    d.order = m
+    d.mode_sizes = ns
+    d.tt_ranks = rs
+    d.n_obs = n_obs
+    d.indices = ip
+    d.values = vp_
+    d.values_fp64 = vfp64
+    d.mem_device = mem_device
+    d.init_cores = init.ctypes.data_as(C.POINTER(C.c_double))
+    d.truth_cores = truth.ctypes.data_as(C.POINTER(C.c_double)) if truth is not None else None
+    d.precision = PREC[precision]
+    d.step_policy = STEP[step_policy]
+    d.step = float(step)
+    d.eps_fixed = float(eps_fixed)
+    d.stop_rule = STOP[stop_rule]
+    d.tol = float(tol)
+    d.max_iter = int(max_iter)
+    d.sort_mode = int(sort_mode)
+    d.stream = stream
+    h = C.c_void_p()
+    _check(lib.prgd_create(C.byref(d), C.byref(h)))
+    return h.value
+
+
+def prgd_iterate(h, iters: int) -> None:
+    _check(load().prgd_iterate(h, int(iters)))
+
+
+def prgd_sync(h) -> None:
+    _check(load().prgd_sync(h))
+
+
+def _report(rep: prgd_report) -> dict:
+    return {"iterations": rep.iterations, "status": rep.status, "rel_residual": rep.rel_residual,
+            "rel_change": rep.rel_change, "rel_error": rep.rel_error, "seconds": rep.seconds}
+
+
+def prgd_run(h) -> dict:
+    rep = prgd_report()
+    st = load().prgd_run(h, C.byref(rep))
+    _check(st, allow=(OK, NOT_CONVERGED))
+    return _report(rep)
+
+
+def prgd_get_report(h) -> dict:
+    rep = prgd_report()
+    _check(load().prgd_get_report(h, C.byref(rep)))
+    return _report(rep)
+
+
+def prgd_get_cores(h, shape, ranks) -> List[np.ndarray]:
+    numel = prgd_cores_numel(shape, ranks)
+    out = np.empty(numel, dtype=np.float64)
+    _check(load().prgd_get_cores(h, out.ctypes.data_as(C.POINTER(C.c_double)), numel))
+    return unpack(out, shape, ranks)
+
+
+def prgd_get_history(h, cap: int = 100000) -> List[dict]:
+    buf = (prgd_iter_info * cap)()
+    cnt = C.c_int32(0)
+    _check(load().prgd_get_history(h, buf, cap, C.byref(cnt)))
+    out = []
+    for i in range(cnt.value):
+        r = buf[i]
+        rec = {"iter": r.iter, "rel_residual": r.rel_residual, "eps": r.eps, "alpha": r.alpha}
+        if r.flags & 1:
+            rec["rel_change"] = r.rel_change
+        if r.flags & 2:
+            rec["rel_error"] = r.rel_error
+        out.append(rec)
+    return out
+
+
+def prgd_sampled_pass(h, shape, ranks):
+    numel = prgd_cores_numel(shape, ranks)
+    grad = np.empty(numel, dtype=np.float64)
+    ssq = np.empty(int(sum(shape)), dtype=np.float64)
+    rsq = C.c_double(0.0)
+    _check(load().prgd_sampled_pass(h, grad.ctypes.data_as(C.POINTER(C.c_double)),
+                                    ssq.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rsq)))
+    splits = np.cumsum(shape)[:-1]
+    return unpack(grad, shape, ranks), list(np.split(ssq, splits)), float(rsq.value)
+
+
+def prgd_eval(shape, ranks, cores, indices, out=None, stream=None):
+    """TT values at the columns of ``indices``; numpy in -> numpy out, torch CUDA in -> torch CUDA out."""
+    lib = load()
+    flat = pack(cores)
+    m = len(shape)
+    if hasattr(indices, "data_ptr"):
+        import torch
+        n_obs = int(indices.shape[1])
+        if out is None:
+            out = torch.empty(n_obs, dtype=torch.float64, device=indices.device)
+        _check(lib.prgd_eval(m, _i32arr(shape), _i32arr(ranks), flat.ctypes.data_as(C.POINTER(C.c_double)),
+                             n_obs, int(indices.data_ptr()), int(out.data_ptr()), 1, stream))
+        return out
+    idx = np.ascontiguousarray(indices, dtype=np.int32)
+    n_obs = int(idx.shape[1])
+    res = np.empty(n_obs, dtype=np.float64)
+    _check(lib.prgd_eval(m, _i32arr(shape), _i32arr(ranks), flat.ctypes.data_as(C.POINTER(C.c_double)),
+                         n_obs, idx.ctypes.data, res.ctypes.data, 0, stream))
+    return res
+
+
+def prgd_destroy(h) -> None:
+    _check(load().prgd_destroy(h))
+
+
+class Solver:
+    """Convenience owner of one solver handle (calls the functions above)."""
+
+    def __init__(self, shape, ranks, indices, values, init_cores, **kw):
+        self.shape = [int(s) for s in shape]
+        self.ranks = [int(r) for r in ranks]
+        self.h = prgd_create(self.shape, self.ranks, indices, values, init_cores, **kw)
+
+    def iterate(self, k: int):
+        prgd_iterate(self.h, k)
+
+    def sync(self):
+        prgd_sync(self.h)
+
+    def run(self) -> dict:
+        return prgd_run(self.h)
+
+    def report(self) -> dict:
+        return prgd_get_report(self.h)
+
+    def cores(self) -> List[np.ndarray]:
+        return prgd_get_cores(self.h, self.shape, self.ranks)
+
+    def history(self) -> List[dict]:
+        return prgd_get_history(self.h)
+
+    def sampled_pass(self):
+        return prgd_sampled_pass(self.h, self.shape, self.ranks)
+
+    def close(self):
+        if self.h:
+            prgd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,625 @@
+// Host runtime of the PRGD library: validation, device memory, launch
+// sequencing and the C ABI declared in include/prgd.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/prgd.h"
+#include "prgd_internal.hpp"
+
+namespace prgd {
+hipError_t launch_sampled(const Dev &d, int diag, int nblocks, hipStream_t s);
+int sampled_block_size(int m, int R, int prec);
+hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *cores, const long long *coff_dev,
+                       double *out, hipStream_t s);
+hipError_t launch_dense_iteration(const Dev &d, hipStream_t s, int init);
+hipError_t launch_truth_sweep(const Dev &d, hipStream_t s, int mode);
+hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *idx_in, const void *values_in,
+                         int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s);
+hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
+hipError_t fill_f32(float *p, long long n, float v, hipStream_t s);
+hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream_t s);
+}  // namespace prgd
+
+using namespace prgd;
+
+namespace {
+
+thread_local std::string g_err;
+
+prgd_status fail(prgd_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHECK(call)                                                                                   \
+  do {                                                                                                   \
+    hipError_t _e = (call);                                                                              \
+    if (_e != hipSuccess) return fail(PRGD_EDEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+int padded_dim(int rmax) {
+  static const int buckets[] = {2, 4, 6, 8, 10, 12, 16};
+  for (int b : buckets)
+    if (rmax <= b) return b;
+  return -1;
+}
+
+bool checked_numel(int m, const int32_t *n, const int32_t *r, int64_t &out) {
+  if (m < 2 || m > MAXM || !n || !r) return false;
+  if (r[0] != 1 || r[m] != 1) return false;
+  int64_t tot = 0;
+  for (int k = 0; k < m; ++k) {
+    if (n[k] < 1 || r[k] < 1 || r[k + 1] < 1) return false;
+    tot += (int64_t)r[k] * n[k] * r[k + 1];
+  }
+  out = tot;
+  return true;
+}
+
+// packed (a, x, b) row-major per core  ->  padded slice-major (x, a, b), R x R slices
+void pack_cores(int m, const int *n, const int *r, int R, const double *src, std::vector<double> &dst,
+                const std::vector<long long> &coff) {
+  dst.assign(coff[m], 0.0);
+  long long p = 0;
+  for (int k = 0; k < m; ++k)
+    for (int a = 0; a < r[k]; ++a)
+      for (int x = 0; x < n[k]; ++x)
+        for (int b = 0; b < r[k + 1]; ++b) dst[coff[k] + ((long long)x * R + a) * R + b] = src[p++];
+}
+
+void unpack_cores(int m, const int *n, const int *r, int R, const double *src, double *dst,
+                  const std::vector<long long> &coff) {
+  long long p = 0;
+  for (int k = 0; k < m; ++k)
+    for (int a = 0; a < r[k]; ++a)
+      for (int x = 0; x < n[k]; ++x)
+        for (int b = 0; b < r[k + 1]; ++b) dst[p++] = src[coff[k] + ((long long)x * R + a) * R + b];
+}
+
+}  // namespace
+
+struct prgd_solver_s {
+  Dev d{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int m = 0, R = 0;
+  std::vector<int> n, r;
+  std::vector<long long> coff;
+  long long N = 0;
+  int64_t numel = 0;
+  int sampled_blocks = 0;
+  bool has_truth = false;
+  std::vector<void *> allocs;
+  double last_seconds = 0.0;
+
+  ~prgd_solver_s() {
+    if (stream) hipStreamSynchronize(stream);
+    for (void *p : allocs) hipFree(p);
+    if (own_stream && stream) hipStreamDestroy(stream);
+  }
+  template <typename T>
+  hipError_t alloc(T **p, long long count) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, (size_t)std::max<long long>(count, 1) * sizeof(T));
+    if (e == hipSuccess) {
+      allocs.push_back(q);
+      *p = (T *)q;
+    }
+    return e;
+  }
+};
+
+namespace {
+
+prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *vals, int64_t &numel) {
+  const int m = ds->order;
+  if (m < 2 || m > MAXM) return fail(m < 2 ? PRGD_EINVAL : PRGD_ENOTSUP, "order must be in [2, 32]");
+  if (!checked_numel(m, ds->mode_sizes, ds->tt_ranks, numel))
+    return fail(PRGD_EINVAL, "invalid mode sizes or ranks (need n_k >= 1, r_0 = r_m = 1, r_k >= 1)");
+  const int32_t *n = ds->mode_sizes, *r = ds->tt_ranks;
+  for (int k = 1; k < m; ++k) {
+    if (r[k] > RMAX) return fail(PRGD_ENOTSUP, "TT ranks above 16 are not supported by this build");
+    double left = 1, right = 1;
+    for (int i = 0; i < k; ++i) left *= n[i];
+    for (int i = k; i < m; ++i) right *= n[i];
+    if ((double)r[k] > left || (double)r[k] > right)
+      return fail(PRGD_EINVAL, "rank r_" + std::to_string(k) + " exceeds the size of the separation");
+  }
+  const long long N = ds->n_obs;
+  if (N < 1 || N >= (1LL << 31)) return fail(PRGD_EINVAL, "n_obs must be in [1, 2^31)");
+  if (!(ds->tol >= 0.0) || ds->max_iter < 0) return fail(PRGD_EINVAL, "tol must be >= 0 and max_iter >= 0");
+  if (!(ds->step > 0.0) || !std::isfinite(ds->step)) return fail(PRGD_EINVAL, "step must be positive");
+  if (ds->precision != PRGD_PREC_FP64 && ds->precision != PRGD_PREC_MIXED) return fail(PRGD_EINVAL, "precision");
+  if (ds->step_policy != PRGD_STEP_THEORY && ds->step_policy != PRGD_STEP_CONST)
+    return fail(PRGD_EINVAL, "step_policy");
+  if (ds->step_policy == PRGD_STEP_CONST && !(ds->eps_fixed > 0.0))
+    return fail(PRGD_EINVAL, "the constant step policy needs eps_fixed > 0");
+  if (ds->stop_rule < PRGD_STOP_RESIDUAL || ds->stop_rule > PRGD_STOP_NONE) return fail(PRGD_EINVAL, "stop_rule");
+  if (ds->stop_rule == PRGD_STOP_ERROR && !ds->truth_cores) return fail(PRGD_EINVAL, "STOP_ERROR needs truth_cores");
+  if (!ds->init_cores) return fail(PRGD_EINVAL, "init_cores is required");
+  if (ds->sort_mode < -1 || ds->sort_mode >= m) return fail(PRGD_EINVAL, "sort_mode");
+  for (int64_t i = 0; i < numel; ++i)
+    if (!std::isfinite(ds->init_cores[i])) return fail(PRGD_EINVAL, "init_cores has a non-finite entry");
+  if (ds->truth_cores)
+    for (int64_t i = 0; i < numel; ++i)
+      if (!std::isfinite(ds->truth_cores[i])) return fail(PRGD_EINVAL, "truth_cores has a non-finite entry");
+  // indices in range, values finite
+  for (int k = 0; k < m; ++k) {
+    const int32_t *row = idx + (long long)k * N;
+    for (long long j = 0; j < N; ++j)
+      if (row[j] < 0 || row[j] >= n[k])
+        return fail(PRGD_EINVAL, "index out of range in mode " + std::to_string(k) + " at sample " + std::to_string(j));
+  }
+  for (long long j = 0; j < N; ++j) {
+    const double v = ds->values_fp64 ? ((const double *)vals)[j] : (double)((const float *)vals)[j];
+    if (!std::isfinite(v)) return fail(PRGD_EINVAL, "non-finite observed value at sample " + std::to_string(j));
+  }
+  // distinct multi-indices
+  double dstar = 1;
+  for (int k = 0; k < m; ++k) dstar *= n[k];
+  bool dup = false;
+  if (dstar < 9.0e18) {
+    std::vector<uint64_t> key(N);
+    for (long long j = 0; j < N; ++j) {
+      uint64_t v = 0;
+      for (int k = 0; k < m; ++k) v = v * (uint64_t)n[k] + (uint64_t)idx[(long long)k * N + j];
+      key[j] = v;
+    }
+    std::sort(key.begin(), key.end());
+    for (long long j = 1; j < N && !dup; ++j) dup = key[j] == key[j - 1];
+  } else {
+    std::vector<int> ord(N);
+    std::iota(ord.begin(), ord.end(), 0);
+    auto less = [&](int a, int b) {
+      for (int k = 0; k < m; ++k) {
+        const int va = idx[(long long)k * N + a], vb = idx[(long long)k * N + b];
+        if (va != vb) return va < vb;
+      }
+      return false;
+    };
+    std::sort(ord.begin(), ord.end(), less);
+    for (long long j = 1; j < N && !dup; ++j) dup = !less(ord[j - 1], ord[j]) && !less(ord[j], ord[j - 1]);
+  }
+  if (dup) return fail(PRGD_EDUPLICATE, "Omega contains a repeated multi-index");
+  return PRGD_OK;
+}
+
+prgd_status enqueue_iterations(prgd_solver s, int iters) {
+  for (int it = 0; it < iters; ++it) {
+    HIPCHECK(launch_sampled(s->d, 0, s->sampled_blocks, s->stream));
+    HIPCHECK(launch_dense_iteration(s->d, s->stream, 0));
+    if (s->has_truth) HIPCHECK(launch_truth_sweep(s->d, s->stream, 0));
+  }
+  return PRGD_OK;
+}
+
+prgd_status read_state(prgd_solver s, State &st) {
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  HIPCHECK(hipMemcpy(&st, s->d.st, sizeof(State), hipMemcpyDeviceToHost));
+  return PRGD_OK;
+}
+
+void fill_report(prgd_solver s, const State &st, prgd_report *rep) {
+  if (!rep) return;
+  rep->iterations = st.iter;
+  rep->rel_residual = st.rel_res;
+  rep->rel_change = st.iter > 0 ? st.rel_change : NAN;
+  rep->rel_error = s->has_truth ? st.rel_error : NAN;
+  rep->seconds = s->last_seconds;
+  if (st.status < 0) rep->status = st.status;
+  else if (st.done) rep->status = st.status;
+  else rep->status = PRGD_NOT_CONVERGED;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t prgd_cores_numel(int32_t m, const int32_t *n, const int32_t *r) {
+  int64_t t = 0;
+  return checked_numel(m, n, r, t) ? t : -1;
+}
+
+const char *prgd_last_error(void) { return g_err.c_str(); }
+
+const char *prgd_status_str(prgd_status st) {
+  switch (st) {
+    case PRGD_OK: return "ok";
+    case PRGD_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case PRGD_PENDING: return "pending";
+    case PRGD_EINVAL: return "invalid argument";
+    case PRGD_EDUPLICATE: return "duplicate multi-index in Omega";
+    case PRGD_ENOMEM: return "out of memory";
+    case PRGD_EDEVICE: return "HIP device error";
+    case PRGD_EBREAKDOWN: return "numerical breakdown";
+    case PRGD_ESTATE: return "invalid solver state";
+    case PRGD_ENOTSUP: return "not supported by this build";
+    default: return "unknown status";
+  }
+}
+
+prgd_status prgd_create(const prgd_desc *ds, prgd_solver *out) {
+  if (!ds || !out) return fail(PRGD_EINVAL, "null descriptor or output handle");
+  *out = nullptr;
+  if (!ds->indices || !ds->values) return fail(PRGD_EINVAL, "indices and values are required");
+  if (ds->order < 2 || ds->order > MAXM) return fail(ds->order < 2 ? PRGD_EINVAL : PRGD_ENOTSUP, "order must be in [2, 32]");
+  if (ds->n_obs < 1 || ds->n_obs >= (1LL << 31)) return fail(PRGD_EINVAL, "n_obs must be in [1, 2^31)");
+  const int m = ds->order;
+  const long long N = ds->n_obs;
+  const size_t vbytes = ds->values_fp64 ? sizeof(double) : sizeof(float);
+
+  // host copies for validation (device inputs are brought over once)
+  std::vector<int32_t> hidx;
+  std::vector<unsigned char> hval;
+  const int32_t *idx_h = ds->indices;
+  const void *val_h = ds->values;
+  if (ds->mem_device) {
+    hidx.resize((size_t)m * N);
+    hval.resize((size_t)N * vbytes);
+    HIPCHECK(hipMemcpy(hidx.data(), ds->indices, hidx.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(hval.data(), ds->values, hval.size(), hipMemcpyDeviceToHost));
+    idx_h = hidx.data();
+    val_h = hval.data();
+  }
+  int64_t numel = 0;
+  prgd_status vs = validate_host(ds, idx_h, val_h, numel);
+  if (vs != PRGD_OK) return vs;
+
+  prgd_solver s = new (std::nothrow) prgd_solver_s();
+  if (!s) return fail(PRGD_ENOMEM, "host allocation failed");
+  auto cleanup = [&](prgd_status st) {
+    delete s;
+    return st;
+  };
+  HIPCHECK(hipGetDevice(&s->device));
+  if (ds->stream) {
+    s->stream = (hipStream_t)ds->stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(fail(PRGD_EDEVICE, "hipStreamCreate failed"));
+    s->own_stream = true;
+  }
+  s->m = m;
+  s->N = N;
+  s->numel = numel;
+  s->n.assign(ds->mode_sizes, ds->mode_sizes + m);
+  s->r.assign(ds->tt_ranks, ds->tt_ranks + m + 1);
+  int rmax = 1;
+  for (int k = 0; k <= m; ++k) rmax = std::max(rmax, s->r[k]);
+  s->R = padded_dim(rmax);
+  const int R = s->R;
+  s->coff.assign(m + 1, 0);
+  for (int k = 0; k < m; ++k) s->coff[k + 1] = s->coff[k] + (long long)s->n[k] * R * R;
+  const long long pn = s->coff[m];
+
+  Dev &d = s->d;
+  d.m = m;
+  d.R = R;
+  d.prec = ds->precision;
+  d.step_policy = ds->step_policy;
+  d.stop_rule = ds->stop_rule;
+  d.max_iter = ds->max_iter;
+  d.N = N;
+  d.step = ds->step;
+  d.eps_fixed = ds->eps_fixed;
+  d.tol = ds->tol;
+  double dstar = 1.0;
+  for (int k = 0; k < m; ++k) dstar *= (double)s->n[k];
+  d.p = (double)N / dstar;
+  int sm = ds->sort_mode;
+  if (sm < 0) {
+    sm = 0;
+    for (int k = 1; k < m; ++k)
+      if ((long long)s->r[k] * s->r[k + 1] > (long long)s->r[sm] * s->r[sm + 1]) sm = k;
+  }
+  d.sort_mode = sm;
+  int soff = 0;
+  int blk = 0;
+  for (int k = 0; k < m; ++k) {
+    d.n[k] = s->n[k];
+    d.coff[k] = s->coff[k];
+    d.soff[k] = soff;
+    soff += s->n[k];
+    int spb = (s->n[k] + 255) / 256;
+    if (spb < 4) spb = std::min(4, s->n[k]);
+    d.spb[k] = spb;
+    d.blk_off[k] = blk;
+    blk += (s->n[k] + spb - 1) / spb;
+  }
+  d.coff[m] = s->coff[m];
+  d.soff[m] = soff;
+  d.blk_off[m] = blk;
+  for (int k = 0; k <= m; ++k) d.r[k] = s->r[k];
+  if (sampled_block_size(m, R, d.prec) == 0)
+    return cleanup(fail(PRGD_ENOTSUP, "order x rank too large for the sampled-pass interface stack"));
+
+  const bool mixed = d.prec == PREC_MIXED;
+  // allocations
+  int *idx_raw = nullptr, *idx_sorted = nullptr;
+  void *val_raw = nullptr;
+  double *y64 = nullptr;
+  float *y32 = nullptr;
+  auto A = [&](hipError_t e) { return e == hipSuccess; };
+  bool ok = A(s->alloc(&idx_sorted, (long long)m * N)) && A(s->alloc(&d.cores, pn)) && A(s->alloc(&d.X, pn)) &&
+            A(s->alloc(&d.omega, soff)) && A(s->alloc(&d.sm, (long long)(m + 1) * SM_SLOTS * SLOT)) &&
+            A(s->alloc(&d.part, 1 << 20)) && A(s->alloc(&d.st, 1));
+  d.hist_cap = ds->max_iter + 1;
+  ok = ok && A(s->alloc(&d.hist, d.hist_cap));
+  if (mixed) {
+    ok = ok && A(s->alloc(&y32, N)) && A(s->alloc(&d.cores32, pn)) && A(s->alloc((float **)&d.Y, pn)) &&
+         A(s->alloc((float **)&d.s, soff));
+  } else {
+    ok = ok && A(s->alloc(&y64, N)) && A(s->alloc((double **)&d.Y, pn)) && A(s->alloc((double **)&d.s, soff));
+  }
+  if (!ok) return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+  d.y64 = y64;
+  d.y32 = y32;
+  d.idx = idx_sorted;
+
+  // observation set: to device, then grouped by the sort mode
+  const int32_t *idx_dev = ds->indices;
+  const void *val_dev = ds->values;
+  if (!ds->mem_device) {
+    if (!A(s->alloc(&idx_raw, (long long)m * N)) || !A(s->alloc((unsigned char **)&val_raw, (long long)N * vbytes)))
+      return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+    hipError_t e1 = hipMemcpyAsync(idx_raw, ds->indices, (size_t)m * N * sizeof(int32_t), hipMemcpyHostToDevice, s->stream);
+    hipError_t e2 = hipMemcpyAsync(val_raw, ds->values, (size_t)N * vbytes, hipMemcpyHostToDevice, s->stream);
+    if (e1 != hipSuccess || e2 != hipSuccess) return cleanup(fail(PRGD_EDEVICE, "copy of Omega failed"));
+    idx_dev = idx_raw;
+    val_dev = val_raw;
+  }
+  {
+    hipError_t e = group_by_mode(m, N, sm, s->n[sm], idx_dev, val_dev, ds->values_fp64, idx_sorted, y64, y32, s->stream);
+    if (e != hipSuccess) return cleanup(fail(PRGD_EDEVICE, std::string("grouping Omega: ") + hipGetErrorString(e)));
+  }
+
+  // cores
+  std::vector<double> packed;
+  pack_cores(m, s->n.data(), s->r.data(), R, ds->init_cores, packed, s->coff);
+  if (hipMemcpyAsync(d.cores, packed.data(), pn * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+    return cleanup(fail(PRGD_EDEVICE, "copy of cores failed"));
+  std::vector<double> tpacked;
+  if (ds->truth_cores) {
+    double *tr = nullptr;
+    if (!A(s->alloc(&tr, pn))) return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+    pack_cores(m, s->n.data(), s->r.data(), R, ds->truth_cores, tpacked, s->coff);
+    if (hipMemcpyAsync(tr, tpacked.data(), pn * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+      return cleanup(fail(PRGD_EDEVICE, "copy of truth failed"));
+    d.truth = tr;
+    d.has_truth = 1;
+    s->has_truth = true;
+  }
+  // state and constant small matrices
+  State st0{};
+  double ysq = 0.0;
+  for (long long j = 0; j < N; ++j) {
+    const double v = ds->values_fp64 ? ((const double *)val_h)[j] : (double)((const float *)val_h)[j];
+    ysq += v * v;
+  }
+  st0.y_sq = ysq;
+  st0.alpha_n = 0.0;
+  st0.rel_change = NAN;
+  st0.rel_error = NAN;
+  st0.rel_res = NAN;
+  std::vector<double> smh((size_t)(m + 1) * SM_SLOTS * SLOT, 0.0);
+  auto slot = [&](int b, int sl) { return smh.data() + ((size_t)b * SM_SLOTS + sl) * SLOT; };
+  for (int i = 0; i < R; ++i) {
+    slot(0, S_GL)[i * R + i] = 1.0;
+    slot(0, S_GLI)[i * R + i] = 1.0;
+    slot(m, S_H)[i * R + i] = 1.0;
+    slot(m, S_HI)[i * R + i] = 1.0;
+  }
+  if (hipMemcpyAsync(d.st, &st0, sizeof(State), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+      hipMemcpyAsync(d.sm, smh.data(), smh.size() * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+    return cleanup(fail(PRGD_EDEVICE, "state upload failed"));
+  if (fill_f64(d.X, pn, 0.0, s->stream) != hipSuccess || fill_f64(d.omega, soff, 1.0, s->stream) != hipSuccess)
+    return cleanup(fail(PRGD_EDEVICE, "fill failed"));
+  if (mixed) {
+    if (fill_f32((float *)d.Y, pn, 0.0f, s->stream) != hipSuccess || fill_f32((float *)d.s, soff, 0.0f, s->stream) != hipSuccess)
+      return cleanup(fail(PRGD_EDEVICE, "fill failed"));
+  } else {
+    if (fill_f64((double *)d.Y, pn, 0.0, s->stream) != hipSuccess || fill_f64((double *)d.s, soff, 0.0, s->stream) != hipSuccess)
+      return cleanup(fail(PRGD_EDEVICE, "fill failed"));
+  }
+  // sampled-pass grid: enough waves to fill 256 CUs
+  {
+    const int B = sampled_block_size(m, R, d.prec);
+    long long nb = (N + B - 1) / B;
+    nb = std::min<long long>(nb, 2048);
+    s->sampled_blocks = (int)std::max<long long>(nb, 1);
+  }
+  // left-orthogonalise T_0 (TT-SVD to its own ranks with a zero direction) and
+  // measure ||T_0||, ||T*||
+  if (launch_dense_iteration(d, s->stream, 1) != hipSuccess) return cleanup(fail(PRGD_EDEVICE, "init launch failed"));
+  if (s->has_truth && launch_truth_sweep(d, s->stream, 1) != hipSuccess)
+    return cleanup(fail(PRGD_EDEVICE, "truth norm launch failed"));
+  if (mixed && convert_f64_f32(d.cores, d.cores32, pn, s->stream) != hipSuccess)
+    return cleanup(fail(PRGD_EDEVICE, "convert failed"));
+  State st;
+  if (read_state(s, st) != PRGD_OK) return cleanup(PRGD_EDEVICE);
+  if (st.status < 0) return cleanup(fail(PRGD_EBREAKDOWN, "left-orthogonalisation of init_cores broke down"));
+  if (idx_raw) {   // free the unsorted copies
+    hipStreamSynchronize(s->stream);
+  }
+  *out = s;
+  return PRGD_OK;
+}
+
+prgd_status prgd_iterate(prgd_solver s, int32_t iters) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  if (iters < 0) return fail(PRGD_EINVAL, "iters < 0");
+  return enqueue_iterations(s, iters);
+}
+
+prgd_status prgd_sync(prgd_solver s) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  return PRGD_OK;
+}
+
+prgd_status prgd_run(prgd_solver s, prgd_report *rep) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  State st;
+  prgd_status e = read_state(s, st);
+  if (e != PRGD_OK) return e;
+  const auto t0 = std::chrono::steady_clock::now();
+  int chunk = 1;
+  while (!st.done) {
+    e = enqueue_iterations(s, chunk);
+    if (e != PRGD_OK) return e;
+    e = read_state(s, st);
+    if (e != PRGD_OK) return e;
+    chunk = std::min(chunk * 2, 32);
+  }
+  s->last_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  fill_report(s, st, rep);
+  if (st.status < 0) return fail((prgd_status)st.status, "iteration broke down (non-SPD Gram, non-finite residual or rank-deficient truncation)");
+  return st.status == 0 ? PRGD_OK : PRGD_NOT_CONVERGED;
+}
+
+prgd_status prgd_get_report(prgd_solver s, prgd_report *rep) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  State st;
+  prgd_status e = read_state(s, st);
+  if (e != PRGD_OK) return e;
+  fill_report(s, st, rep);
+  return PRGD_OK;
+}
+
+prgd_status prgd_get_cores(prgd_solver s, double *out, int64_t cap) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  if (!out || cap < s->numel) return fail(PRGD_EINVAL, "output buffer too small");
+  std::vector<double> padded(s->coff[s->m]);
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  HIPCHECK(hipMemcpy(padded.data(), s->d.cores, padded.size() * sizeof(double), hipMemcpyDeviceToHost));
+  unpack_cores(s->m, s->n.data(), s->r.data(), s->R, padded.data(), out, s->coff);
+  return PRGD_OK;
+}
+
+prgd_status prgd_get_history(prgd_solver s, prgd_iter_info *out, int32_t cap, int32_t *count) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  State st;
+  prgd_status e = read_state(s, st);
+  if (e != PRGD_OK) return e;
+  int nrec = st.iter + ((st.done && st.iter < s->d.hist_cap && st.status >= 0) ? 1 : 0);
+  nrec = std::min(nrec, s->d.hist_cap);
+  std::vector<IterRecord> h(std::max(nrec, 1));
+  if (nrec > 0) HIPCHECK(hipMemcpy(h.data(), s->d.hist, nrec * sizeof(IterRecord), hipMemcpyDeviceToHost));
+  const int w = std::min(nrec, cap);
+  for (int i = 0; i < w; ++i) {
+    out[i].iter = h[i].iter;
+    out[i].flags = h[i].flags;
+    out[i].rel_residual = h[i].rel_residual;
+    out[i].rel_change = h[i].rel_change;
+    out[i].rel_error = h[i].rel_error;
+    out[i].eps = h[i].eps;
+    out[i].alpha = h[i].alpha;
+  }
+  if (count) *count = w;
+  return PRGD_OK;
+}
+
+prgd_status prgd_sampled_pass(prgd_solver s, double *grad, double *slice_sq, double *res_sq) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  Dev &d = s->d;
+  const long long pn = s->coff[s->m];
+  const int soff = d.soff[s->m];
+  const bool mixed = d.prec == PREC_MIXED;
+  if (mixed) {
+    HIPCHECK(fill_f32((float *)d.Y, pn, 0.0f, s->stream));
+    HIPCHECK(fill_f32((float *)d.s, soff, 0.0f, s->stream));
+  } else {
+    HIPCHECK(fill_f64((double *)d.Y, pn, 0.0, s->stream));
+    HIPCHECK(fill_f64((double *)d.s, soff, 0.0, s->stream));
+  }
+  HIPCHECK(launch_sampled(d, 1, s->sampled_blocks, s->stream));
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  std::vector<double> gp(pn), sv(soff);
+  if (mixed) {
+    std::vector<float> gf(pn), sf(soff);
+    HIPCHECK(hipMemcpy(gf.data(), d.Y, pn * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(sf.data(), d.s, soff * sizeof(float), hipMemcpyDeviceToHost));
+    for (long long i = 0; i < pn; ++i) gp[i] = gf[i];
+    for (int i = 0; i < soff; ++i) sv[i] = sf[i];
+  } else {
+    HIPCHECK(hipMemcpy(gp.data(), d.Y, pn * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(sv.data(), d.s, soff * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  State st;
+  HIPCHECK(hipMemcpy(&st, d.st, sizeof(State), hipMemcpyDeviceToHost));
+  if (grad) unpack_cores(s->m, s->n.data(), s->r.data(), s->R, gp.data(), grad, s->coff);
+  if (slice_sq) std::copy(sv.begin(), sv.end(), slice_sq);
+  if (res_sq) *res_sq = st.res_sq;
+  // leave the accumulators clear for the iteration
+  if (mixed) {
+    HIPCHECK(fill_f32((float *)d.Y, pn, 0.0f, s->stream));
+    HIPCHECK(fill_f32((float *)d.s, soff, 0.0f, s->stream));
+  } else {
+    HIPCHECK(fill_f64((double *)d.Y, pn, 0.0, s->stream));
+    HIPCHECK(fill_f64((double *)d.s, soff, 0.0, s->stream));
+  }
+  HIPCHECK(hipStreamSynchronize(s->stream));
+  return PRGD_OK;
+}
+
+prgd_status prgd_eval(int32_t m, const int32_t *n, const int32_t *r, const double *cores, int64_t n_obs,
+                      const int32_t *indices, double *out, int32_t mem_device, void *stream) {
+  int64_t numel = 0;
+  if (!checked_numel(m, n, r, numel)) return fail(PRGD_EINVAL, "invalid shape or ranks");
+  if (!cores || !indices || !out || n_obs < 0) return fail(PRGD_EINVAL, "null argument");
+  int rmax = 1;
+  for (int k = 0; k <= m; ++k) rmax = std::max(rmax, (int)r[k]);
+  const int R = padded_dim(rmax);
+  if (R < 0) return fail(PRGD_ENOTSUP, "TT ranks above 16 are not supported by this build");
+  if (n_obs == 0) return PRGD_OK;
+  if (!mem_device)
+    for (int k = 0; k < m; ++k)
+      for (int64_t j = 0; j < n_obs; ++j)
+        if (indices[k * n_obs + j] < 0 || indices[k * n_obs + j] >= n[k]) return fail(PRGD_EINVAL, "index out of range");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<long long> coff(m + 1, 0);
+  for (int k = 0; k < m; ++k) coff[k + 1] = coff[k] + (long long)n[k] * R * R;
+  std::vector<double> packed;
+  pack_cores(m, n, r, R, cores, packed, coff);
+  double *dc = nullptr, *dout = nullptr;
+  long long *dcoff = nullptr;
+  int *didx = nullptr;
+  HIPCHECK(hipMalloc(&dc, packed.size() * sizeof(double)));
+  HIPCHECK(hipMalloc(&dcoff, coff.size() * sizeof(long long)));
+  HIPCHECK(hipMemcpy(dc, packed.data(), packed.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(dcoff, coff.data(), coff.size() * sizeof(long long), hipMemcpyHostToDevice));
+  const int *ip = indices;
+  double *op = out;
+  if (!mem_device) {
+    HIPCHECK(hipMalloc(&didx, (size_t)m * n_obs * sizeof(int)));
+    HIPCHECK(hipMalloc(&dout, (size_t)n_obs * sizeof(double)));
+    HIPCHECK(hipMemcpy(didx, indices, (size_t)m * n_obs * sizeof(int), hipMemcpyHostToDevice));
+    ip = didx;
+    op = dout;
+  }
+  HIPCHECK(launch_eval(m, R, n_obs, ip, dc, dcoff, op, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  if (!mem_device) HIPCHECK(hipMemcpy(out, dout, (size_t)n_obs * sizeof(double), hipMemcpyDeviceToHost));
+  hipFree(dc);
+  hipFree(dcoff);
+  if (didx) hipFree(didx);
+  if (dout) hipFree(dout);
+  return PRGD_OK;
+}
+
+prgd_status prgd_destroy(prgd_solver s) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  delete s;
+  return PRGD_OK;
+}
+
+}  // extern "C"

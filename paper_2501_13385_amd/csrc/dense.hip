@@ -1,0 +1,979 @@
+// Dense stage of one PRGD iteration on the device, float64.
+//
+// Notation: cores T_c, c = 0..m-1 (0-based), bond b = 0..m between cores b-1
+// and b, r_b the TT rank of bond b, omega_c(x) = (1 + s_c(x)/eps)^{1/(2m)} the
+// metric factor of slice x of core c (the diagonal of G_{l,c}^{1/(2m)} divided
+// by eps^{1/2m}; section 3.2.1 and Proposition 1), Y_c the Euclidean core
+// gradient from the sampled pass.
+//
+// Preconditioned projection (Lemma 3).  With the weighted left and right Grams
+//   GL_b = sum_x omega_{b-1}(x) T_{b-1}(x)^T GL_{b-1} T_{b-1}(x),   GL_0 = 1
+//   H_b  = sum_x omega_b(x)     T_b(x) H_{b+1} T_b(x)^T,            H_m  = 1
+// (Gram matrices of the left/right parts of W^{1/2} T), and
+//   Theta_c = sum_x T_c(x)^T Y_c(x),
+// the projected components of eq. "tsp in nm", moved back by W^{-1/2} and
+// expressed in the gauge of the stored cores T_c, are
+//   X_c(x) = omega_c(x)^{-1} GL_c^{-1} Y_c(x) H_{c+1}^{-1}
+//            - T_c(x) GL_{c+1}^{-1} Theta_c H_{c+1}^{-1}          (c < m-1)
+//   X_{m-1}(x) = omega_{m-1}(x)^{-1} GL_{m-1}^{-1} Y_{m-1}(x).
+// This is the closed form of Lemma 3 after substituting the left-orthogonal
+// decomposition of W^{1/2}T through its QR factors; every weight and gauge
+// factor acts per mode slice, which is why the single sampled pass suffices.
+// In units normalised by eps (weights 1 + s/eps), the direction scales by
+// eps^{1/2}, so the step alpha = c eps^{1/2}/p becomes c/p.
+//
+// Update (Algorithm 2): W_l = T_l - alpha xi is the rank-2r block TT with
+//   C_0 = [X'_0, T_0],  C_c = [[T_c, 0], [X'_c, T_c]],  C_{m-1} = [[T], [T + X']]
+// where X' = -alpha X.
+//
+// Retraction (Algorithm 1 on W_l, in TT form).  The truncated SVD at cut i
+// needs the left singular vectors of B_i W^{>=i}, B_i = P_{i-1} C_{i-1}.  With
+// the right Gram GR_i = W^{>=i} W^{>=i,T} = F_i F_i^T (pivoted Cholesky) these
+// are the left singular vectors of K = B_i F_i; from S = F^T (B^T B) F = Z
+// Sigma^2 Z^T the new core is T'_{i-1} = B_i Tr_i with Tr_i = F Z_r Sigma_r^{-1},
+// and P_i = T'^{<=i,T} W^{<=i} = Tr_i^T (B^T B).  The last core is
+// P_{m-1} C_{m-1}.
+#include "prgd_internal.hpp"
+#include "block_ops.hpp"
+
+namespace prgd {
+
+constexpr int SMEM = 6656;   // doubles of static LDS used by the dense kernels
+
+// thread groups: G groups of TPG threads, each group working on its own slice
+struct Grp {
+  int G, TPG, g, tl;
+};
+__device__ inline Grp make_grp(int ne) {
+  Grp q;
+  q.G = (int)blockDim.x / ne;
+  if (q.G < 1) q.G = 1;
+  if (q.G > 64) q.G = 64;
+  q.TPG = (int)blockDim.x / q.G;
+  q.g = (int)threadIdx.x / q.TPG;
+  q.tl = (int)threadIdx.x % q.TPG;
+  return q;
+}
+
+__device__ inline double load_grad(const Dev &d, long long i) {
+  return d.prec == PREC_MIXED ? (double)((const float *)d.Y)[i] : ((const double *)d.Y)[i];
+}
+__device__ inline void zero_grad(const Dev &d, long long i) {
+  if (d.prec == PREC_MIXED)
+    ((float *)d.Y)[i] = 0.0f;
+  else
+    ((double *)d.Y)[i] = 0.0;
+}
+
+// core index and slice range of this block for slice-parallel kernels over all cores
+__device__ inline void block_core(const Dev &d, int &c, int &x0, int &x1) {
+  const int b = blockIdx.x;
+  c = 0;
+  while (c + 1 < d.m && d.blk_off[c + 1] <= b) ++c;
+  const int lb = b - d.blk_off[c];
+  x0 = lb * d.spb[c];
+  x1 = x0 + d.spb[c];
+  if (x1 > d.n[c]) x1 = d.n[c];
+}
+
+// ---------------------------------------------------------------------------
+// small dense linear algebra on LDS (block-cooperative; callers sync around)
+// ---------------------------------------------------------------------------
+
+// inverse of the SPD leading n x n block of A (row-major, leading dim ld) via
+// Cholesky; writes Ainv (ld) with zeros outside the block.  Returns false if
+// a pivot is not positive.  scratch: 2*n*n doubles.
+__device__ bool spd_inverse(const double *A, int ld, int n, double *Ainv, int R, double *scratch) {
+  __shared__ int fail;
+  double *L = scratch, *Li = scratch + n * n;
+  if (threadIdx.x == 0) fail = 0;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e % n;
+    L[e] = (j <= i) ? A[i * ld + j] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      const double dk = L[k * n + k];
+      if (!(dk > 0.0) || !isfinite(dk)) fail = 1;
+      else L[k * n + k] = sqrt(dk);
+    }
+    __syncthreads();
+    if (fail) return false;
+    const double piv = L[k * n + k];
+    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) L[i * n + k] /= piv;
+    __syncthreads();
+    const int rem = n - k - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+      if (j <= i) L[i * n + j] -= L[i * n + k] * L[j * n + k];
+    }
+    __syncthreads();
+  }
+  // Li = L^{-1} (lower), one column per thread
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    for (int i = 0; i < n; ++i) {
+      double v = (i == j) ? 1.0 : 0.0;
+      if (i < j) {
+        Li[i * n + j] = 0.0;
+        continue;
+      }
+      for (int k = j; k < i; ++k) v -= L[i * n + k] * Li[k * n + j];
+      Li[i * n + j] = v / L[i * n + i];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
+    const int i = e / R, j = e % R;
+    double v = 0.0;
+    if (i < n && j < n)
+      for (int k = (i > j ? i : j); k < n; ++k) v += Li[k * n + i] * Li[k * n + j];
+    Ainv[i * R + j] = v;
+  }
+  __syncthreads();
+  return true;
+}
+
+// Pivoted Cholesky of a symmetric positive semidefinite n x n matrix A
+// (dense, leading dim n; destroyed): F (n x n, row-major) gets columns
+// 0..rank-1 with F F^T = A up to pivots below n * 2.3e-16 * max diag.
+__device__ int pivoted_cholesky(double *A, int n, double *F, int *used) {
+  __shared__ int piv, stop, rank;
+  __shared__ double pvs, tol;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) F[e] = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) used[i] = 0;
+  if (threadIdx.x == 0) {
+    double dm = 0.0;
+    for (int i = 0; i < n; ++i) dm = fmax(dm, A[i * n + i]);
+    tol = (double)n * 2.3e-16 * dm;
+    rank = 0;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      int p = -1;
+      double best = 0.0;
+      for (int i = 0; i < n; ++i)
+        if (!used[i] && A[i * n + i] > best) {
+          best = A[i * n + i];
+          p = i;
+        }
+      stop = (p < 0 || !(best > tol)) ? 1 : 0;
+      if (!stop) {
+        piv = p;
+        used[p] = 1;
+        pvs = sqrt(best);
+        rank = k + 1;
+      }
+    }
+    __syncthreads();
+    if (stop) break;
+    const int p = piv;
+    const double pv = pvs;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double f = (used[i] && i != p) ? 0.0 : A[i * n + p] / pv;
+      F[i * n + k] = f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e % n;
+      A[e] -= F[i * n + k] * F[j * n + k];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  return rank;
+}
+
+// Cyclic Jacobi for a symmetric n x n matrix A (dense, ld n, destroyed), n <= 32,
+// round-robin ordering (n/2 disjoint rotations per round).  On exit w[0..n) are
+// the eigenvalues in descending order and V (ld n) holds the eigenvectors as columns.
+__device__ void jacobi_eig(double *A, int n, double *V, double *w, double *Vs, double *cs) {
+  __shared__ double sbuf[16];
+  __shared__ int goon;
+  const int ne = n + (n & 1);
+  const int np = ne / 2;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const double v = A[e];
+      if (e / n == e % n) dia += v * v;
+      else off += v * v;
+    }
+    off = block_sum(off, sbuf);
+    dia = block_sum(dia, sbuf);
+    if (threadIdx.x == 0) goon = (off > 1e-32 * (dia + off)) ? 1 : 0;
+    __syncthreads();
+    if (!goon) break;
+    for (int rd = 0; rd < ne - 1; ++rd) {
+      for (int k = threadIdx.x; k < np; k += blockDim.x) {
+        int p, q;
+        if (k == 0) {
+          p = ne - 1;
+          q = rd;
+        } else {
+          p = (rd + k) % (ne - 1);
+          q = (rd - k + ne - 1) % (ne - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = A[p * n + q];
+          if (apq != 0.0) {
+            const double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        cs[4 * k + 0] = c;
+        cs[4 * k + 1] = s;
+        cs[4 * k + 2] = (double)p;
+        cs[4 * k + 3] = (double)q;
+      }
+      __syncthreads();
+      // A <- A J, V <- V J (columns p, q)
+      for (int e = threadIdx.x; e < n * np; e += blockDim.x) {
+        const int i = e / np, k = e % np;
+        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
+        if (q >= n) continue;
+        const double c = cs[4 * k], s = cs[4 * k + 1];
+        const double ap = A[i * n + p], aq = A[i * n + q];
+        A[i * n + p] = c * ap - s * aq;
+        A[i * n + q] = s * ap + c * aq;
+        const double vp = V[i * n + p], vq = V[i * n + q];
+        V[i * n + p] = c * vp - s * vq;
+        V[i * n + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+      // A <- J^T A (rows p, q)
+      for (int e = threadIdx.x; e < n * np; e += blockDim.x) {
+        const int k = e / n, j = e % n;
+        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
+        if (q >= n) continue;
+        const double c = cs[4 * k], s = cs[4 * k + 1];
+        const double ap = A[p * n + j], aq = A[q * n + j];
+        A[p * n + j] = c * ap - s * aq;
+        A[q * n + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+    }
+  }
+  // sort descending (stable by index)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double wi = A[i * n + i];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double wj = A[j * n + j];
+      if (wj > wi || (wj == wi && j < i)) ++rk;
+    }
+    w[rk] = wi;
+    for (int r = 0; r < n; ++r) Vs[r * n + rk] = V[r * n + i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[e] = Vs[e];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// weighted Gram sweeps (one launch per step j = 1..m-1)
+// ---------------------------------------------------------------------------
+// blocks [0, nbL): core j-1 -> GL_j and Theta_{j-1}
+// blocks [nbL, nbL+nbH): core m-j -> H_{m-j}
+__global__ void __launch_bounds__(256) k_gram(Dev d, int j, int nbL) {
+  if (d.st->done) return;
+  __shared__ double smem[SMEM];
+  const int R = d.R, RR = R * R, m = d.m;
+  const bool left = (int)blockIdx.x < nbL;
+  const int c = left ? j - 1 : m - j;
+  const int lb = left ? (int)blockIdx.x : (int)blockIdx.x - nbL;
+  const int nbk = left ? nbL : (int)gridDim.x - nbL;
+  const int per = (d.n[c] + nbk - 1) / nbk;
+  const int x0 = lb * per;
+  const int x1 = min(d.n[c], x0 + per);
+  const bool want_th = left && c < m - 1;
+
+  double *Gin = smem;                    // GL_{j-1} or H_{m-j+1}
+  const double *gsrc = left ? sm_slot(d, j - 1, S_GL) : sm_slot(d, m - j + 1, S_H);
+  for (int e = threadIdx.x; e < RR; e += blockDim.x) Gin[e] = gsrc[e];
+  const Grp q = make_grp(RR);
+  double *sT = smem + RR + q.g * 3 * RR;
+  double *sY = sT + RR;
+  double *tmp = sY + RR;
+  double acc = 0.0, acct = 0.0;
+  const int e = q.tl;                    // one output entry per thread (RR <= TPG)
+  const int ea = e / R, eb = e % R;
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    if (act) {
+      const long long off = d.coff[c] + (long long)x * RR;
+      for (int t = q.tl; t < RR; t += q.TPG) {
+        sT[t] = d.cores[off + t];
+        if (want_th) sY[t] = load_grad(d, off + t);
+      }
+    }
+    __syncthreads();
+    if (act && e < RR) {
+      if (left) {
+        double v = 0.0;   // tmp = GLprev * T
+        for (int k = 0; k < R; ++k) v += Gin[ea * R + k] * sT[k * R + eb];
+        tmp[e] = v;
+      } else {
+        double v = 0.0;   // tmp = T * Hnext
+        for (int k = 0; k < R; ++k) v += sT[ea * R + k] * Gin[k * R + eb];
+        tmp[e] = v;
+      }
+    }
+    __syncthreads();
+    if (act && e < RR) {
+      const double w = d.omega[d.soff[c] + x];
+      double v = 0.0;
+      if (left) {
+        for (int k = 0; k < R; ++k) v += sT[k * R + ea] * tmp[k * R + eb];
+        if (want_th) {
+          double t2 = 0.0;
+          for (int k = 0; k < R; ++k) t2 += sT[k * R + ea] * sY[k * R + eb];
+          acct += t2;
+        }
+      } else {
+        for (int k = 0; k < R; ++k) v += tmp[ea * R + k] * sT[eb * R + k];
+      }
+      acc += w * v;
+    }
+    __syncthreads();
+  }
+  // reduce the groups' accumulators in LDS, then publish the block partial
+  double *red = smem + RR;   // reuse: G * 2 * RR <= 3 * 256 * ... fits
+  __syncthreads();
+  if (q.g < q.G && e < RR) {
+    red[(q.g * 2 + 0) * RR + e] = acc;
+    red[(q.g * 2 + 1) * RR + e] = acct;
+  }
+  __syncthreads();
+  double *mypart = d.part + (long long)blockIdx.x * 2 * RR;
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int g = 0; g < q.G; ++g) {
+      a0 += red[(g * 2 + 0) * RR + t];
+      a1 += red[(g * 2 + 1) * RR + t];
+    }
+    mypart[t] = a0;
+    mypart[RR + t] = a1;
+  }
+  if (!arrive_last(&d.st->counter[C_GRAM])) return;
+
+  // last block: totals, inverses
+  double *GLj = sm_slot(d, j, S_GL), *THc = sm_slot(d, j - 1, S_TH), *Hb = sm_slot(d, m - j, S_H);
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    double gl = 0.0, th = 0.0, h = 0.0;
+    for (int b = 0; b < nbL; ++b) {
+      gl += d.part[(long long)b * 2 * RR + t];
+      th += d.part[(long long)b * 2 * RR + RR + t];
+    }
+    for (int b = nbL; b < (int)gridDim.x; ++b) h += d.part[(long long)b * 2 * RR + t];
+    GLj[t] = gl;
+    THc[t] = th;
+    Hb[t] = h;
+  }
+  __threadfence_block();
+  __syncthreads();
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  if (!spd_inverse(GLj, R, d.r[j], sm_slot(d, j, S_GLI), R, smem)) bad = 1;
+  __syncthreads();
+  if (!spd_inverse(Hb, R, d.r[m - j], sm_slot(d, m - j, S_HI), R, smem)) bad = 1;
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) {
+      d.st->status = -5;
+      d.st->done = 1;
+    }
+    return;
+  }
+  if (j == m - 1) {
+    // Psi_c = GL_{c+1}^{-1} Theta_c H_{c+1}^{-1}, c = 0..m-2
+    for (int cc = 0; cc < m - 1; ++cc) {
+      const double *gi = sm_slot(d, cc + 1, S_GLI), *th = sm_slot(d, cc, S_TH), *hi = sm_slot(d, cc + 1, S_HI);
+      double *t1 = smem;
+      for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+        const int a = t / R, b = t % R;
+        double v = 0.0;
+        for (int k = 0; k < R; ++k) v += gi[a * R + k] * th[k * R + b];
+        t1[t] = v;
+      }
+      __syncthreads();
+      double *psi = sm_slot(d, cc, S_PSI);
+      for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+        const int a = t / R, b = t % R;
+        double v = 0.0;
+        for (int k = 0; k < R; ++k) v += t1[a * R + k] * hi[k * R + b];
+        psi[t] = v;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// tangent components X_c(x) (all cores, slice-parallel); clears Y
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_tangent(Dev d) {
+  if (d.st->done) return;
+  __shared__ double smem[SMEM];
+  int c, x0, x1;
+  block_core(d, c, x0, x1);
+  const int R = d.R, RR = R * R, m = d.m;
+  double *GI = smem, *HI = smem + RR, *PS = smem + 2 * RR;
+  const double *gi = sm_slot(d, c, S_GLI), *hi = sm_slot(d, c + 1, S_HI), *ps = sm_slot(d, c, S_PSI);
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    GI[t] = gi[t];
+    HI[t] = hi[t];
+    PS[t] = (c < m - 1) ? ps[t] : 0.0;
+  }
+  const Grp q = make_grp(RR);
+  double *sT = smem + 3 * RR + q.g * 3 * RR;
+  double *sY = sT + RR, *tmp = sY + RR;
+  const int e = q.tl, ea = e / R, eb = e % R;
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    const long long off = d.coff[c] + (long long)x * RR;
+    if (act)
+      for (int t = q.tl; t < RR; t += q.TPG) {
+        sT[t] = d.cores[off + t];
+        sY[t] = load_grad(d, off + t);
+        zero_grad(d, off + t);
+      }
+    __syncthreads();
+    if (act && e < RR) {
+      double v = 0.0;
+      for (int k = 0; k < R; ++k) v += GI[ea * R + k] * sY[k * R + eb];
+      tmp[e] = v;
+    }
+    __syncthreads();
+    if (act && e < RR) {
+      const double iw = 1.0 / d.omega[d.soff[c] + x];
+      double v = 0.0;
+      for (int k = 0; k < R; ++k) v += tmp[ea * R + k] * HI[k * R + eb];
+      v *= iw;
+      double u = 0.0;
+      for (int k = 0; k < R; ++k) u += sT[ea * R + k] * PS[k * R + eb];
+      d.X[off + e] = v - u;
+    }
+    __syncthreads();
+  }
+}
+
+// block core C_c(x) of W_l = T_l - alpha xi as a 2R x 2R matrix in LDS
+__device__ inline void build_block(const Dev &d, int c, const double *sT, const double *sX, double alpha,
+                                   double *C, int tl, int tpg) {
+  const int R = d.R, R2 = 2 * R, m = d.m;
+  for (int t = tl; t < R2 * R2; t += tpg) {
+    const int i = t / R2, jj = t % R2;
+    double v = 0.0;
+    if (c == 0) {
+      if (i < R) v = (jj < R) ? -alpha * sX[i * R + jj] : sT[i * R + jj - R];
+    } else if (c == m - 1) {
+      if (jj < R) v = (i < R) ? sT[i * R + jj] : sT[(i - R) * R + jj] - alpha * sX[(i - R) * R + jj];
+    } else {
+      if (i < R) v = (jj < R) ? sT[i * R + jj] : 0.0;
+      else v = (jj < R) ? -alpha * sX[(i - R) * R + jj] : sT[(i - R) * R + jj - R];
+    }
+    C[t] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// right Grams of the block TT: GR_b = sum_x C_b(x) GR_{b+1} C_b(x)^T, b = m-1..1
+// last block: pivoted Cholesky factor F_b of GR_b on its active indices
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_rgram(Dev d, int b) {
+  if (d.st->done) return;
+  __shared__ double smem[SMEM];
+  const int R = d.R, R2 = 2 * R, NE = R2 * R2, m = d.m;
+  const int nb = gridDim.x;
+  const int per = (d.n[b] + nb - 1) / nb;
+  const int x0 = blockIdx.x * per, x1 = min(d.n[b], x0 + per);
+  const double alpha = d.st->alpha_n;
+  double *GN = smem;   // GR_{b+1}
+  const double *gn = sm_slot(d, b + 1, S_GR);
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) GN[t] = (b == m - 1) ? ((t / R2 == t % R2) ? 1.0 : 0.0) : gn[t];
+  const Grp q = make_grp(NE);
+  double *C = smem + NE + q.g * (2 * NE + 2 * R * R);
+  double *tmp = C + NE;
+  double *sT = tmp + NE, *sX = sT + R * R;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    const long long off = d.coff[b] + (long long)x * R * R;
+    if (act)
+      for (int t = q.tl; t < R * R; t += q.TPG) {
+        sT[t] = d.cores[off + t];
+        sX[t] = d.X[off + t];
+      }
+    __syncthreads();
+    if (act) build_block(d, b, sT, sX, alpha, C, q.tl, q.TPG);
+    __syncthreads();
+    if (act)
+      for (int t = q.tl; t < NE; t += q.TPG) {
+        const int i = t / R2, jj = t % R2;
+        double v = 0.0;
+        for (int k = 0; k < R2; ++k) v += C[i * R2 + k] * GN[k * R2 + jj];
+        tmp[t] = v;
+      }
+    __syncthreads();
+    if (act) {
+      int u = 0;
+      for (int t = q.tl; t < NE; t += q.TPG, ++u) {
+        const int i = t / R2, jj = t % R2;
+        double v = 0.0;
+        for (int k = 0; k < R2; ++k) v += tmp[i * R2 + k] * C[jj * R2 + k];
+        acc[u] += v;
+      }
+    }
+    __syncthreads();
+  }
+  double *red = smem + NE;
+  __syncthreads();
+  if (q.g < q.G) {
+    int u = 0;
+    for (int t = q.tl; t < NE; t += q.TPG, ++u) red[q.g * NE + t] = acc[u];
+  }
+  __syncthreads();
+  double *mypart = d.part + (long long)blockIdx.x * NE;
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+    double v = 0.0;
+    for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
+    mypart[t] = v;
+  }
+  if (!arrive_last(&d.st->counter[C_GR])) return;
+
+  double *GR = sm_slot(d, b, S_GR);
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+    double v = 0.0;
+    for (int k = 0; k < nb; ++k) v += d.part[(long long)k * NE + t];
+    GR[t] = v;
+  }
+  __syncthreads();
+  // compress to the active indices [0, r_b) U [R, R + r_b)
+  const int rb = d.r[b], na = 2 * rb;
+  double *A = smem, *Fc = smem + 1024;
+  int *used = (int *)(smem + 2048);
+  for (int t = threadIdx.x; t < na * na; t += blockDim.x) {
+    const int i = t / na, jj = t % na;
+    const int gi = i < rb ? i : R + i - rb, gj = jj < rb ? jj : R + jj - rb;
+    A[t] = GR[gi * R2 + gj];
+  }
+  __syncthreads();
+  const int rank = pivoted_cholesky(A, na, Fc, used);
+  double *F = sm_slot(d, b, S_F);
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+    const int gi = t / R2, col = t % R2;
+    int i = -1;
+    if (gi < rb) i = gi;
+    else if (gi >= R && gi < R + rb) i = gi - R + rb;
+    F[t] = (i >= 0 && col < rank) ? Fc[i * na + col] : 0.0;
+  }
+  if (threadIdx.x == 0) d.st->rank_f[b] = rank;
+}
+
+// ---------------------------------------------------------------------------
+// left sweep of the retraction, cut i = 1..m-1 (core c = i-1)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_left(Dev d, int i) {
+  if (d.st->done) return;
+  __shared__ double smem[SMEM];
+  const int R = d.R, R2 = 2 * R, NE = R2 * R2, m = d.m, c = i - 1;
+  const int nb = gridDim.x;
+  const int per = (d.n[c] + nb - 1) / nb;
+  const int x0 = blockIdx.x * per, x1 = min(d.n[c], x0 + per);
+  const double alpha = d.st->alpha_n;
+  double *P = smem;    // R x 2R
+  const double *ps = sm_slot(d, c, S_P);
+  for (int t = threadIdx.x; t < R * R2; t += blockDim.x) P[t] = (c == 0) ? (t == 0 ? 1.0 : 0.0) : ps[t];
+  const Grp q = make_grp(NE);
+  double *C = smem + R * R2 + q.g * (NE + R * R2 + 2 * R * R);
+  double *B = C + NE;
+  double *sT = B + R * R2, *sX = sT + R * R;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    const long long off = d.coff[c] + (long long)x * R * R;
+    if (act)
+      for (int t = q.tl; t < R * R; t += q.TPG) {
+        sT[t] = d.cores[off + t];
+        sX[t] = d.X[off + t];
+      }
+    __syncthreads();
+    if (act) build_block(d, c, sT, sX, alpha, C, q.tl, q.TPG);
+    __syncthreads();
+    if (act)
+      for (int t = q.tl; t < R * R2; t += q.TPG) {
+        const int a = t / R2, jj = t % R2;
+        double v = 0.0;
+        for (int k = 0; k < R2; ++k) v += P[a * R2 + k] * C[k * R2 + jj];
+        B[t] = v;
+      }
+    __syncthreads();
+    if (act) {
+      int u = 0;
+      for (int t = q.tl; t < NE; t += q.TPG, ++u) {
+        const int a = t / R2, bb = t % R2;
+        double v = 0.0;
+        for (int k = 0; k < R; ++k) v += B[k * R2 + a] * B[k * R2 + bb];
+        acc[u] += v;
+      }
+    }
+    __syncthreads();
+  }
+  double *red = smem + R * R2;
+  __syncthreads();
+  if (q.g < q.G) {
+    int u = 0;
+    for (int t = q.tl; t < NE; t += q.TPG, ++u) red[q.g * NE + t] = acc[u];
+  }
+  __syncthreads();
+  double *mypart = d.part + (long long)blockIdx.x * NE;
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+    double v = 0.0;
+    for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
+    mypart[t] = v;
+  }
+  if (!arrive_last(&d.st->counter[C_LEFT])) return;
+
+  // last block: S = F^T GB F, eigen-decomposition, truncation to r_i
+  double *GB = smem;                 // NE
+  double *F = smem + 1024;           // 2R x rank (ld R2)
+  double *T1 = smem + 2048;          // GB F (2R x rank)
+  double *S = smem + 3072;           // rank x rank
+  double *V = smem + 4096;           // rank x rank
+  double *Vs = smem + 5120;          // rank x rank (sort scratch)
+  double *w = smem + 6144;           // 32
+  double *cs = smem + 6176;          // 64
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+    double v = 0.0;
+    for (int k = 0; k < nb; ++k) v += d.part[(long long)k * NE + t];
+    GB[t] = v;
+  }
+  const double *fs = sm_slot(d, i, S_F);
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) F[t] = fs[t];
+  __syncthreads();
+  const int rk = d.st->rank_f[i];
+  const int ri = d.r[i];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = (rk < ri) ? 1 : 0;
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) {
+      d.st->status = -5;
+      d.st->done = 1;
+    }
+    return;
+  }
+  for (int t = threadIdx.x; t < R2 * rk; t += blockDim.x) {
+    const int a = t / rk, bcol = t % rk;
+    double v = 0.0;
+    for (int k = 0; k < R2; ++k) v += GB[a * R2 + k] * F[k * R2 + bcol];
+    T1[a * rk + bcol] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < rk * rk; t += blockDim.x) {
+    const int a = t / rk, bcol = t % rk;
+    double v = 0.0;
+    for (int k = 0; k < R2; ++k) v += F[k * R2 + a] * T1[k * rk + bcol];
+    S[t] = v;
+  }
+  __syncthreads();
+  // symmetrise (rounding) before Jacobi
+  for (int t = threadIdx.x; t < rk * rk; t += blockDim.x) {
+    const int a = t / rk, bcol = t % rk;
+    if (a < bcol) {
+      const double v = 0.5 * (S[a * rk + bcol] + S[bcol * rk + a]);
+      S[a * rk + bcol] = v;
+      S[bcol * rk + a] = v;
+    }
+  }
+  __syncthreads();
+  jacobi_eig(S, rk, V, w, Vs, cs);
+  if (threadIdx.x == 0) {
+    const double s0 = w[0];
+    if (!(w[ri - 1] > 1e-28 * s0) || !isfinite(s0)) bad = 1;
+  }
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) {
+      d.st->status = -5;
+      d.st->done = 1;
+    }
+    return;
+  }
+  // Tr = F Z_r Sigma_r^{-1}  (2R x R; columns >= r_i zero)
+  double *Tr = sm_slot(d, i, S_TR);
+  double *TrL = smem + 3072;  // reuse S area: 2R x R
+  for (int t = threadIdx.x; t < R2 * R; t += blockDim.x) {
+    const int a = t / R, col = t % R;
+    double v = 0.0;
+    if (col < ri) {
+      for (int k = 0; k < rk; ++k) v += F[a * R2 + k] * V[k * rk + col];
+      v /= sqrt(w[col]);
+    }
+    TrL[t] = v;
+    Tr[t] = v;
+  }
+  __syncthreads();
+  // P_i = Tr^T GB  (R x 2R)
+  double *Pn = sm_slot(d, i, S_P);
+  for (int t = threadIdx.x; t < R * R2; t += blockDim.x) {
+    const int a = t / R2, bcol = t % R2;
+    double v = 0.0;
+    for (int k = 0; k < R2; ++k) v += TrL[k * R + a] * GB[k * R2 + bcol];
+    Pn[t] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// output: new cores T'_c(x) = P_c C_c(x) Tr_{c+1} (c < m-1), P_{m-1} C_{m-1}(x);
+// stop-test reductions ||T'||^2 = ||T'_{m-1}||^2 and <T', T>
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_output(Dev d, int init) {
+  if (d.st->done) return;
+  __shared__ double smem[SMEM];
+  int c, x0, x1;
+  block_core(d, c, x0, x1);
+  const int R = d.R, R2 = 2 * R, m = d.m, RR = R * R;
+  const double alpha = d.st->alpha_n;
+  double *P = smem;                  // R x 2R
+  double *Tr = smem + R * R2;        // 2R x R
+  double *Zc = Tr + R2 * R;          // R x R (second block of P_{m-1})
+  const double *ps = sm_slot(d, c, S_P);
+  const double *trs = sm_slot(d, c + 1, S_TR);
+  for (int t = threadIdx.x; t < R * R2; t += blockDim.x) {
+    P[t] = (c == 0) ? (t == 0 ? 1.0 : 0.0) : ps[t];
+    if (c < m - 1) Tr[t] = trs[t];
+  }
+  for (int t = threadIdx.x; t < RR; t += blockDim.x)
+    Zc[t] = (c == m - 1) ? sm_slot(d, m - 1, S_P)[(t / R) * R2 + R + t % R] : 0.0;
+  const Grp q = make_grp(R * R2);
+  double *C = Zc + RR + q.g * (R2 * R2 + R * R2 + 3 * RR);
+  double *PC = C + R2 * R2;
+  double *sT = PC + R * R2, *sX = sT + RR, *out = sX + RR;
+  double nn = 0.0, cr = 0.0;
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    const long long off = d.coff[c] + (long long)x * RR;
+    if (act)
+      for (int t = q.tl; t < RR; t += q.TPG) {
+        sT[t] = d.cores[off + t];
+        sX[t] = d.X[off + t];
+      }
+    __syncthreads();
+    if (act) build_block(d, c, sT, sX, alpha, C, q.tl, q.TPG);
+    __syncthreads();
+    if (act)
+      for (int t = q.tl; t < R * R2; t += q.TPG) {
+        const int a = t / R2, jj = t % R2;
+        double v = 0.0;
+        for (int k = 0; k < R2; ++k) v += P[a * R2 + k] * C[k * R2 + jj];
+        PC[t] = v;
+      }
+    __syncthreads();
+    if (act)
+      for (int t = q.tl; t < RR; t += q.TPG) {
+        const int a = t / R, bcol = t % R;
+        double v = 0.0;
+        if (c < m - 1) {
+          for (int k = 0; k < R2; ++k) v += PC[a * R2 + k] * Tr[k * R + bcol];
+        } else {
+          v = PC[a * R2 + bcol];
+        }
+        out[t] = v;
+      }
+    __syncthreads();
+    if (act) {
+      for (int t = q.tl; t < RR; t += q.TPG) {
+        d.cores[off + t] = out[t];
+        if (d.prec == PREC_MIXED) d.cores32[off + t] = (float)out[t];
+      }
+      if (c == m - 1)
+        for (int a = q.tl; a < R; a += q.TPG) {
+          const double v = out[a * R];
+          nn += v * v;
+          double z = 0.0;
+          for (int k = 0; k < R; ++k) z += Zc[a * R + k] * sT[k * R];
+          cr += v * z;
+        }
+    }
+    __syncthreads();
+  }
+  __shared__ double sbuf[16];
+  nn = block_sum(nn, sbuf);
+  cr = block_sum(cr, sbuf);
+  if (threadIdx.x == 0) {
+    d.part[2 * blockIdx.x] = nn;
+    d.part[2 * blockIdx.x + 1] = cr;
+  }
+  if (!arrive_last(&d.st->counter[C_OUT])) return;
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) {
+    a0 += d.part[2 * k];
+    a1 += d.part[2 * k + 1];
+  }
+  a0 = block_sum(a0, sbuf);
+  a1 = block_sum(a1, sbuf);
+  if (threadIdx.x == 0) {
+    State *st = d.st;
+    if (init) {
+      st->tnorm_sq = a0;
+    } else {
+      const double old = st->tnorm_sq;
+      const double diff = fmax(0.0, a0 - 2.0 * a1 + old);
+      const double rc = sqrt(diff) / fmax(1.0, sqrt(old));
+      st->rel_change = rc;
+      st->tnorm_sq = a0;
+      const int it = st->iter;
+      if (it < d.hist_cap) {
+        d.hist[it].rel_change = rc;
+        d.hist[it].flags |= 1;
+      }
+      st->iter = it + 1;
+      st->upd = 1;
+      if (d.stop_rule == STOP_CHANGE && rc <= d.tol) {
+        st->status = 0;
+        st->done = 1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cross Gram sweep with the truth: Z_{c+1} = sum_x A_c(x)^T Z_c B_c(x)
+// mode 0: A = iterate, B = truth (relative error); mode 1: A = B = truth (||T*||^2)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_cross(Dev d, int c, int mode) {
+  if (mode == 0 && !d.st->upd) return;
+  __shared__ double smem[SMEM];
+  const int R = d.R, RR = R * R, m = d.m;
+  const int nb = gridDim.x;
+  const int per = (d.n[c] + nb - 1) / nb;
+  const int x0 = blockIdx.x * per, x1 = min(d.n[c], x0 + per);
+  const double *Acore = (mode == 0) ? d.cores : d.truth;
+  double *Z = smem;
+  const double *zs = sm_slot(d, c, S_ZT);
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) Z[t] = (c == 0) ? ((t / R == t % R) ? 1.0 : 0.0) : zs[t];
+  const Grp q = make_grp(RR);
+  double *sA = smem + RR + q.g * 3 * RR, *sB = sA + RR, *tmp = sB + RR;
+  const int e = q.tl, ea = e / R, eb = e % R;
+  double acc = 0.0;
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    const long long off = d.coff[c] + (long long)x * RR;
+    if (act)
+      for (int t = q.tl; t < RR; t += q.TPG) {
+        sA[t] = Acore[off + t];
+        sB[t] = d.truth[off + t];
+      }
+    __syncthreads();
+    if (act && e < RR) {
+      double v = 0.0;
+      for (int k = 0; k < R; ++k) v += Z[ea * R + k] * sB[k * R + eb];
+      tmp[e] = v;
+    }
+    __syncthreads();
+    if (act && e < RR) {
+      double v = 0.0;
+      for (int k = 0; k < R; ++k) v += sA[k * R + ea] * tmp[k * R + eb];
+      acc += v;
+    }
+    __syncthreads();
+  }
+  double *red = smem + RR;
+  __syncthreads();
+  if (q.g < q.G && e < RR) red[q.g * RR + e] = acc;
+  __syncthreads();
+  double *mypart = d.part + (long long)blockIdx.x * RR;
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    double v = 0.0;
+    for (int g = 0; g < q.G; ++g) v += red[g * RR + t];
+    mypart[t] = v;
+  }
+  if (!arrive_last(&d.st->counter[C_TRUTH])) return;
+  double *Zn = sm_slot(d, c + 1, S_ZT);
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    double v = 0.0;
+    for (int k = 0; k < nb; ++k) v += d.part[(long long)k * RR + t];
+    Zn[t] = v;
+  }
+  __threadfence_block();
+  __syncthreads();
+  if (c == m - 1 && threadIdx.x == 0) {
+    State *st = d.st;
+    const double ip = Zn[0];
+    if (mode == 1) {
+      st->truth_sq = ip;
+    } else {
+      const double diff = fmax(0.0, st->tnorm_sq - 2.0 * ip + st->truth_sq);
+      const double re = sqrt(diff) / sqrt(st->truth_sq);
+      st->rel_error = re;
+      const int it = st->iter - 1;
+      if (it >= 0 && it < d.hist_cap) {
+        d.hist[it].rel_error = re;
+        d.hist[it].flags |= 2;
+      }
+      if (d.stop_rule == STOP_ERROR && re <= d.tol && !st->done) {
+        st->status = 0;
+        st->done = 1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int nblocks_for(int n, int target) {
+  int nb = (n + target - 1) / target;
+  if (nb < 1) nb = 1;
+  if (nb > 256) nb = 256;
+  return nb;
+}
+
+hipError_t launch_dense_iteration(const Dev &d, hipStream_t s, int init) {
+  const int m = d.m;
+  int total_slices_blocks = d.blk_off[m];
+  if (!init) {
+    for (int j = 1; j <= m - 1; ++j) {
+      const int nbL = nblocks_for(d.n[j - 1], 4), nbH = nblocks_for(d.n[m - j], 4);
+      hipLaunchKernelGGL(k_gram, dim3(nbL + nbH), dim3(256), 0, s, d, j, nbL);
+    }
+    hipLaunchKernelGGL(k_tangent, dim3(total_slices_blocks), dim3(256), 0, s, d);
+  }
+  for (int b = m - 1; b >= 1; --b) hipLaunchKernelGGL(k_rgram, dim3(nblocks_for(d.n[b], 4)), dim3(256), 0, s, d, b);
+  for (int i = 1; i <= m - 1; ++i) hipLaunchKernelGGL(k_left, dim3(nblocks_for(d.n[i - 1], 4)), dim3(256), 0, s, d, i);
+  hipLaunchKernelGGL(k_output, dim3(total_slices_blocks), dim3(256), 0, s, d, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_truth_sweep(const Dev &d, hipStream_t s, int mode) {
+  for (int c = 0; c < d.m; ++c) hipLaunchKernelGGL(k_cross, dim3(nblocks_for(d.n[c], 4)), dim3(256), 0, s, d, c, mode);
+  return hipGetLastError();
+}
+
+}  // namespace prgd

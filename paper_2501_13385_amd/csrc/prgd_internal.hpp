@@ -1,0 +1,120 @@
+// Internal definitions shared by the host runtime and the HIP kernels.
+//
+// Device layout of one solve (all sizes in elements):
+//   cores   : core k stored slice-major, padded: [n_k][R][R] at coff[k], where
+//             R >= max r_k is the padded slice dimension.  Entries outside the
+//             true ranks are exactly zero.  Core 0 uses row 0 only, core m-1
+//             column 0 only.
+//   idx     : int32 [m][N], Omega grouped (stably sorted) by mode `sort_mode`.
+//   y       : observed values [N] in the working precision, same order.
+//   Y       : gradient accumulator, layout of the cores (float or double).
+//   X       : tangent components, layout of the cores (double).
+//   s/omega : [sum n_k] mode-slice sums and metric factors at soff[k].
+//   sm      : small-matrix workspace, SM_SLOTS slots of SLOT doubles per bond
+//             b = 0..m (bond b sits between cores b-1 and b).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace prgd {
+
+constexpr int MAXM = 32;
+constexpr int RMAX = 16;
+constexpr int SLOT = 4 * RMAX * RMAX;   // one 2R x 2R double matrix
+
+// small-matrix slots per bond
+enum Slot {
+  S_GL = 0,   // weighted left Gram  GL_b = sum_x w T^T GL_{b-1} T        (R x R)
+  S_GLI,      // inverse of GL_b on its active r_b x r_b block            (R x R)
+  S_H,        // weighted right Gram H_b = sum_x w T H_{b+1} T^T          (R x R)
+  S_HI,       // inverse of H_b                                           (R x R)
+  S_TH,       // Theta_b = sum_x T_b^T Y_b  (core b)                       (R x R)
+  S_PSI,      // Psi_b = GL_{b+1}^{-1} Theta_b H_{b+1}^{-1}  (core b)       (R x R)
+  S_GR,       // right Gram of the block TT W^{>=b}                       (2R x 2R)
+  S_F,        // factor F_b with F F^T = GR_b (columns 0..rankF-1)       (2R x 2R)
+  S_P,        // P_b = T'^{<=b,T} W^{<=b}                                (R x 2R)
+  S_TR,       // truncation map Tr_b = F Z_r Sigma_r^{-1}                 (2R x R)
+  S_ZT,       // cross Gram with the truth  T'^{<=b,T} T*^{<=b}           (R x R)
+  SM_SLOTS
+};
+
+enum Precision { PREC_FP64 = 0, PREC_MIXED = 1 };
+enum StepPolicy { STEP_THEORY = 0, STEP_CONST = 1 };
+enum StopRule { STOP_RESIDUAL = 0, STOP_CHANGE = 1, STOP_ERROR = 2, STOP_NONE = 3 };
+
+// counters used by the "last block finishes the reduction" pattern
+enum Counter { C_SAMPLED = 0, C_GRAM, C_GR, C_LEFT, C_OUT, C_TRUTH, C_COUNT };
+
+struct IterRecord {      // mirrors prgd_iter_info
+  int iter;
+  int flags;
+  double rel_residual;
+  double rel_change;
+  double rel_error;
+  double eps;
+  double alpha;
+};
+
+struct State {
+  double y_sq;          // ||y||^2
+  double res_sq;        // ||R||^2 of the last evaluated iterate
+  double eps_n;         // eps used to normalise the metric (eps_l or eps_fixed)
+  double alpha_n;       // step in normalised units (see dense kernels)
+  double tnorm_sq;      // ||T_l||^2
+  double truth_sq;      // ||T*||^2
+  double newnorm_sq;    // ||T_{l+1}||^2 (scratch of the output kernel)
+  double cross;         // <T_{l+1}, T_l>
+  double rel_res;
+  double rel_change;
+  double rel_error;
+  int iter;             // completed iterations
+  int done;             // 1: no further work
+  int status;           // 0 ok/running, 1 not converged, <0 error
+  int upd;              // 1: the current iteration produced T_{l+1}
+  int rank_f[MAXM + 1]; // numerical rank of F_b
+  unsigned counter[C_COUNT];
+};
+
+struct Dev {
+  int m;
+  int R;                       // padded slice dimension
+  int prec;
+  int step_policy;
+  int stop_rule;
+  int max_iter;
+  int sort_mode;
+  int has_truth;
+  long long N;
+  double step;
+  double eps_fixed;
+  double tol;
+  double p;                    // sampling ratio N / d*
+  int n[MAXM];
+  int r[MAXM + 1];
+  long long coff[MAXM + 1];    // core offsets (padded)
+  int soff[MAXM + 1];          // slice-vector offsets
+  int blk_off[MAXM + 1];       // per-core block offsets for slice-parallel kernels
+  int spb[MAXM];               // slices per block for core k
+  const int *idx;
+  const double *y64;
+  const float *y32;
+  double *cores;               // current iterate T_l (float64 master)
+  float *cores32;              // float32 copy (mixed precision)
+  const double *truth;         // truth cores (padded) or null
+  void *Y;                     // gradient accumulator (float or double per prec)
+  void *s;                     // slice sums (float or double per prec)
+  double *omega;               // metric factors omega_k(x)
+  double *X;                   // tangent components
+  double *sm;                  // small matrices
+  double *part;                // per-block partial results
+  State *st;
+  IterRecord *hist;
+  int hist_cap;
+};
+
+__host__ __device__ inline double *sm_slot(const Dev &d, int bond, int slot) {
+  return d.sm + ((long long)bond * SM_SLOTS + slot) * SLOT;
+}
+
+}  // namespace prgd

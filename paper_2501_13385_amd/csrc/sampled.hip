@@ -1,0 +1,289 @@
+// Sampled-entry pass: for every observed multi-index x^(j) evaluate the
+// current TT iterate as a chain of core-slice products (section 2.1, TT
+// format), form the residual R_j = T_l(x^(j)) - y_j (G_l = P_Omega(T_l - T*),
+// Algorithm 2), accumulate the squared mode-slice norms
+// s_k(x) = sum_{j: x_k = x} R_j^2 (diagonal of M_k(G_l) M_k(G_l)^T, section
+// 3.2.1) and scatter the residual into the Euclidean core gradient
+// Y_k(:, x_k, :) += R_j * l_{k-1}(x)^T rho_{k+1}(x)^T, where l and rho are the
+// left and right interface vectors T^{<=k-1}(x_{<k}) and T^{>=k+1}(x_{>k}).
+//
+// The weights and the gauge of the preconditioned projection act per mode
+// slice, so this one pass with the unscaled cores carries all the sampled
+// information the projection of Lemma 3 needs (see dense.hip).
+#include "prgd_internal.hpp"
+#include "block_ops.hpp"
+
+namespace prgd {
+
+template <typename F>
+__device__ inline void atomic_add(F *p, F v) {
+  atomicAdd(p, v);
+}
+
+// Finish the pass in the last block: total ||R||^2, residual stopping test,
+// eps_l = max_{k,x} s_k(x) (= ||G_l||_vee^2), metric factors
+// omega_k(x) = (1 + s_k(x)/eps)^{1/(2m)} and the normalised step.
+template <typename F>
+__device__ void sampled_finish(const Dev &d, F *sacc, int diag) {
+  __shared__ double sbuf[16];
+  State *st = d.st;
+  const int nb = gridDim.x;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += d.part[i];
+  const double rs = block_sum(v, sbuf);
+  if (diag) {
+    if (threadIdx.x == 0) st->res_sq = rs;
+    return;
+  }
+  const int m = d.m;
+  const int stot = d.soff[m];
+  double emax = 0.0;
+  for (int i = threadIdx.x; i < stot; i += blockDim.x) emax = fmax(emax, (double)sacc[i]);
+  emax = block_max(emax, sbuf);
+  __shared__ int go;
+  if (threadIdx.x == 0) {
+    go = 0;
+    st->res_sq = rs;
+    const double rel = st->y_sq > 0.0 ? sqrt(rs / st->y_sq) : sqrt(rs);
+    st->rel_res = rel;
+    const int it = st->iter;
+    IterRecord rec;
+    rec.iter = it;
+    rec.flags = 0;
+    rec.rel_residual = rel;
+    rec.rel_change = 0.0;
+    rec.rel_error = 0.0;
+    rec.eps = 0.0;
+    rec.alpha = 0.0;
+    if (!isfinite(rs)) {
+      st->status = -5;
+      st->done = 1;
+    } else if (d.stop_rule == STOP_RESIDUAL && rel <= d.tol) {
+      st->status = 0;
+      st->done = 1;
+    } else if (it >= d.max_iter) {
+      st->status = (d.stop_rule == STOP_NONE) ? 0 : 1;
+      st->done = 1;
+    } else if (emax == 0.0) {
+      st->status = 0;      // G_l = 0: T_l fits every observation
+      st->done = 1;
+    } else {
+      const double epsn = d.eps_fixed > 0.0 ? d.eps_fixed : emax;
+      st->eps_n = epsn;
+      st->alpha_n = (d.step_policy == STEP_THEORY) ? d.step / d.p : d.step / sqrt(epsn);
+      rec.eps = epsn;
+      rec.alpha = st->alpha_n * sqrt(epsn);
+      st->upd = 0;
+      go = 1;
+    }
+    if (it < d.hist_cap) d.hist[it] = rec;
+  }
+  __syncthreads();
+  if (go) {
+    const double inv = 1.0 / st->eps_n;
+    const double ex = 1.0 / (2.0 * m);
+    for (int i = threadIdx.x; i < stot; i += blockDim.x) {
+      d.omega[i] = pow(1.0 + (double)sacc[i] * inv, ex);
+      sacc[i] = (F)0;
+    }
+  }
+}
+
+// One thread per sample.  The right interface vectors rho_k (k = m..2) are
+// computed first and kept in LDS (thread-interleaved, conflict-free); the
+// left vector is then carried left to right while scattering.
+template <typename F, int R>
+__global__ void __launch_bounds__(256) k_sampled(Dev d, int diag) {
+  if (!diag && d.st->done) return;
+  extern __shared__ unsigned char lds_raw[];
+  F *stack = reinterpret_cast<F *>(lds_raw);
+  const F *cores = (d.prec == PREC_MIXED) ? (const F *)d.cores32 : (const F *)d.cores;
+  const F *y = (d.prec == PREC_MIXED) ? (const F *)d.y32 : (const F *)d.y64;
+  F *Yg = (F *)d.Y;
+  F *sacc = (F *)d.s;
+  const int m = d.m;
+  const long long N = d.N;
+  const int B = blockDim.x, t = threadIdx.x;
+  constexpr int RR = R * R;
+  double rsq = 0.0;
+  for (long long j = (long long)blockIdx.x * B + t; j < N; j += (long long)gridDim.x * B) {
+    F rho[R];
+    {
+      const int x = d.idx[(long long)(m - 1) * N + j];
+      const F *sl = cores + d.coff[m - 1] + (long long)x * RR;
+#pragma unroll
+      for (int a = 0; a < R; ++a) rho[a] = sl[a * R];
+    }
+#pragma unroll
+    for (int a = 0; a < R; ++a) stack[((m - 2) * R + a) * B + t] = rho[a];
+    for (int k = m - 2; k >= 1; --k) {
+      const int x = d.idx[(long long)k * N + j];
+      const F *sl = cores + d.coff[k] + (long long)x * RR;
+      F nr[R];
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        F acc = (F)0;
+#pragma unroll
+        for (int b = 0; b < R; ++b) acc = fma(sl[a * R + b], rho[b], acc);
+        nr[a] = acc;
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        rho[a] = nr[a];
+        stack[((k - 1) * R + a) * B + t] = nr[a];
+      }
+    }
+    // rho now holds T^{>=2}(x_{>=2}); the entry is T_1(0, x_1, :) rho
+    const int x0 = d.idx[j];
+    const F *sl0 = cores + d.coff[0] + (long long)x0 * RR;
+    F l[R];
+    F tv = (F)0;
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      l[b] = sl0[b];
+      tv = fma(l[b], rho[b], tv);
+    }
+    const F res = tv - y[j];
+    const F r2 = res * res;
+    rsq += (double)r2;
+    {
+      F *yg = Yg + d.coff[0] + (long long)x0 * RR;
+#pragma unroll
+      for (int b = 0; b < R; ++b) atomic_add(&yg[b], res * rho[b]);
+      atomic_add(&sacc[d.soff[0] + x0], r2);
+    }
+    for (int k = 1; k <= m - 2; ++k) {
+      const int x = d.idx[(long long)k * N + j];
+      const F *sl = cores + d.coff[k] + (long long)x * RR;
+      F *yg = Yg + d.coff[k] + (long long)x * RR;
+      F rr[R];
+#pragma unroll
+      for (int b = 0; b < R; ++b) rr[b] = stack[(k * R + b) * B + t];
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        const F ra = res * l[a];
+#pragma unroll
+        for (int b = 0; b < R; ++b) atomic_add(&yg[a * R + b], ra * rr[b]);
+      }
+      F nl[R];
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        F acc = (F)0;
+#pragma unroll
+        for (int a = 0; a < R; ++a) acc = fma(l[a], sl[a * R + b], acc);
+        nl[b] = acc;
+      }
+#pragma unroll
+      for (int b = 0; b < R; ++b) l[b] = nl[b];
+      atomic_add(&sacc[d.soff[k] + x], r2);
+    }
+    {
+      const int x = d.idx[(long long)(m - 1) * N + j];
+      F *yg = Yg + d.coff[m - 1] + (long long)x * RR;
+#pragma unroll
+      for (int a = 0; a < R; ++a) atomic_add(&yg[a * R], res * l[a]);
+      atomic_add(&sacc[d.soff[m - 1] + x], r2);
+    }
+  }
+  __shared__ double sbuf[16];
+  const double bs = block_sum(rsq, sbuf);
+  if (threadIdx.x == 0) d.part[blockIdx.x] = bs;
+  if (arrive_last(&d.st->counter[C_SAMPLED])) sampled_finish<F>(d, sacc, diag);
+}
+
+// Plain evaluation T(x^(j)) for prgd_eval (float64, padded cores).
+template <int R>
+__global__ void __launch_bounds__(256) k_eval(int m, long long N, const int *__restrict__ idx,
+                                              const double *__restrict__ cores, const long long *coff_dev,
+                                              double *__restrict__ out) {
+  constexpr int RR = R * R;
+  __shared__ long long coff[MAXM + 1];
+  for (int i = threadIdx.x; i <= m; i += blockDim.x) coff[i] = coff_dev[i];
+  __syncthreads();
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < N;
+       j += (long long)gridDim.x * blockDim.x) {
+    double l[R];
+    const double *sl0 = cores + coff[0] + (long long)idx[j] * RR;
+#pragma unroll
+    for (int b = 0; b < R; ++b) l[b] = sl0[b];
+    for (int k = 1; k < m; ++k) {
+      const double *sl = cores + coff[k] + (long long)idx[(long long)k * N + j] * RR;
+      double nl[R];
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < R; ++a) acc = fma(l[a], sl[a * R + b], acc);
+        nl[b] = acc;
+      }
+#pragma unroll
+      for (int b = 0; b < R; ++b) l[b] = nl[b];
+    }
+    out[j] = l[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+
+static int lds_block(int m, int R, int elem) {
+  // choose the largest block (multiple of 64, <= 256) whose interface stack fits 63 KiB
+  const long long per = (long long)(m - 1) * R * elem;
+  for (int b = 256; b >= 64; b -= 64)
+    if (per * b <= 64512) return b;
+  return 0;
+}
+
+template <typename F, int R>
+static hipError_t launch_sampled_t(const Dev &d, int diag, int nblocks, hipStream_t s) {
+  const int B = lds_block(d.m, R, (int)sizeof(F));
+  if (B == 0) return hipErrorInvalidValue;
+  const size_t lds = (size_t)(d.m - 1) * R * sizeof(F) * B;
+  hipLaunchKernelGGL((k_sampled<F, R>), dim3(nblocks), dim3(B), lds, s, d, diag);
+  return hipGetLastError();
+}
+
+template <typename F>
+static hipError_t launch_sampled_f(const Dev &d, int diag, int nblocks, hipStream_t s) {
+  switch (d.R) {
+    case 2: return launch_sampled_t<F, 2>(d, diag, nblocks, s);
+    case 4: return launch_sampled_t<F, 4>(d, diag, nblocks, s);
+    case 6: return launch_sampled_t<F, 6>(d, diag, nblocks, s);
+    case 8: return launch_sampled_t<F, 8>(d, diag, nblocks, s);
+    case 10: return launch_sampled_t<F, 10>(d, diag, nblocks, s);
+    case 12: return launch_sampled_t<F, 12>(d, diag, nblocks, s);
+    case 16: return launch_sampled_t<F, 16>(d, diag, nblocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int sampled_block_size(int m, int R, int prec) {
+  return lds_block(m, R, prec == PREC_MIXED ? 4 : 8);
+}
+
+hipError_t launch_sampled(const Dev &d, int diag, int nblocks, hipStream_t s) {
+  if (d.prec == PREC_MIXED) return launch_sampled_f<float>(d, diag, nblocks, s);
+  return launch_sampled_f<double>(d, diag, nblocks, s);
+}
+
+hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *cores, const long long *coff_dev,
+                       double *out, hipStream_t s) {
+  const int nb = (int)((N + 255) / 256 < 4096 ? (N + 255) / 256 : 4096);
+  switch (R) {
+#define PRGD_EVAL_CASE(RV) \
+  case RV: hipLaunchKernelGGL((k_eval<RV>), dim3(nb), dim3(256), 0, s, m, N, idx, cores, coff_dev, out); break;
+    PRGD_EVAL_CASE(2)
+    PRGD_EVAL_CASE(4)
+    PRGD_EVAL_CASE(6)
+    PRGD_EVAL_CASE(8)
+    PRGD_EVAL_CASE(10)
+    PRGD_EVAL_CASE(12)
+    PRGD_EVAL_CASE(16)
+#undef PRGD_EVAL_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace prgd

@@ -1,0 +1,111 @@
+// One-time preparation of the observation set on the device: group Omega by
+// one mode with a stable radix sort (rocPRIM), gather the index rows and the
+// values into that order, and small fill/convert kernels.
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
+#include "prgd_internal.hpp"
+
+namespace prgd {
+
+__global__ void k_iota(int *p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = (int)i;
+}
+
+__global__ void k_gather_idx(int m, long long N, const int *__restrict__ src, const int *__restrict__ perm,
+                             int *__restrict__ dst) {
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (long long)gridDim.x * blockDim.x) {
+    const long long p = perm[j];
+    for (int k = 0; k < m; ++k) dst[(long long)k * N + j] = src[(long long)k * N + p];
+  }
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_gather_val(long long N, const Tin *__restrict__ src, const int *__restrict__ perm,
+                             Tout *__restrict__ dst) {
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (long long)gridDim.x * blockDim.x)
+    dst[j] = (Tout)src[perm[j]];
+}
+
+__global__ void k_fill_f64(double *p, long long n, double v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_fill_f32(float *p, long long n, float v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_convert_f64_f32(const double *src, float *dst, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+static int grid_for(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t fill_f64(double *p, long long n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t fill_f32(float *p, long long n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert_f64_f32, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+// Group Omega by mode `mode`: stable sort of the samples by their mode index.
+// idx_in: [m][N] device, values_in: [N] device (float or double).
+// Outputs idx_out [m][N], y64/y32 (whichever is non-null) in sorted order.
+hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *idx_in, const void *values_in,
+                         int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s) {
+  hipError_t e;
+  int *keys_out = nullptr, *perm_in = nullptr, *perm_out = nullptr;
+  void *temp = nullptr;
+  size_t temp_bytes = 0;
+  unsigned end_bit = 1;
+  while (end_bit < 31 && (1u << end_bit) < (unsigned)n_mode) ++end_bit;
+  if ((e = hipMalloc((void **)&keys_out, N * sizeof(int))) != hipSuccess) return e;
+  if ((e = hipMalloc((void **)&perm_in, N * sizeof(int))) != hipSuccess) return e;
+  if ((e = hipMalloc((void **)&perm_out, N * sizeof(int))) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_iota, dim3(grid_for(N)), dim3(256), 0, s, perm_in, N);
+  const int *keys_in = idx_in + (long long)mode * N;
+  e = rocprim::radix_sort_pairs(nullptr, temp_bytes, keys_in, keys_out, perm_in, perm_out, (size_t)N, 0, end_bit, s);
+  if (e != hipSuccess) return e;
+  if ((e = hipMalloc(&temp, temp_bytes ? temp_bytes : 16)) != hipSuccess) return e;
+  e = rocprim::radix_sort_pairs(temp, temp_bytes, keys_in, keys_out, perm_in, perm_out, (size_t)N, 0, end_bit, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_gather_idx, dim3(grid_for(N)), dim3(256), 0, s, m, N, idx_in, perm_out, idx_out);
+  if (values_fp64) {
+    if (y64) hipLaunchKernelGGL((k_gather_val<double, double>), dim3(grid_for(N)), dim3(256), 0, s, N,
+                                (const double *)values_in, perm_out, y64);
+    if (y32) hipLaunchKernelGGL((k_gather_val<double, float>), dim3(grid_for(N)), dim3(256), 0, s, N,
+                                (const double *)values_in, perm_out, y32);
+  } else {
+    if (y64) hipLaunchKernelGGL((k_gather_val<float, double>), dim3(grid_for(N)), dim3(256), 0, s, N,
+                                (const float *)values_in, perm_out, y64);
+    if (y32) hipLaunchKernelGGL((k_gather_val<float, float>), dim3(grid_for(N)), dim3(256), 0, s, N,
+                                (const float *)values_in, perm_out, y32);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  hipFree(temp);
+  hipFree(keys_out);
+  hipFree(perm_in);
+  hipFree(perm_out);
+  return hipGetLastError();
+}
+
+}  // namespace prgd

@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 reference.
+
+Bars (written here, derived in the design notes):
+* sampled pass in float64: gradient blocks, slice sums and ||R||^2 within
+  1e-12 relative (summation order differs: atomics vs numpy);
+* full iteration in float64: per-iteration relative iterate difference
+  ||T_gpu - T_ref||_F / ||T_ref||_F <= 1e-10 (tensors, gauge-free);
+* mixed precision: final relative recovery error within 1e-5 of the reference's.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import prgd, tt
+from paper_2501_13385_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2501_13385_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def rel_dist(a, b):
+    return tt.tt_dist(a, b) / tt.tt_norm(b)
+
+
+def observed(pb):
+    return tt.tt_eval(pb.truth, pb.indices) + pb.noise_std * pb.noise
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ragged_problem(seed=3):
+    shape = [7, 11, 5, 9]
+    ranks = [1, 3, 5, 2, 1]
+    return wl.problem(shape, ranks, 1500, seed, name="ragged", truth_kind="gaussian", init_rel=0.1)
+
+
+SAMPLED_CASES = ["c1", "c2_small", "ragged", "order2", "order6"]
+
+
+def make_case(name):
+    if name == "ragged":
+        return ragged_problem()
+    if name == "order2":
+        return wl.problem([37, 29], [1, 3, 1], 400, 5, name="order2", init_rel=0.2)
+    if name == "order6":
+        shape = [3, 4, 3, 5, 3, 4]
+        return wl.problem(shape, wl.feasible_ranks(shape, 4), 1200, 6, name="order6", init_rel=0.1)
+    return wl.named(name)
+
+
+@pytest.mark.parametrize("name", SAMPLED_CASES)
+def test_sampled_pass_fp64_matches_reference(L, name):
+    pb = make_case(name)
+    say("case", name, pb.shape, pb.ranks, pb.n_obs)
+    y = observed(pb)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, stop_rule="none", max_iter=0)
+    try:
+        cores = s.cores()        # left-orthogonalised T_0 (same tensor)
+        assert rel_dist(cores, pb.init) < 1e-12
+        grads, ssq, rsq = s.sampled_pass()
+    finally:
+        s.close()
+    r = prgd.residual(cores, pb.indices, y)
+    ref_g = prgd.core_gradient(cores, pb.indices, r)
+    ref_s = prgd.slice_norms(pb.indices, r, pb.shape)
+    assert abs(rsq - float(r @ r)) <= 1e-12 * float(r @ r)
+    for k in range(pb.order):
+        scale = np.abs(ref_g[k]).max()
+        assert np.abs(grads[k] - ref_g[k]).max() <= 1e-12 * scale, k
+        np.testing.assert_allclose(ssq[k], ref_s[k], rtol=1e-12, atol=1e-14 * ref_s[k].max())
+
+
+@pytest.mark.parametrize("name", ["c1", "c2_small"])
+def test_sampled_pass_mixed_matches_reference(L, name):
+    pb = make_case(name)
+    y = observed(pb)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, precision="mixed", stop_rule="none", max_iter=0)
+    try:
+        cores = s.cores()
+        grads, ssq, rsq = s.sampled_pass()
+    finally:
+        s.close()
+    r = prgd.residual(cores, pb.indices, y)
+    ref_g = prgd.core_gradient(cores, pb.indices, r)
+    assert abs(rsq - float(r @ r)) <= 1e-4 * float(r @ r)
+    for k in range(pb.order):
+        assert np.linalg.norm(grads[k] - ref_g[k]) <= 1e-4 * np.linalg.norm(ref_g[k]), k
+
+
+def test_eval_matches_reference(L):
+    pb = make_case("ragged")
+    got = L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices)
+    ref = tt.tt_eval(pb.truth, pb.indices)
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("name,c,iters", [("c1", 1.001, 25), ("c2_small", 0.8, 12), ("ragged", 0.8, 10),
+                                          ("order2", 0.8, 10), ("order6", 0.8, 8)])
+def test_fp64_iterates_match_reference_each_iteration(L, name, c, iters):
+    pb = make_case(name)
+    say("case", name, "iters", iters)
+    y = observed(pb)
+    pol = prgd.Policy(step_rule="theory", c=c)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, step=c, stop_rule="none", max_iter=iters)
+    ref = [x.copy() for x in pb.init]
+    worst = 0.0
+    try:
+        for it in range(iters):
+            s.iterate(1)
+            got = s.cores()
+            ref, info = prgd.prgd_step(ref, pb.indices, y, pol, pb.ranks)
+            d = rel_dist(got, ref)
+            worst = max(worst, d)
+            assert d <= 1e-10, (it, d)
+        hist = s.history()
+    finally:
+        s.close()
+    say("worst per-iteration difference", worst)
+    assert len(hist) >= iters
+    # left-orthogonal output cores
+    for core in got[:-1]:
+        lm = core.reshape(-1, core.shape[2])
+        np.testing.assert_allclose(lm.T @ lm, np.eye(core.shape[2]), atol=1e-12)
+
+
+def test_fp64_history_matches_reference(L):
+    pb = make_case("c2_small")
+    y = observed(pb)
+    pol = prgd.Policy(step_rule="theory", c=0.8, stop_rule="change", tol=1e-6, max_iter=8)
+    ref = prgd.prgd(pb.init, pb.indices, y, pol, truth=pb.truth)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, truth_cores=pb.truth, step=0.8,
+                 stop_rule="change", tol=1e-6, max_iter=8)
+    try:
+        rep = s.run()
+        hist = s.history()
+        got = s.cores()
+    finally:
+        s.close()
+    assert rep["iterations"] == ref.iterations == 8
+    assert rel_dist(got, ref.cores) < 1e-10
+    for h, rh in zip(hist, ref.history):
+        assert h["iter"] == rh["iter"]
+        assert abs(h["rel_residual"] - rh["rel_res"]) <= 1e-10 * rh["rel_res"]
+        assert abs(h["eps"] - rh["eps"]) <= 1e-10 * rh["eps"]
+        assert abs(h["alpha"] - rh["alpha"]) <= 1e-10 * rh["alpha"]
+        assert abs(h["rel_change"] - rh["rel_change"]) <= 1e-6 * rh["rel_change"]
+        assert abs(h["rel_error"] - rh["rel_err"]) <= 1e-6 * rh["rel_err"]
+
+
+def test_c1_recovery_matches_reference(L):
+    """Configuration 1: noiseless, stop at relative residual 1e-10 or 500 iterations."""
+    pb = wl.named("c1")
+    y = observed(pb)
+    pol = prgd.Policy(step_rule="theory", c=1.001, stop_rule="residual", tol=1e-10, max_iter=500)
+    ref = prgd.prgd(pb.init, pb.indices, y, pol, truth=pb.truth)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, truth_cores=pb.truth, step=1.001,
+                 stop_rule="residual", tol=1e-10, max_iter=500)
+    try:
+        rep = s.run()
+        got = s.cores()
+    finally:
+        s.close()
+    say("gpu", rep, "ref iterations", ref.iterations)
+    assert rep["status"] == 0
+    assert abs(rep["iterations"] - ref.iterations) <= 1
+    assert rep["rel_residual"] <= 1e-10
+    assert rel_dist(got, pb.truth) <= 1e-9
+
+
+def test_mixed_precision_recovery_within_1e5_of_reference(L):
+    pb = make_case("c2_small")
+    y = observed(pb)
+    pol = prgd.Policy(step_rule="theory", c=0.8, stop_rule="change", tol=1e-6, max_iter=200)
+    ref = prgd.prgd(pb.init, pb.indices, y, pol, truth=pb.truth)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y.astype(np.float32), pb.init, truth_cores=pb.truth,
+                 precision="mixed", step=0.8, stop_rule="change", tol=1e-6, max_iter=200)
+    try:
+        rep = s.run()
+        got = s.cores()
+    finally:
+        s.close()
+    e_gpu = rel_dist(got, pb.truth)
+    e_ref = rel_dist(ref.cores, pb.truth)
+    say("mixed", e_gpu, "ref", e_ref, rep["iterations"], ref.iterations)
+    assert abs(e_gpu - e_ref) <= 1e-5
+
+
+def test_device_inputs_and_sort_modes_agree(L):
+    torch = pytest.importorskip("torch")
+    pb = make_case("ragged")
+    y = observed(pb)
+    outs = []
+    for mode in (-1, 0, 3):
+        s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, stop_rule="none", max_iter=3, sort_mode=mode)
+        s.iterate(3)
+        outs.append(s.cores())
+        s.close()
+    di = torch.from_numpy(pb.indices).cuda()
+    dv = torch.from_numpy(y).cuda()
+    s = L.Solver(pb.shape, pb.ranks, di, dv, pb.init, stop_rule="none", max_iter=3)
+    s.iterate(3)
+    outs.append(s.cores())
+    s.close()
+    for o in outs[1:]:
+        assert rel_dist(o, outs[0]) < 1e-12
