@@ -94,6 +94,7 @@ def load() -> C.CDLL:
         "prgd_create": (i32, [C.POINTER(prgd_desc), C.POINTER(vp)]),
         "prgd_iterate": (i32, [vp, i32]),
         "prgd_sync": (i32, [vp]),
+        "prgd_iterate_profiled": (i32, [vp, i32, dp]),
         "prgd_run": (i32, [vp, C.POINTER(prgd_report)]),
         "prgd_get_report": (i32, [vp, C.POINTER(prgd_report)]),
         "prgd_get_cores": (i32, [vp, dp, i64]),
@@ -113,7 +114,8 @@ def load() -> C.CDLL:
 
 
 def exported_symbols() -> List[str]:
-    return [n for n in ("prgd_cores_numel", "prgd_create", "prgd_iterate", "prgd_sync", "prgd_run",
+    return [n for n in ("prgd_cores_numel", "prgd_create", "prgd_iterate", "prgd_iterate_profiled",
+                        "prgd_sync", "prgd_run",
                         "prgd_get_report", "prgd_get_cores", "prgd_get_history", "prgd_sampled_pass",
                         "prgd_eval", "prgd_destroy", "prgd_status_str", "prgd_last_error")]
 
@@ -223,6 +225,17 @@ def prgd_iterate(h, iters: int) -> None:
     _check(load().prgd_iterate(h, int(iters)))
 
 
+NPHASES = 5
+PHASES = ["sampled", "project", "retract", "output", "truth"]
+
+
+def prgd_iterate_profiled(h, iters: int) -> dict:
+    """Run ``iters`` iterations with per-phase HIP events; returns summed milliseconds per phase."""
+    buf = (C.c_double * NPHASES)()
+    _check(load().prgd_iterate_profiled(h, int(iters), buf))
+    return {PHASES[i]: float(buf[i]) for i in range(NPHASES)}
+
+
 def prgd_sync(h) -> None:
     _check(load().prgd_sync(h))
 
@@ -317,6 +330,9 @@ class Solver:
 
     def sync(self):
         prgd_sync(self.h)
+
+    def iterate_profiled(self, k: int) -> dict:
+        return prgd_iterate_profiled(self.h, k)
 
     def run(self) -> dict:
         return prgd_run(self.h)

@@ -52,14 +52,39 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _runtime_stub() -> str:
+    """An empty link-time stand-in named libamdhip64.so.
+
+    Linking against it records the dependency as ``libamdhip64.so`` (the name
+    PyTorch's ROCm build loads its HIP runtime under) instead of the versioned
+    ``libamdhip64.so.7``.  In a process that already holds a HIP runtime under
+    that name the library then binds to it, so one process never ends up with
+    two HIP runtimes; on its own it resolves to ROCm's runtime through the rpath.
+    """
+    d = os.path.join(BUILD, "stub")
+    os.makedirs(d, exist_ok=True)
+    src = os.path.join(d, "stub.c")
+    with open(src, "w") as f:
+        f.write("/* link-time stand-in; the real runtime is resolved at load time */\n")
+    out = os.path.join(d, "libamdhip64.so")
+    cmd = ["gcc", "-shared", "-fPIC", "-Wl,-soname,libamdhip64.so", "-o", out, src]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"stub build failed: {res.stderr}")
+    return d
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    stub = _runtime_stub()
     srcs = sources()
     jobs = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(hipcc()))), "lib")
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", f"-L{stub}", "-Wl,--no-as-needed",
+           f"-Wl,-rpath,{rocm_lib}", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -20,6 +20,9 @@ int sampled_block_size(int m, int R, int prec);
 hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *cores, const long long *coff_dev,
                        double *out, hipStream_t s);
 hipError_t launch_dense_iteration(const Dev &d, hipStream_t s, int init);
+hipError_t launch_project(const Dev &d, hipStream_t s);
+hipError_t launch_retract(const Dev &d, hipStream_t s);
+hipError_t launch_output(const Dev &d, hipStream_t s, int init);
 hipError_t launch_truth_sweep(const Dev &d, hipStream_t s, int mode);
 hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *idx_in, const void *values_in,
                          int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s);
@@ -458,6 +461,44 @@ prgd_status prgd_iterate(prgd_solver s, int32_t iters) {
   if (!s) return fail(PRGD_ESTATE, "null solver");
   if (iters < 0) return fail(PRGD_EINVAL, "iters < 0");
   return enqueue_iterations(s, iters);
+}
+
+prgd_status prgd_iterate_profiled(prgd_solver s, int32_t iters, double *phase_ms) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  if (iters < 0 || !phase_ms) return fail(PRGD_EINVAL, "iters < 0 or null phase_ms");
+  constexpr int NP = PRGD_NPHASES;
+  for (int p = 0; p < NP; ++p) phase_ms[p] = 0.0;
+  if (iters == 0) return PRGD_OK;
+  std::vector<hipEvent_t> ev((size_t)iters * (NP + 1));
+  for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
+  prgd_status rc = PRGD_OK;
+  for (int it = 0; it < iters && rc == PRGD_OK; ++it) {
+    hipEvent_t *e = ev.data() + (size_t)it * (NP + 1);
+    hipError_t err = hipSuccess;
+    auto chk = [&](hipError_t x) { if (x != hipSuccess && err == hipSuccess) err = x; };
+    chk(hipEventRecord(e[0], s->stream));
+    chk(launch_sampled(s->d, 0, s->sampled_blocks, s->stream));
+    chk(hipEventRecord(e[1], s->stream));
+    chk(launch_project(s->d, s->stream));
+    chk(hipEventRecord(e[2], s->stream));
+    chk(launch_retract(s->d, s->stream));
+    chk(hipEventRecord(e[3], s->stream));
+    chk(launch_output(s->d, s->stream, 0));
+    chk(hipEventRecord(e[4], s->stream));
+    if (s->has_truth) chk(launch_truth_sweep(s->d, s->stream, 0));
+    chk(hipEventRecord(e[5], s->stream));
+    if (err != hipSuccess) rc = fail(PRGD_EDEVICE, std::string("launch: ") + hipGetErrorString(err));
+  }
+  if (rc == PRGD_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = fail(PRGD_EDEVICE, "sync failed");
+  if (rc == PRGD_OK)
+    for (int it = 0; it < iters; ++it)
+      for (int p = 0; p < NP; ++p) {
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, ev[(size_t)it * (NP + 1) + p], ev[(size_t)it * (NP + 1) + p + 1]);
+        phase_ms[p] += ms;
+      }
+  for (auto &e : ev) hipEventDestroy(e);
+  return rc;
 }
 
 prgd_status prgd_sync(prgd_solver s) {

@@ -955,20 +955,36 @@ static int nblocks_for(int n, int target) {
   return nb;
 }
 
-hipError_t launch_dense_iteration(const Dev &d, hipStream_t s, int init) {
+// phase 1: metric-weighted Gram sweeps and the tangent components
+hipError_t launch_project(const Dev &d, hipStream_t s) {
   const int m = d.m;
-  int total_slices_blocks = d.blk_off[m];
-  if (!init) {
-    for (int j = 1; j <= m - 1; ++j) {
-      const int nbL = nblocks_for(d.n[j - 1], 4), nbH = nblocks_for(d.n[m - j], 4);
-      hipLaunchKernelGGL(k_gram, dim3(nbL + nbH), dim3(256), 0, s, d, j, nbL);
-    }
-    hipLaunchKernelGGL(k_tangent, dim3(total_slices_blocks), dim3(256), 0, s, d);
+  for (int j = 1; j <= m - 1; ++j) {
+    const int nbL = nblocks_for(d.n[j - 1], 4), nbH = nblocks_for(d.n[m - j], 4);
+    hipLaunchKernelGGL(k_gram, dim3(nbL + nbH), dim3(256), 0, s, d, j, nbL);
   }
+  hipLaunchKernelGGL(k_tangent, dim3(d.blk_off[m]), dim3(256), 0, s, d);
+  return hipGetLastError();
+}
+
+// phase 2: retraction sweeps (right Grams of W_l, then the truncated left sweep)
+hipError_t launch_retract(const Dev &d, hipStream_t s) {
+  const int m = d.m;
   for (int b = m - 1; b >= 1; --b) hipLaunchKernelGGL(k_rgram, dim3(nblocks_for(d.n[b], 4)), dim3(256), 0, s, d, b);
   for (int i = 1; i <= m - 1; ++i) hipLaunchKernelGGL(k_left, dim3(nblocks_for(d.n[i - 1], 4)), dim3(256), 0, s, d, i);
-  hipLaunchKernelGGL(k_output, dim3(total_slices_blocks), dim3(256), 0, s, d, init);
   return hipGetLastError();
+}
+
+// phase 3: new cores and the stopping-test reductions
+hipError_t launch_output(const Dev &d, hipStream_t s, int init) {
+  hipLaunchKernelGGL(k_output, dim3(d.blk_off[d.m]), dim3(256), 0, s, d, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_iteration(const Dev &d, hipStream_t s, int init) {
+  hipError_t e;
+  if (!init && (e = launch_project(d, s)) != hipSuccess) return e;
+  if ((e = launch_retract(d, s)) != hipSuccess) return e;
+  return launch_output(d, s, init);
 }
 
 hipError_t launch_truth_sweep(const Dev &d, hipStream_t s, int mode) {
