@@ -58,7 +58,7 @@ def sampled_pass_bytes(shape, n_obs, val_bytes):
     return float(n_obs) * (4 * len(shape) + val_bytes)
 
 
-def gpu_leg(pb, L, precision, steps, warmup):
+def gpu_leg(pb, L, precision, steps, warmup, timed_only=False):
     vals = L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices) + pb.noise_std * pb.noise
     vals = vals.astype(np.float64 if precision == "fp64" else np.float32)
     step_c = pb.step
@@ -81,6 +81,8 @@ def gpu_leg(pb, L, precision, steps, warmup):
     out["ms_per_step"] = 1e3 * wall / steps
     out["value"] = pb.n_obs * steps / wall
     out["phase_ms_per_step"] = {k: v / steps for k, v in phases.items()}
+    if timed_only:
+        return out
     # time to tolerance (relative change <= 1e-6; the noise floor keeps the error
     # against T* near 3e-4, so 1e-6 error is unreachable on this workload)
     s = L.Solver(pb.shape, pb.ranks, pb.indices, vals, pb.init, precision=precision, step=step_c,
@@ -130,6 +132,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run only the timed iterations (for kernel profilers); prints the phase times")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
@@ -145,9 +149,12 @@ def main():
     res = {}
     for prec in (["fp64", "mixed"] if args.only == "both" else [args.only]):
         log(f"gpu leg {prec}: warmup {args.warmup}, steps {args.steps}")
-        res[prec] = gpu_leg(pb, L, prec, args.steps, args.warmup)
+        res[prec] = gpu_leg(pb, L, prec, args.steps, args.warmup, timed_only=args.profile_only)
         log(f"  {prec}: {res[prec]['value']:.4g} samples*it/s, {res[prec]['ms_per_step']:.4f} ms/step, "
             f"phases {res[prec]['phase_ms_per_step']}")
+    if args.profile_only:
+        print(json.dumps({p: r["phase_ms_per_step"] for p, r in res.items()}), flush=True)
+        return
     head = "fp64" if "fp64" in res else "mixed"
     h = res[head]
     flops = sampled_pass_flops(pb.shape, pb.ranks, pb.n_obs)

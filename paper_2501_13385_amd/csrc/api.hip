@@ -29,6 +29,8 @@ hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *id
 hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t s);
 hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream_t s);
+size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage);
+hipError_t launch_sampled3(const Dev &d, const S3 &q, int diag, hipStream_t st);
 }  // namespace prgd
 
 using namespace prgd;
@@ -100,6 +102,8 @@ struct prgd_solver_s {
   long long N = 0;
   int64_t numel = 0;
   int sampled_blocks = 0;
+  bool use3 = false;     // order-3 grouped sampled pass
+  S3 q3{};
   bool has_truth = false;
   std::vector<void *> allocs;
   double last_seconds = 0.0;
@@ -196,9 +200,14 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
   return PRGD_OK;
 }
 
+hipError_t sampled_pass(prgd_solver s, int diag) {
+  if (s->use3) return launch_sampled3(s->d, s->q3, diag, s->stream);
+  return launch_sampled(s->d, diag, s->sampled_blocks, s->stream);
+}
+
 prgd_status enqueue_iterations(prgd_solver s, int iters) {
   for (int it = 0; it < iters; ++it) {
-    HIPCHECK(launch_sampled(s->d, 0, s->sampled_blocks, s->stream));
+    HIPCHECK(sampled_pass(s, 0));
     HIPCHECK(launch_dense_iteration(s->d, s->stream, 0));
     if (s->has_truth) HIPCHECK(launch_truth_sweep(s->d, s->stream, 0));
   }
@@ -357,11 +366,13 @@ prgd_status prgd_create(const prgd_desc *ds, prgd_solver *out) {
             A(s->alloc(&d.part, 1 << 20)) && A(s->alloc(&d.st, 1));
   d.hist_cap = ds->max_iter + 1;
   ok = ok && A(s->alloc(&d.hist, d.hist_cap));
+  const long long nbnd = (long long)(s->n[0] + s->n[m - 1]) * R;
   if (mixed) {
     ok = ok && A(s->alloc(&y32, N)) && A(s->alloc(&d.cores32, pn)) && A(s->alloc((float **)&d.Y, pn)) &&
-         A(s->alloc((float **)&d.s, soff));
+         A(s->alloc((float **)&d.s, soff)) && A(s->alloc((float **)&d.bnd, nbnd));
   } else {
-    ok = ok && A(s->alloc(&y64, N)) && A(s->alloc((double **)&d.Y, pn)) && A(s->alloc((double **)&d.s, soff));
+    ok = ok && A(s->alloc(&y64, N)) && A(s->alloc((double **)&d.Y, pn)) && A(s->alloc((double **)&d.s, soff)) &&
+         A(s->alloc((double **)&d.bnd, nbnd));
   }
   if (!ok) return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
   d.y64 = y64;
@@ -433,6 +444,56 @@ prgd_status prgd_create(const prgd_desc *ds, prgd_solver *out) {
     if (fill_f64((double *)d.Y, pn, 0.0, s->stream) != hipSuccess || fill_f64((double *)d.s, soff, 0.0, s->stream) != hipSuccess)
       return cleanup(fail(PRGD_EDEVICE, "fill failed"));
   }
+  // order-3 grouped sampled pass: per-workgroup chunks of the samples sorted by the middle mode
+  if (m == 3 && sm == 1 && sampled3_lds_bytes(s->n[0], s->n[2], R, d.prec, 0) <= 163840) {
+    S3 &q = s->q3;
+    q.stage = sampled3_lds_bytes(s->n[0], s->n[2], R, d.prec, 1) <= 163840 ? 1 : 0;
+    long long nwg = std::min<long long>(256, std::max<long long>(1, (N + 63) / 64));
+    q.chunk = (N + nwg - 1) / nwg;
+    nwg = (N + q.chunk - 1) / q.chunk;
+    q.nwg = (int)nwg;
+    const int n1 = s->n[1];
+    std::vector<long long> seg(n1 + 1, 0);
+    for (long long j = 0; j < N; ++j) seg[idx_h[N + j] + 1]++;
+    for (int v = 0; v < n1; ++v) seg[v + 1] += seg[v];
+    std::vector<int> vfirst(nwg), blo(n1), bhi(n1);
+    for (long long b = 0; b < nwg; ++b) {
+      const long long j0 = b * q.chunk;
+      vfirst[b] = (int)(std::upper_bound(seg.begin(), seg.end(), j0) - seg.begin()) - 1;
+    }
+    for (int v = 0; v < n1; ++v) {
+      if (seg[v + 1] > seg[v]) {
+        blo[v] = (int)(seg[v] / q.chunk);
+        bhi[v] = (int)((seg[v + 1] - 1) / q.chunk);
+      } else {
+        blo[v] = 1;
+        bhi[v] = 0;
+      }
+    }
+    const size_t f = mixed ? 4 : 8;
+    const long long L = (long long)(s->n[0] + s->n[2]) * (R + 1);
+    const long long segw = (long long)R * R + 1;
+    int *dvf = nullptr, *dlo = nullptr, *dhi = nullptr;
+    unsigned char *pbnd = nullptr, *pseg = nullptr, *povf = nullptr;
+    if (!A(s->alloc(&dvf, nwg)) || !A(s->alloc(&dlo, n1)) || !A(s->alloc(&dhi, n1)) ||
+        !A(s->alloc(&pbnd, nwg * L * (long long)f)) || !A(s->alloc(&pseg, nwg * KSEG * segw * (long long)f)) ||
+        !A(s->alloc(&povf, n1 * segw * (long long)f)) || !A(s->alloc(&q.part_rsq, nwg)))
+      return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+    if (hipMemcpyAsync(dvf, vfirst.data(), nwg * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(dlo, blo.data(), n1 * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(dhi, bhi.data(), n1 * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+      return cleanup(fail(PRGD_EDEVICE, "upload of the segment map failed"));
+    const long long novf = n1 * segw;
+    hipError_t fe = mixed ? fill_f32((float *)povf, novf, 0.0f, s->stream) : fill_f64((double *)povf, novf, 0.0, s->stream);
+    if (fe != hipSuccess) return cleanup(fail(PRGD_EDEVICE, "fill failed"));
+    q.vfirst = dvf;
+    q.blo = dlo;
+    q.bhi = dhi;
+    q.part_bnd = pbnd;
+    q.part_seg = pseg;
+    q.ovf = povf;
+    s->use3 = true;
+  }
   // sampled-pass grid: enough waves to fill 256 CUs
   {
     const int B = sampled_block_size(m, R, d.prec);
@@ -477,7 +538,7 @@ prgd_status prgd_iterate_profiled(prgd_solver s, int32_t iters, double *phase_ms
     hipError_t err = hipSuccess;
     auto chk = [&](hipError_t x) { if (x != hipSuccess && err == hipSuccess) err = x; };
     chk(hipEventRecord(e[0], s->stream));
-    chk(launch_sampled(s->d, 0, s->sampled_blocks, s->stream));
+    chk(sampled_pass(s, 0));
     chk(hipEventRecord(e[1], s->stream));
     chk(launch_project(s->d, s->stream));
     chk(hipEventRecord(e[2], s->stream));
@@ -582,7 +643,7 @@ prgd_status prgd_sampled_pass(prgd_solver s, double *grad, double *slice_sq, dou
     HIPCHECK(fill_f64((double *)d.Y, pn, 0.0, s->stream));
     HIPCHECK(fill_f64((double *)d.s, soff, 0.0, s->stream));
   }
-  HIPCHECK(launch_sampled(d, 1, s->sampled_blocks, s->stream));
+  HIPCHECK(sampled_pass(s, 1));
   HIPCHECK(hipStreamSynchronize(s->stream));
   std::vector<double> gp(pn), sv(soff);
   if (mixed) {

@@ -43,6 +43,49 @@ __device__ inline double block_max(double v, double *sbuf) {
   return r;
 }
 
+// Sum nb partial vectors part[b * ne + e] (b < nb, e < ne) into out[e] (LDS),
+// deterministically.  Threads split the partials into groups with several
+// independent accumulators each, so many loads are in flight at once (the
+// partials were written by blocks on other XCDs and arrive with long latency).
+// scratch: LDS of at least blockDim.x doubles.  Ends with a barrier.
+__device__ inline void reduce_partials(const double *part, int nb, int ne, double *out, double *scratch) {
+  const int nt = blockDim.x, t = threadIdx.x;
+  if (ne <= nt) {
+    const int G = nt / ne;                 // groups per entry
+    const int g = t / ne, e = t % ne;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (g < G) {
+      int b = g;
+      for (; b + 3 * G < nb; b += 4 * G) {
+        a0 += part[(long long)b * ne + e];
+        a1 += part[(long long)(b + G) * ne + e];
+        a2 += part[(long long)(b + 2 * G) * ne + e];
+        a3 += part[(long long)(b + 3 * G) * ne + e];
+      }
+      for (; b < nb; b += G) a0 += part[(long long)b * ne + e];
+      scratch[g * ne + e] = (a0 + a1) + (a2 + a3);
+    }
+    __syncthreads();
+    for (int i = t; i < ne; i += nt) {
+      double v = 0.0;
+      for (int gg = 0; gg < G; ++gg) v += scratch[gg * ne + i];
+      out[i] = v;
+    }
+  } else {
+    for (int e = t; e < ne; e += nt) {
+      double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      int b = 0;
+      for (; b + 8 <= nb; b += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += part[(long long)(b + u) * ne + e];
+      }
+      for (; b < nb; ++b) a[0] += part[(long long)b * ne + e];
+      out[e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+  }
+  __syncthreads();
+}
+
 // "Last block" pattern: every block publishes its partial results, then
 // increments a counter; the block that brings the counter to gridDim.x sees
 // all partials (release/acquire fences at device scope) and finishes the

@@ -372,16 +372,16 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, int j, int nbL) {
 
   // last block: totals, inverses
   double *GLj = sm_slot(d, j, S_GL), *THc = sm_slot(d, j - 1, S_TH), *Hb = sm_slot(d, m - j, S_H);
-  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
-    double gl = 0.0, th = 0.0, h = 0.0;
-    for (int b = 0; b < nbL; ++b) {
-      gl += d.part[(long long)b * 2 * RR + t];
-      th += d.part[(long long)b * 2 * RR + RR + t];
+  {
+    double *tot = smem + 2048;           // [2 RR]
+    reduce_partials(d.part, nbL, 2 * RR, tot, smem);
+    for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+      GLj[t] = tot[t];
+      THc[t] = tot[RR + t];
     }
-    for (int b = nbL; b < (int)gridDim.x; ++b) h += d.part[(long long)b * 2 * RR + t];
-    GLj[t] = gl;
-    THc[t] = th;
-    Hb[t] = h;
+    __syncthreads();
+    reduce_partials(d.part + (long long)nbL * 2 * RR, (int)gridDim.x - nbL, 2 * RR, tot, smem);
+    for (int t = threadIdx.x; t < RR; t += blockDim.x) Hb[t] = tot[t];
   }
   __threadfence_block();
   __syncthreads();
@@ -561,10 +561,12 @@ __global__ void __launch_bounds__(256) k_rgram(Dev d, int b) {
   if (!arrive_last(&d.st->counter[C_GR])) return;
 
   double *GR = sm_slot(d, b, S_GR);
-  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
-    double v = 0.0;
-    for (int k = 0; k < nb; ++k) v += d.part[(long long)k * NE + t];
-    GR[t] = v;
+  {
+    double *tot = smem + 4096;
+    reduce_partials(d.part, nb, NE, tot, smem);
+    for (int t = threadIdx.x; t < NE; t += blockDim.x) GR[t] = tot[t];
+    __syncthreads();
+    for (int t = threadIdx.x; t < NE; t += blockDim.x) smem[3072 + t] = tot[t];
   }
   __syncthreads();
   // compress to the active indices [0, r_b) U [R, R + r_b)
@@ -574,7 +576,7 @@ __global__ void __launch_bounds__(256) k_rgram(Dev d, int b) {
   for (int t = threadIdx.x; t < na * na; t += blockDim.x) {
     const int i = t / na, jj = t % na;
     const int gi = i < rb ? i : R + i - rb, gj = jj < rb ? jj : R + jj - rb;
-    A[t] = GR[gi * R2 + gj];
+    A[t] = smem[3072 + gi * R2 + gj];
   }
   __syncthreads();
   const int rank = pivoted_cholesky(A, na, Fc, used);
@@ -664,11 +666,7 @@ __global__ void __launch_bounds__(256) k_left(Dev d, int i) {
   double *Vs = smem + 5120;          // rank x rank (sort scratch)
   double *w = smem + 6144;           // 32
   double *cs = smem + 6176;          // 64
-  for (int t = threadIdx.x; t < NE; t += blockDim.x) {
-    double v = 0.0;
-    for (int k = 0; k < nb; ++k) v += d.part[(long long)k * NE + t];
-    GB[t] = v;
-  }
+  reduce_partials(d.part, nb, NE, GB, smem + 1024);
   const double *fs = sm_slot(d, i, S_F);
   for (int t = threadIdx.x; t < NE; t += blockDim.x) F[t] = fs[t];
   __syncthreads();
@@ -810,6 +808,14 @@ __global__ void __launch_bounds__(256) k_output(Dev d, int init) {
         d.cores[off + t] = out[t];
         if (d.prec == PREC_MIXED) d.cores32[off + t] = (float)out[t];
       }
+      if (c == 0 || c == m - 1) {
+        const long long bo = (c == 0) ? (long long)x * R : (long long)d.n[0] * R + (long long)x * R;
+        for (int a = q.tl; a < R; a += q.TPG) {
+          const double v = (c == 0) ? out[a] : out[a * R];
+          if (d.prec == PREC_MIXED) ((float *)d.bnd)[bo + a] = (float)v;
+          else ((double *)d.bnd)[bo + a] = v;
+        }
+      }
       if (c == m - 1)
         for (int a = q.tl; a < R; a += q.TPG) {
           const double v = out[a * R];
@@ -916,11 +922,8 @@ __global__ void __launch_bounds__(256) k_cross(Dev d, int c, int mode) {
   }
   if (!arrive_last(&d.st->counter[C_TRUTH])) return;
   double *Zn = sm_slot(d, c + 1, S_ZT);
-  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
-    double v = 0.0;
-    for (int k = 0; k < nb; ++k) v += d.part[(long long)k * RR + t];
-    Zn[t] = v;
-  }
+  reduce_partials(d.part, nb, RR, smem + 1024, smem);
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) Zn[t] = smem[1024 + t];
   __threadfence_block();
   __syncthreads();
   if (c == m - 1 && threadIdx.x == 0) {

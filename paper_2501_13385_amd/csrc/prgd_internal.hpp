@@ -105,12 +105,30 @@ struct Dev {
   void *Y;                     // gradient accumulator (float or double per prec)
   void *s;                     // slice sums (float or double per prec)
   double *omega;               // metric factors omega_k(x)
+  void *bnd;                   // compact boundary vectors in the working precision:
+                               // [n_0][R] row 0 of core 0, then [n_{m-1}][R] column 0 of core m-1
   double *X;                   // tangent components
   double *sm;                  // small matrices
   double *part;                // per-block partial results
   State *st;
   IterRecord *hist;
   int hist_cap;
+};
+
+// order-3 sampled pass: per-workgroup partials (see sampled3.hip)
+constexpr int KSEG = 8;   // segment slots per workgroup table
+
+struct S3 {
+  long long chunk;       // samples per workgroup
+  int nwg;
+  int stage;             // 1: boundary vectors staged in LDS
+  const int *vfirst;     // [nwg] first segment (middle-mode index) of each workgroup's chunk
+  const int *blo;        // [n_1] first workgroup covering segment v (blo > bhi: empty segment)
+  const int *bhi;        // [n_1]
+  void *part_bnd;        // [nwg][L]: dT_0 [n_0 R] | dT_2 [n_2 R] | s_0 [n_0] | s_2 [n_2]
+  void *part_seg;        // [nwg][KSEG][R*R + 1]: middle-core gradient pieces and s_1
+  void *ovf;             // [n_1][R*R + 1] overflow accumulator (zero between passes)
+  double *part_rsq;      // [nwg]
 };
 
 __host__ __device__ inline double *sm_slot(const Dev &d, int bond, int slot) {

@@ -12,81 +12,13 @@
 // information the projection of Lemma 3 needs (see dense.hip).
 #include "prgd_internal.hpp"
 #include "block_ops.hpp"
+#include "sampled_common.hpp"
 
 namespace prgd {
 
 template <typename F>
 __device__ inline void atomic_add(F *p, F v) {
   atomicAdd(p, v);
-}
-
-// Finish the pass in the last block: total ||R||^2, residual stopping test,
-// eps_l = max_{k,x} s_k(x) (= ||G_l||_vee^2), metric factors
-// omega_k(x) = (1 + s_k(x)/eps)^{1/(2m)} and the normalised step.
-template <typename F>
-__device__ void sampled_finish(const Dev &d, F *sacc, int diag) {
-  __shared__ double sbuf[16];
-  State *st = d.st;
-  const int nb = gridDim.x;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += d.part[i];
-  const double rs = block_sum(v, sbuf);
-  if (diag) {
-    if (threadIdx.x == 0) st->res_sq = rs;
-    return;
-  }
-  const int m = d.m;
-  const int stot = d.soff[m];
-  double emax = 0.0;
-  for (int i = threadIdx.x; i < stot; i += blockDim.x) emax = fmax(emax, (double)sacc[i]);
-  emax = block_max(emax, sbuf);
-  __shared__ int go;
-  if (threadIdx.x == 0) {
-    go = 0;
-    st->res_sq = rs;
-    const double rel = st->y_sq > 0.0 ? sqrt(rs / st->y_sq) : sqrt(rs);
-    st->rel_res = rel;
-    const int it = st->iter;
-    IterRecord rec;
-    rec.iter = it;
-    rec.flags = 0;
-    rec.rel_residual = rel;
-    rec.rel_change = 0.0;
-    rec.rel_error = 0.0;
-    rec.eps = 0.0;
-    rec.alpha = 0.0;
-    if (!isfinite(rs)) {
-      st->status = -5;
-      st->done = 1;
-    } else if (d.stop_rule == STOP_RESIDUAL && rel <= d.tol) {
-      st->status = 0;
-      st->done = 1;
-    } else if (it >= d.max_iter) {
-      st->status = (d.stop_rule == STOP_NONE) ? 0 : 1;
-      st->done = 1;
-    } else if (emax == 0.0) {
-      st->status = 0;      // G_l = 0: T_l fits every observation
-      st->done = 1;
-    } else {
-      const double epsn = d.eps_fixed > 0.0 ? d.eps_fixed : emax;
-      st->eps_n = epsn;
-      st->alpha_n = (d.step_policy == STEP_THEORY) ? d.step / d.p : d.step / sqrt(epsn);
-      rec.eps = epsn;
-      rec.alpha = st->alpha_n * sqrt(epsn);
-      st->upd = 0;
-      go = 1;
-    }
-    if (it < d.hist_cap) d.hist[it] = rec;
-  }
-  __syncthreads();
-  if (go) {
-    const double inv = 1.0 / st->eps_n;
-    const double ex = 1.0 / (2.0 * m);
-    for (int i = threadIdx.x; i < stot; i += blockDim.x) {
-      d.omega[i] = pow(1.0 + (double)sacc[i] * inv, ex);
-      sacc[i] = (F)0;
-    }
-  }
 }
 
 // One thread per sample.  The right interface vectors rho_k (k = m..2) are
@@ -188,7 +120,11 @@ __global__ void __launch_bounds__(256) k_sampled(Dev d, int diag) {
   __shared__ double sbuf[16];
   const double bs = block_sum(rsq, sbuf);
   if (threadIdx.x == 0) d.part[blockIdx.x] = bs;
-  if (arrive_last(&d.st->counter[C_SAMPLED])) sampled_finish<F>(d, sacc, diag);
+  if (!arrive_last(&d.st->counter[C_SAMPLED])) return;
+  __shared__ double sb2[16];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) v += d.part[i];
+  sampled_finish_total<F>(d, sacc, block_sum(v, sb2), diag);
 }
 
 // Plain evaluation T(x^(j)) for prgd_eval (float64, padded cores).

@@ -1,0 +1,325 @@
+// Sampled pass for order-3 tensors, samples grouped by the middle mode.
+//
+// For x = (x1, x2, x3) the entry is T(x) = l(x1)^T S(x2) r(x3) with
+// l = T_1(0, x1, :), S = T_2(:, x2, :) (r1 x r2) and r = T_3(:, x3, 0)
+// (section 2.1, TT format).  With u = S r and l2 = S^T l, the residual is
+// R = l.u - y and the Euclidean core gradients (chain rule) are
+//   dT_1(x1) += R u,   dT_3(x3) += R l2,   dT_2(x2) += R l r^T,
+// and the squared mode-slice norms s_k(x_k) += R^2 (section 3.2.1).
+//
+// Layout of the work: Omega is stably sorted by x2, so a workgroup that owns a
+// contiguous chunk of samples sees few distinct x2 ("segments") and the
+// middle-core slice S(x2) is uniform across a wave.  Per workgroup:
+//   * the boundary vectors l(.) and r(.) are staged in LDS when they fit;
+//   * dT_1, dT_3, s_1, s_3 are accumulated in LDS (LDS atomics) and written
+//     once as a per-workgroup partial;
+//   * dT_2(x2) = sum over the segment of R l r^T is a rank-K update that the
+//     matrix cores accumulate: 16x16x4 MFMAs whose A/B operands (R_k l_k[c],
+//     r_k[c]) are fetched directly in the MFMA lane layout, so no transpose
+//     is needed; each wave's accumulator is added into a small per-workgroup
+//     segment table in LDS when the segment changes.
+// A second kernel sums the partials in a fixed order (deterministic) and
+// finishes the metric weights.
+#include "prgd_internal.hpp"
+#include "block_ops.hpp"
+#include "sampled_common.hpp"
+
+namespace prgd {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename F>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef d4v acc_t;
+  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of the 16x16 result held in element v of lane l (column l % 16)
+  __device__ static int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct Mma<float> {
+  typedef f4v acc_t;
+  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+__device__ inline double ld_shfl(double v, int src) { return __shfl(v, src, 64); }
+__device__ inline float ld_shfl(float v, int src) { return __shfl(v, src, 64); }
+
+template <typename F, int R, int NT, bool STAGE>
+__global__ void __launch_bounds__(NT) k_sampled3(Dev d, S3 q, const F *__restrict__ cores, const F *__restrict__ bnd,
+                                                 const F *__restrict__ y, int diag) {
+  if (!diag && d.st->done) return;
+  typedef Mma<F> M;
+  constexpr int RR = R * R;
+  constexpr int SEGW = RR + 1;
+  extern __shared__ unsigned char lds_raw[];
+  const int n1 = d.n[0], n3 = d.n[2];
+  const long long N = d.N;
+  F *lY1 = reinterpret_cast<F *>(lds_raw);
+  F *lY3 = lY1 + n1 * R;
+  F *ls1 = lY3 + n3 * R;
+  F *ls3 = ls1 + n1;
+  F *lseg = ls3 + n3;
+  F *lT1 = lseg + KSEG * SEGW;
+  F *lT3 = lT1 + n1 * R;
+  const int L = n1 * R + n3 * R + n1 + n3;
+  for (int i = threadIdx.x; i < L + KSEG * SEGW; i += NT) lY1[i] = (F)0;
+  const F *gT1 = bnd;
+  const F *gT3 = bnd + (long long)n1 * R;
+  if (STAGE)
+    for (int i = threadIdx.x; i < (n1 + n3) * R; i += NT) lT1[i] = bnd[i];
+  const F *T1 = STAGE ? lT1 : gT1;
+  const F *T3 = STAGE ? lT3 : gT3;
+  __syncthreads();
+
+  const long long j0 = (long long)blockIdx.x * q.chunk;
+  const long long j1 = min(N, j0 + q.chunk);
+  const int vfirst = q.vfirst[blockIdx.x];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  const long long per = ((j1 - j0) + NW - 1) / NW;
+  const long long ws = j0 + w * per, we = min(j1, ws + per);
+  const int *ix1 = d.idx, *ix2 = d.idx + N, *ix3 = d.idx + 2 * N;
+  const long long co2 = d.coff[1];
+  F *ovf = (F *)q.ovf;
+
+  typename M::acc_t acc = M::zero();
+  int wv = -1;          // segment accumulated in acc
+  F ws2 = (F)0;         // per-lane sum of R^2 for that segment
+  double rsq = 0.0;
+  const int c = lane & 15;
+
+  auto flush = [&]() {
+    if (wv >= 0) {
+      const int slot = wv - vfirst;
+      const F s2 = (F)wave_sum((double)ws2);
+      F *dst = (slot >= 0 && slot < KSEG) ? lseg + slot * SEGW : nullptr;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = M::row(lane, v);
+        if (i < R && c < R) {
+          if (dst) atomicAdd(&dst[i * R + c], acc[v]);
+          else atomicAdd(&ovf[(long long)wv * SEGW + i * R + c], acc[v]);
+        }
+      }
+      if (lane == 0) {
+        if (dst) atomicAdd(&dst[RR], s2);
+        else atomicAdd(&ovf[(long long)wv * SEGW + RR], s2);
+      }
+    }
+    acc = M::zero();
+    ws2 = (F)0;
+  };
+
+  for (long long jb = ws; jb < we; jb += 64) {
+    const long long j = jb + lane;
+    const bool act = j < we;
+    const int x1 = act ? ix1[j] : 0;
+    const int x2 = act ? ix2[j] : -1;
+    const int x3 = act ? ix3[j] : 0;
+    const F yv = act ? y[j] : (F)0;
+    unsigned long long pending = __ballot(act);
+    while (pending) {
+      const int first = __ffsll((long long)pending) - 1;
+      const int v = __builtin_amdgcn_readlane(x2, first);
+      const bool me = act && (x2 == v);
+      pending &= ~__ballot(me);
+      if (v != wv) {
+        flush();
+        wv = v;
+      }
+      const F *S = cores + co2 + (long long)v * RR;
+      F res = (F)0;
+      if (me) {
+        F l1[R], r3[R], u[R], l2[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+          l1[a] = T1[x1 * R + a];
+          r3[a] = T3[x3 * R + a];
+          u[a] = (F)0;
+          l2[a] = (F)0;
+        }
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+#pragma unroll
+          for (int b = 0; b < R; ++b) {
+            const F sab = S[a * R + b];
+            u[a] = fma(sab, r3[b], u[a]);
+            l2[b] = fma(l1[a], sab, l2[b]);
+          }
+        }
+        F t = (F)0;
+#pragma unroll
+        for (int a = 0; a < R; ++a) t = fma(l1[a], u[a], t);
+        res = t - yv;
+        const F r2 = res * res;
+        rsq += (double)r2;
+        ws2 += r2;
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+          atomicAdd(&lY1[x1 * R + a], res * u[a]);
+          atomicAdd(&lY3[x3 * R + a], res * l2[a]);
+        }
+        atomicAdd(&ls1[x1], r2);
+        atomicAdd(&ls3[x3], r2);
+      }
+      // dT_2(v) += sum_k res_k l1_k r3_k^T over this wave's 64 lanes (zero for others)
+#pragma unroll
+      for (int st = 0; st < 16; ++st) {
+        const int k = 4 * st + (lane >> 4);
+        const F rk = ld_shfl(res, k);
+        const int x1k = __shfl(x1, k, 64);
+        const int x3k = __shfl(x3, k, 64);
+        F av = (F)0, bv = (F)0;
+        if (c < R) {
+          av = rk * T1[x1k * R + c];
+          bv = T3[x3k * R + c];
+        }
+        acc = M::step(av, bv, acc);
+      }
+    }
+  }
+  flush();
+  __shared__ double sbuf[16];
+  const double bs = block_sum(rsq, sbuf);
+  __syncthreads();
+  F *pb = (F *)q.part_bnd + (long long)blockIdx.x * L;
+  for (int i = threadIdx.x; i < L; i += NT) pb[i] = lY1[i];
+  F *ps = (F *)q.part_seg + (long long)blockIdx.x * KSEG * SEGW;
+  for (int i = threadIdx.x; i < KSEG * SEGW; i += NT) ps[i] = lseg[i];
+  if (threadIdx.x == 0) q.part_rsq[blockIdx.x] = bs;
+}
+
+// Deterministic reduction of the per-workgroup partials into the gradient
+// (padded core layout) and the slice sums, then the weight finish.
+// Blocks [0, nbB): 64 boundary outputs each, the 4 waves splitting the
+// workgroup partials; blocks [nbB, grid): middle-core segments, one output
+// per thread (2-3 pieces each).
+template <typename F, int R>
+__global__ void __launch_bounds__(256) k_sampled3_reduce(Dev d, S3 q, int nbB, int diag) {
+  if (!diag && d.st->done) return;
+  constexpr int RR = R * R;
+  constexpr int SEGW = RR + 1;
+  const int n1 = d.n[0], n2 = d.n[1], n3 = d.n[2];
+  const int L = n1 * R + n3 * R + n1 + n3;
+  F *Y = (F *)d.Y;
+  F *s = (F *)d.s;
+  const F *pb = (const F *)q.part_bnd;
+  const F *ps = (const F *)q.part_seg;
+  F *ovf = (F *)q.ovf;
+  __shared__ double red[4][64];
+  if ((int)blockIdx.x < nbB) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + lane;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (o < L) {
+      int b = w;
+      for (; b + 12 < q.nwg; b += 16) {
+        a0 += (double)pb[(long long)b * L + o];
+        a1 += (double)pb[(long long)(b + 4) * L + o];
+        a2 += (double)pb[(long long)(b + 8) * L + o];
+        a3 += (double)pb[(long long)(b + 12) * L + o];
+      }
+      for (; b < q.nwg; b += 4) a0 += (double)pb[(long long)b * L + o];
+    }
+    red[w][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (w == 0 && o < L) {
+      const double acc = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+      const int i = o;
+      if (i < n1 * R) {
+        const int x = i / R, a = i % R;
+        Y[d.coff[0] + (long long)x * RR + a] = (F)acc;          // row 0 of slice x of the first core
+      } else if (i < n1 * R + n3 * R) {
+        const int ii = i - n1 * R, x = ii / R, a = ii % R;
+        Y[d.coff[2] + (long long)x * RR + a * R] = (F)acc;      // column 0 of slice x of the last core
+      } else if (i < n1 * R + n3 * R + n1) {
+        s[d.soff[0] + (i - n1 * R - n3 * R)] = (F)acc;
+      } else {
+        s[d.soff[2] + (i - n1 * R - n3 * R - n1)] = (F)acc;
+      }
+    }
+  } else {
+    const long long tot = (long long)n2 * SEGW;
+    const long long oo = (long long)(blockIdx.x - nbB) * blockDim.x + threadIdx.x;
+    if (oo < tot) {
+      const int v = (int)(oo / SEGW), e = (int)(oo % SEGW);
+      double acc = (double)ovf[oo];
+      ovf[oo] = (F)0;
+      for (int b = q.blo[v]; b <= q.bhi[v]; ++b) {
+        const int slot = v - q.vfirst[b];
+        if (slot >= 0 && slot < KSEG) acc += (double)ps[((long long)b * KSEG + slot) * SEGW + e];
+      }
+      if (e < RR) Y[d.coff[1] + (long long)v * RR + e] = (F)acc;
+      else s[d.soff[1] + v] = (F)acc;
+    }
+  }
+  if (!arrive_last(&d.st->counter[C_SAMPLED])) return;
+  __shared__ double sbuf[16];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < q.nwg; i += blockDim.x) v += q.part_rsq[i];
+  const double rs = block_sum(v, sbuf);
+  sampled_finish_total<F>(d, s, rs, diag);
+}
+
+template <typename F, int R>
+static hipError_t launch3_t(const Dev &d, const S3 &q, int diag, hipStream_t st) {
+  const int n1 = d.n[0], n3 = d.n[2];
+  const size_t base = (size_t)(n1 * R + n3 * R + n1 + n3 + KSEG * (R * R + 1)) * sizeof(F);
+  const size_t lds = base + (q.stage ? (size_t)(n1 + n3) * R * sizeof(F) : 0);
+  const F *cores = (d.prec == PREC_MIXED) ? (const F *)d.cores32 : (const F *)d.cores;
+  const F *y = (d.prec == PREC_MIXED) ? (const F *)d.y32 : (const F *)d.y64;
+  const F *bnd = (const F *)d.bnd;
+  constexpr int NT = (sizeof(F) == 8 && R >= 10) ? 512 : 1024;
+  if (q.stage)
+    hipLaunchKernelGGL((k_sampled3<F, R, NT, true>), dim3(q.nwg), dim3(NT), lds, st, d, q, cores, bnd, y, diag);
+  else
+    hipLaunchKernelGGL((k_sampled3<F, R, NT, false>), dim3(q.nwg), dim3(NT), lds, st, d, q, cores, bnd, y, diag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int L = n1 * R + n3 * R + n1 + n3;
+  const int nbB = (L + 63) / 64;
+  const long long nbS = ((long long)d.n[1] * (R * R + 1) + 255) / 256;
+  hipLaunchKernelGGL((k_sampled3_reduce<F, R>), dim3((int)(nbB + nbS)), dim3(256), 0, st, d, q, nbB, diag);
+  return hipGetLastError();
+}
+
+template <typename F>
+static hipError_t launch3_f(const Dev &d, const S3 &q, int diag, hipStream_t st) {
+  switch (d.R) {
+    case 2: return launch3_t<F, 2>(d, q, diag, st);
+    case 4: return launch3_t<F, 4>(d, q, diag, st);
+    case 6: return launch3_t<F, 6>(d, q, diag, st);
+    case 8: return launch3_t<F, 8>(d, q, diag, st);
+    case 10: return launch3_t<F, 10>(d, q, diag, st);
+    case 12: return launch3_t<F, 12>(d, q, diag, st);
+    case 16: return launch3_t<F, 16>(d, q, diag, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// LDS bytes the order-3 pass needs (without / with staged boundary vectors)
+size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage) {
+  const size_t f = prec == PREC_MIXED ? 4 : 8;
+  size_t b = (size_t)(n1 * R + n3 * R + n1 + n3 + KSEG * (R * R + 1)) * f;
+  if (stage) b += (size_t)(n1 + n3) * R * f;
+  return b;
+}
+
+int sampled3_kseg() { return KSEG; }
+
+hipError_t launch_sampled3(const Dev &d, const S3 &q, int diag, hipStream_t st) {
+  if (d.prec == PREC_MIXED) return launch3_f<float>(d, q, diag, st);
+  return launch3_f<double>(d, q, diag, st);
+}
+
+}  // namespace prgd

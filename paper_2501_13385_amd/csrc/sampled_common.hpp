@@ -1,0 +1,74 @@
+// Finish of the sampled pass, shared by its variants (runs in one block).
+#pragma once
+
+#include "prgd_internal.hpp"
+#include "block_ops.hpp"
+
+namespace prgd {
+
+// Finish the pass in the last block: total ||R||^2, residual stopping test,
+// eps_l = max_{k,x} s_k(x) (= ||G_l||_vee^2), metric factors
+// omega_k(x) = (1 + s_k(x)/eps)^{1/(2m)} and the normalised step.
+template <typename F>
+__device__ void sampled_finish_total(const Dev &d, F *sacc, double rs, int diag) {
+  __shared__ double sbuf[16];
+  State *st = d.st;
+  if (diag) {
+    if (threadIdx.x == 0) st->res_sq = rs;
+    return;
+  }
+  const int m = d.m;
+  const int stot = d.soff[m];
+  double emax = 0.0;
+  for (int i = threadIdx.x; i < stot; i += blockDim.x) emax = fmax(emax, (double)sacc[i]);
+  emax = block_max(emax, sbuf);
+  __shared__ int go;
+  if (threadIdx.x == 0) {
+    go = 0;
+    st->res_sq = rs;
+    const double rel = st->y_sq > 0.0 ? sqrt(rs / st->y_sq) : sqrt(rs);
+    st->rel_res = rel;
+    const int it = st->iter;
+    IterRecord rec;
+    rec.iter = it;
+    rec.flags = 0;
+    rec.rel_residual = rel;
+    rec.rel_change = 0.0;
+    rec.rel_error = 0.0;
+    rec.eps = 0.0;
+    rec.alpha = 0.0;
+    if (!isfinite(rs)) {
+      st->status = -5;
+      st->done = 1;
+    } else if (d.stop_rule == STOP_RESIDUAL && rel <= d.tol) {
+      st->status = 0;
+      st->done = 1;
+    } else if (it >= d.max_iter) {
+      st->status = (d.stop_rule == STOP_NONE) ? 0 : 1;
+      st->done = 1;
+    } else if (emax == 0.0) {
+      st->status = 0;      // G_l = 0: T_l fits every observation
+      st->done = 1;
+    } else {
+      const double epsn = d.eps_fixed > 0.0 ? d.eps_fixed : emax;
+      st->eps_n = epsn;
+      st->alpha_n = (d.step_policy == STEP_THEORY) ? d.step / d.p : d.step / sqrt(epsn);
+      rec.eps = epsn;
+      rec.alpha = st->alpha_n * sqrt(epsn);
+      st->upd = 0;
+      go = 1;
+    }
+    if (it < d.hist_cap) d.hist[it] = rec;
+  }
+  __syncthreads();
+  if (go) {
+    const double inv = 1.0 / st->eps_n;
+    const double ex = 1.0 / (2.0 * m);
+    for (int i = threadIdx.x; i < stot; i += blockDim.x) {
+      d.omega[i] = pow(1.0 + (double)sacc[i] * inv, ex);
+      sacc[i] = (F)0;
+    }
+  }
+}
+
+}  // namespace prgd

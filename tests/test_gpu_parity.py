@@ -46,7 +46,8 @@ def ragged_problem(seed=3):
     return wl.problem(shape, ranks, 1500, seed, name="ragged", truth_kind="gaussian", init_rel=0.1)
 
 
-SAMPLED_CASES = ["c1", "c2_small", "ragged", "order2", "order6"]
+SAMPLED_CASES = ["c1", "c2_small", "ragged", "order2", "order6", "o3_many_segments", "o3_unstaged",
+                 "o3_empty_segments", "o3_rank16"]
 
 
 def make_case(name):
@@ -54,6 +55,14 @@ def make_case(name):
         return ragged_problem()
     if name == "order2":
         return wl.problem([37, 29], [1, 3, 1], 400, 5, name="order2", init_rel=0.2)
+    if name == "o3_many_segments":     # order 3: chunks span more middle-mode slices than table slots
+        return wl.problem([20, 2000, 30], [1, 3, 3, 1], 3000, 7, name=name, init_rel=0.1)
+    if name == "o3_unstaged":          # order 3: boundary vectors too large to stage in LDS
+        return wl.problem([1500, 7, 1500], [1, 4, 4, 1], 20000, 8, name=name, init_rel=0.1)
+    if name == "o3_empty_segments":    # order 3: most middle-mode slices unobserved
+        return wl.problem([9, 300, 11], [1, 2, 2, 1], 200, 9, name=name, init_rel=0.1)
+    if name == "o3_rank16":            # order 3: largest supported rank, several tiles and a ragged tail
+        return wl.problem([33, 47, 29], [1, 16, 16, 1], 30001, 10, name=name, init_rel=0.1)
     if name == "order6":
         shape = [3, 4, 3, 5, 3, 4]
         return wl.problem(shape, wl.feasible_ranks(shape, 4), 1200, 6, name="order6", init_rel=0.1)
@@ -82,7 +91,7 @@ def test_sampled_pass_fp64_matches_reference(L, name):
         np.testing.assert_allclose(ssq[k], ref_s[k], rtol=1e-12, atol=1e-14 * ref_s[k].max())
 
 
-@pytest.mark.parametrize("name", ["c1", "c2_small"])
+@pytest.mark.parametrize("name", ["c1", "c2_small", "o3_many_segments", "o3_unstaged", "o3_rank16"])
 def test_sampled_pass_mixed_matches_reference(L, name):
     pb = make_case(name)
     y = observed(pb)
@@ -107,7 +116,8 @@ def test_eval_matches_reference(L):
 
 
 @pytest.mark.parametrize("name,c,iters", [("c1", 1.001, 25), ("c2_small", 0.8, 12), ("ragged", 0.8, 10),
-                                          ("order2", 0.8, 10), ("order6", 0.8, 8)])
+                                          ("order2", 0.8, 10), ("order6", 0.8, 8), ("o3_many_segments", 0.5, 5),
+                                          ("o3_rank16", 0.8, 5)])
 def test_fp64_iterates_match_reference_each_iteration(L, name, c, iters):
     pb = make_case(name)
     say("case", name, "iters", iters)
