@@ -53,17 +53,15 @@ __device__ inline void reduce_partials(const double *part, int nb, int ne, doubl
   if (ne <= nt) {
     const int G = nt / ne;                 // groups per entry
     const int g = t / ne, e = t % ne;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (g < G) {
       int b = g;
-      for (; b + 3 * G < nb; b += 4 * G) {
-        a0 += part[(long long)b * ne + e];
-        a1 += part[(long long)(b + G) * ne + e];
-        a2 += part[(long long)(b + 2 * G) * ne + e];
-        a3 += part[(long long)(b + 3 * G) * ne + e];
+      for (; b + 7 * G < nb; b += 8 * G) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += part[(long long)(b + u * G) * ne + e];
       }
-      for (; b < nb; b += G) a0 += part[(long long)b * ne + e];
-      scratch[g * ne + e] = (a0 + a1) + (a2 + a3);
+      for (; b < nb; b += G) a[0] += part[(long long)b * ne + e];
+      scratch[g * ne + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
     __syncthreads();
     for (int i = t; i < ne; i += nt) {

@@ -35,6 +35,7 @@
 // P_{m-1} C_{m-1}.
 #include "prgd_internal.hpp"
 #include "block_ops.hpp"
+#include "small_la.hpp"
 
 namespace prgd {
 
@@ -79,207 +80,6 @@ __device__ inline void block_core(const Dev &d, int &c, int &x0, int &x1) {
 // ---------------------------------------------------------------------------
 // small dense linear algebra on LDS (block-cooperative; callers sync around)
 // ---------------------------------------------------------------------------
-
-// inverse of the SPD leading n x n block of A (row-major, leading dim ld) via
-// Cholesky; writes Ainv (ld) with zeros outside the block.  Returns false if
-// a pivot is not positive.  scratch: 2*n*n doubles.
-__device__ bool spd_inverse(const double *A, int ld, int n, double *Ainv, int R, double *scratch) {
-  __shared__ int fail;
-  double *L = scratch, *Li = scratch + n * n;
-  if (threadIdx.x == 0) fail = 0;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e % n;
-    L[e] = (j <= i) ? A[i * ld + j] : 0.0;
-  }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      const double dk = L[k * n + k];
-      if (!(dk > 0.0) || !isfinite(dk)) fail = 1;
-      else L[k * n + k] = sqrt(dk);
-    }
-    __syncthreads();
-    if (fail) return false;
-    const double piv = L[k * n + k];
-    for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) L[i * n + k] /= piv;
-    __syncthreads();
-    const int rem = n - k - 1;
-    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (j <= i) L[i * n + j] -= L[i * n + k] * L[j * n + k];
-    }
-    __syncthreads();
-  }
-  // Li = L^{-1} (lower), one column per thread
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    for (int i = 0; i < n; ++i) {
-      double v = (i == j) ? 1.0 : 0.0;
-      if (i < j) {
-        Li[i * n + j] = 0.0;
-        continue;
-      }
-      for (int k = j; k < i; ++k) v -= L[i * n + k] * Li[k * n + j];
-      Li[i * n + j] = v / L[i * n + i];
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < R * R; e += blockDim.x) {
-    const int i = e / R, j = e % R;
-    double v = 0.0;
-    if (i < n && j < n)
-      for (int k = (i > j ? i : j); k < n; ++k) v += Li[k * n + i] * Li[k * n + j];
-    Ainv[i * R + j] = v;
-  }
-  __syncthreads();
-  return true;
-}
-
-// Pivoted Cholesky of a symmetric positive semidefinite n x n matrix A
-// (dense, leading dim n; destroyed): F (n x n, row-major) gets columns
-// 0..rank-1 with F F^T = A up to pivots below n * 2.3e-16 * max diag.
-__device__ int pivoted_cholesky(double *A, int n, double *F, int *used) {
-  __shared__ int piv, stop, rank;
-  __shared__ double pvs, tol;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) F[e] = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) used[i] = 0;
-  if (threadIdx.x == 0) {
-    double dm = 0.0;
-    for (int i = 0; i < n; ++i) dm = fmax(dm, A[i * n + i]);
-    tol = (double)n * 2.3e-16 * dm;
-    rank = 0;
-  }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      int p = -1;
-      double best = 0.0;
-      for (int i = 0; i < n; ++i)
-        if (!used[i] && A[i * n + i] > best) {
-          best = A[i * n + i];
-          p = i;
-        }
-      stop = (p < 0 || !(best > tol)) ? 1 : 0;
-      if (!stop) {
-        piv = p;
-        used[p] = 1;
-        pvs = sqrt(best);
-        rank = k + 1;
-      }
-    }
-    __syncthreads();
-    if (stop) break;
-    const int p = piv;
-    const double pv = pvs;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const double f = (used[i] && i != p) ? 0.0 : A[i * n + p] / pv;
-      F[i * n + k] = f;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int i = e / n, j = e % n;
-      A[e] -= F[i * n + k] * F[j * n + k];
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  return rank;
-}
-
-// Cyclic Jacobi for a symmetric n x n matrix A (dense, ld n, destroyed), n <= 32,
-// round-robin ordering (n/2 disjoint rotations per round).  On exit w[0..n) are
-// the eigenvalues in descending order and V (ld n) holds the eigenvectors as columns.
-__device__ void jacobi_eig(double *A, int n, double *V, double *w, double *Vs, double *cs) {
-  __shared__ double sbuf[16];
-  __shared__ int goon;
-  const int ne = n + (n & 1);
-  const int np = ne / 2;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const double v = A[e];
-      if (e / n == e % n) dia += v * v;
-      else off += v * v;
-    }
-    off = block_sum(off, sbuf);
-    dia = block_sum(dia, sbuf);
-    if (threadIdx.x == 0) goon = (off > 1e-32 * (dia + off)) ? 1 : 0;
-    __syncthreads();
-    if (!goon) break;
-    for (int rd = 0; rd < ne - 1; ++rd) {
-      for (int k = threadIdx.x; k < np; k += blockDim.x) {
-        int p, q;
-        if (k == 0) {
-          p = ne - 1;
-          q = rd;
-        } else {
-          p = (rd + k) % (ne - 1);
-          q = (rd - k + ne - 1) % (ne - 1);
-        }
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[p * n + q];
-          if (apq != 0.0) {
-            const double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
-        }
-        cs[4 * k + 0] = c;
-        cs[4 * k + 1] = s;
-        cs[4 * k + 2] = (double)p;
-        cs[4 * k + 3] = (double)q;
-      }
-      __syncthreads();
-      // A <- A J, V <- V J (columns p, q)
-      for (int e = threadIdx.x; e < n * np; e += blockDim.x) {
-        const int i = e / np, k = e % np;
-        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
-        if (q >= n) continue;
-        const double c = cs[4 * k], s = cs[4 * k + 1];
-        const double ap = A[i * n + p], aq = A[i * n + q];
-        A[i * n + p] = c * ap - s * aq;
-        A[i * n + q] = s * ap + c * aq;
-        const double vp = V[i * n + p], vq = V[i * n + q];
-        V[i * n + p] = c * vp - s * vq;
-        V[i * n + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-      // A <- J^T A (rows p, q)
-      for (int e = threadIdx.x; e < n * np; e += blockDim.x) {
-        const int k = e / n, j = e % n;
-        const int p = (int)cs[4 * k + 2], q = (int)cs[4 * k + 3];
-        if (q >= n) continue;
-        const double c = cs[4 * k], s = cs[4 * k + 1];
-        const double ap = A[p * n + j], aq = A[q * n + j];
-        A[p * n + j] = c * ap - s * aq;
-        A[q * n + j] = s * ap + c * aq;
-      }
-      __syncthreads();
-    }
-  }
-  // sort descending (stable by index)
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double wi = A[i * n + i];
-    int rk = 0;
-    for (int j = 0; j < n; ++j) {
-      const double wj = A[j * n + j];
-      if (wj > wi || (wj == wi && j < i)) ++rk;
-    }
-    w[rk] = wi;
-    for (int r = 0; r < n; ++r) Vs[r * n + rk] = V[r * n + i];
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) V[e] = Vs[e];
-  __syncthreads();
-}
 
 // ---------------------------------------------------------------------------
 // weighted Gram sweeps (one launch per step j = 1..m-1)
@@ -368,7 +168,14 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, int j, int nbL) {
     mypart[t] = a0;
     mypart[RR + t] = a1;
   }
-  if (!arrive_last(&d.st->counter[C_GRAM])) return;
+}
+
+// finish of a Gram sweep step (one block): totals, inverses, and after the
+// last step the products Psi_c
+__global__ void __launch_bounds__(1024) k_gram_fin(Dev d, int j, int nbL, int nbT) {
+  if (d.st->done) return;
+  __shared__ double smem[SMEM];
+  const int R = d.R, RR = R * R, m = d.m;
 
   // last block: totals, inverses
   double *GLj = sm_slot(d, j, S_GL), *THc = sm_slot(d, j - 1, S_TH), *Hb = sm_slot(d, m - j, S_H);
@@ -380,7 +187,7 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, int j, int nbL) {
       THc[t] = tot[RR + t];
     }
     __syncthreads();
-    reduce_partials(d.part + (long long)nbL * 2 * RR, (int)gridDim.x - nbL, 2 * RR, tot, smem);
+    reduce_partials(d.part + (long long)nbL * 2 * RR, nbT - nbL, 2 * RR, tot, smem);
     for (int t = threadIdx.x; t < RR; t += blockDim.x) Hb[t] = tot[t];
   }
   __threadfence_block();
@@ -388,9 +195,9 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, int j, int nbL) {
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  if (!spd_inverse(GLj, R, d.r[j], sm_slot(d, j, S_GLI), R, smem)) bad = 1;
-  __syncthreads();
-  if (!spd_inverse(Hb, R, d.r[m - j], sm_slot(d, m - j, S_HI), R, smem)) bad = 1;
+  const bool ok1 = block_spd_inverse(GLj, R, d.r[j], sm_slot(d, j, S_GLI), R, R, smem);
+  const bool ok2 = block_spd_inverse(Hb, R, d.r[m - j], sm_slot(d, m - j, S_HI), R, R, smem);
+  if (threadIdx.x == 0 && !(ok1 && ok2)) bad = 1;
   __syncthreads();
   if (bad) {
     if (threadIdx.x == 0) {
@@ -558,7 +365,13 @@ __global__ void __launch_bounds__(256) k_rgram(Dev d, int b) {
     for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
     mypart[t] = v;
   }
-  if (!arrive_last(&d.st->counter[C_GR])) return;
+}
+
+// finish of a right-Gram step (one block): total GR_b and its pivoted Cholesky factor
+__global__ void __launch_bounds__(1024) k_rgram_fin(Dev d, int b, int nb) {
+  if (d.st->done) return;
+  __shared__ double smem[SMEM];
+  const int R = d.R, R2 = 2 * R, NE = R2 * R2;
 
   double *GR = sm_slot(d, b, S_GR);
   {
@@ -572,14 +385,13 @@ __global__ void __launch_bounds__(256) k_rgram(Dev d, int b) {
   // compress to the active indices [0, r_b) U [R, R + r_b)
   const int rb = d.r[b], na = 2 * rb;
   double *A = smem, *Fc = smem + 1024;
-  int *used = (int *)(smem + 2048);
   for (int t = threadIdx.x; t < na * na; t += blockDim.x) {
     const int i = t / na, jj = t % na;
     const int gi = i < rb ? i : R + i - rb, gj = jj < rb ? jj : R + jj - rb;
     A[t] = smem[3072 + gi * R2 + gj];
   }
   __syncthreads();
-  const int rank = pivoted_cholesky(A, na, Fc, used);
+  const int rank = block_pivoted_cholesky(A, na, Fc);
   double *F = sm_slot(d, b, S_F);
   for (int t = threadIdx.x; t < NE; t += blockDim.x) {
     const int gi = t / R2, col = t % R2;
@@ -655,7 +467,14 @@ __global__ void __launch_bounds__(256) k_left(Dev d, int i) {
     for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
     mypart[t] = v;
   }
-  if (!arrive_last(&d.st->counter[C_LEFT])) return;
+}
+
+// finish of a left-sweep cut (one block): S = F^T (B^T B) F, eigen-decomposition,
+// truncation to r_i: Tr_i and P_i
+__global__ void __launch_bounds__(1024) k_left_fin(Dev d, int i, int nb) {
+  if (d.st->done) return;
+  __shared__ double smem[SMEM];
+  const int R = d.R, R2 = 2 * R, NE = R2 * R2;
 
   // last block: S = F^T GB F, eigen-decomposition, truncation to r_i
   double *GB = smem;                 // NE
@@ -706,7 +525,7 @@ __global__ void __launch_bounds__(256) k_left(Dev d, int i) {
     }
   }
   __syncthreads();
-  jacobi_eig(S, rk, V, w, Vs, cs);
+  block_jacobi_eig(S, rk, V, w, Vs, cs);
   if (threadIdx.x == 0) {
     const double s0 = w[0];
     if (!(w[ri - 1] > 1e-28 * s0) || !isfinite(s0)) bad = 1;
@@ -834,9 +653,14 @@ __global__ void __launch_bounds__(256) k_output(Dev d, int init) {
     d.part[2 * blockIdx.x] = nn;
     d.part[2 * blockIdx.x + 1] = cr;
   }
-  if (!arrive_last(&d.st->counter[C_OUT])) return;
+}
+
+// finish of the output step (one block): relative change, iteration count, stop test
+__global__ void __launch_bounds__(1024) k_output_fin(Dev d, int init, int nb) {
+  if (d.st->done) return;
+  __shared__ double sbuf[16];
   double a0 = 0.0, a1 = 0.0;
-  for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) {
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
     a0 += d.part[2 * k];
     a1 += d.part[2 * k + 1];
   }
@@ -920,7 +744,13 @@ __global__ void __launch_bounds__(256) k_cross(Dev d, int c, int mode) {
     for (int g = 0; g < q.G; ++g) v += red[g * RR + t];
     mypart[t] = v;
   }
-  if (!arrive_last(&d.st->counter[C_TRUTH])) return;
+}
+
+// finish of a cross-Gram step (one block)
+__global__ void __launch_bounds__(1024) k_cross_fin(Dev d, int c, int mode, int nb) {
+  if (mode == 0 && !d.st->upd) return;
+  __shared__ double smem[SMEM];
+  const int R = d.R, RR = R * R, m = d.m;
   double *Zn = sm_slot(d, c + 1, S_ZT);
   reduce_partials(d.part, nb, RR, smem + 1024, smem);
   for (int t = threadIdx.x; t < RR; t += blockDim.x) Zn[t] = smem[1024 + t];
@@ -951,10 +781,13 @@ __global__ void __launch_bounds__(256) k_cross(Dev d, int c, int mode) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// blocks for a slice-parallel reduction kernel over n slices: at least `target`
+// slices per block and at most 128 blocks, so the finishing block reads few partials
 static int nblocks_for(int n, int target) {
-  int nb = (n + target - 1) / target;
+  int per = (n + 127) / 128;
+  if (per < target) per = target;
+  int nb = (n + per - 1) / per;
   if (nb < 1) nb = 1;
-  if (nb > 256) nb = 256;
   return nb;
 }
 
@@ -964,6 +797,7 @@ hipError_t launch_project(const Dev &d, hipStream_t s) {
   for (int j = 1; j <= m - 1; ++j) {
     const int nbL = nblocks_for(d.n[j - 1], 4), nbH = nblocks_for(d.n[m - j], 4);
     hipLaunchKernelGGL(k_gram, dim3(nbL + nbH), dim3(256), 0, s, d, j, nbL);
+    hipLaunchKernelGGL(k_gram_fin, dim3(1), dim3(1024), 0, s, d, j, nbL, nbL + nbH);
   }
   hipLaunchKernelGGL(k_tangent, dim3(d.blk_off[m]), dim3(256), 0, s, d);
   return hipGetLastError();
@@ -972,14 +806,23 @@ hipError_t launch_project(const Dev &d, hipStream_t s) {
 // phase 2: retraction sweeps (right Grams of W_l, then the truncated left sweep)
 hipError_t launch_retract(const Dev &d, hipStream_t s) {
   const int m = d.m;
-  for (int b = m - 1; b >= 1; --b) hipLaunchKernelGGL(k_rgram, dim3(nblocks_for(d.n[b], 4)), dim3(256), 0, s, d, b);
-  for (int i = 1; i <= m - 1; ++i) hipLaunchKernelGGL(k_left, dim3(nblocks_for(d.n[i - 1], 4)), dim3(256), 0, s, d, i);
+  for (int b = m - 1; b >= 1; --b) {
+    const int nb = nblocks_for(d.n[b], 4);
+    hipLaunchKernelGGL(k_rgram, dim3(nb), dim3(256), 0, s, d, b);
+    hipLaunchKernelGGL(k_rgram_fin, dim3(1), dim3(1024), 0, s, d, b, nb);
+  }
+  for (int i = 1; i <= m - 1; ++i) {
+    const int nb = nblocks_for(d.n[i - 1], 4);
+    hipLaunchKernelGGL(k_left, dim3(nb), dim3(256), 0, s, d, i);
+    hipLaunchKernelGGL(k_left_fin, dim3(1), dim3(1024), 0, s, d, i, nb);
+  }
   return hipGetLastError();
 }
 
 // phase 3: new cores and the stopping-test reductions
 hipError_t launch_output(const Dev &d, hipStream_t s, int init) {
   hipLaunchKernelGGL(k_output, dim3(d.blk_off[d.m]), dim3(256), 0, s, d, init);
+  hipLaunchKernelGGL(k_output_fin, dim3(1), dim3(1024), 0, s, d, init, d.blk_off[d.m]);
   return hipGetLastError();
 }
 
@@ -991,7 +834,11 @@ hipError_t launch_dense_iteration(const Dev &d, hipStream_t s, int init) {
 }
 
 hipError_t launch_truth_sweep(const Dev &d, hipStream_t s, int mode) {
-  for (int c = 0; c < d.m; ++c) hipLaunchKernelGGL(k_cross, dim3(nblocks_for(d.n[c], 4)), dim3(256), 0, s, d, c, mode);
+  for (int c = 0; c < d.m; ++c) {
+    const int nb = nblocks_for(d.n[c], 4);
+    hipLaunchKernelGGL(k_cross, dim3(nb), dim3(256), 0, s, d, c, mode);
+    hipLaunchKernelGGL(k_cross_fin, dim3(1), dim3(1024), 0, s, d, c, mode, nb);
+  }
   return hipGetLastError();
 }
 

@@ -120,11 +120,25 @@ __global__ void __launch_bounds__(256) k_sampled(Dev d, int diag) {
   __shared__ double sbuf[16];
   const double bs = block_sum(rsq, sbuf);
   if (threadIdx.x == 0) d.part[blockIdx.x] = bs;
-  if (!arrive_last(&d.st->counter[C_SAMPLED])) return;
-  __shared__ double sb2[16];
+}
+
+// finish of the sampled pass (one block): total ||R||^2 from the per-block
+// partials, then the weights and the residual stopping test
+template <typename F>
+__global__ void __launch_bounds__(256) k_sampled_fin(Dev d, const double *rsq_part, int nb, int diag) {
+  if (!diag && d.st->done) return;
+  __shared__ double sbuf[16];
   double v = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) v += d.part[i];
-  sampled_finish_total<F>(d, sacc, block_sum(v, sb2), diag);
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += rsq_part[i];
+  sampled_finish_total<F>(d, (F *)d.s, block_sum(v, sbuf), diag);
+}
+
+hipError_t launch_sampled_fin(const Dev &d, const double *rsq_part, int nb, int diag, hipStream_t s) {
+  if (d.prec == PREC_MIXED)
+    hipLaunchKernelGGL(k_sampled_fin<float>, dim3(1), dim3(256), 0, s, d, rsq_part, nb, diag);
+  else
+    hipLaunchKernelGGL(k_sampled_fin<double>, dim3(1), dim3(256), 0, s, d, rsq_part, nb, diag);
+  return hipGetLastError();
 }
 
 // Plain evaluation T(x^(j)) for prgd_eval (float64, padded cores).
@@ -163,6 +177,8 @@ __global__ void __launch_bounds__(256) k_eval(int m, long long N, const int *__r
 // host-side launchers
 // ---------------------------------------------------------------------------
 
+hipError_t launch_sampled_fin(const Dev &d, const double *rsq_part, int nb, int diag, hipStream_t s);
+
 static int lds_block(int m, int R, int elem) {
   // choose the largest block (multiple of 64, <= 256) whose interface stack fits 63 KiB
   const long long per = (long long)(m - 1) * R * elem;
@@ -177,7 +193,9 @@ static hipError_t launch_sampled_t(const Dev &d, int diag, int nblocks, hipStrea
   if (B == 0) return hipErrorInvalidValue;
   const size_t lds = (size_t)(d.m - 1) * R * sizeof(F) * B;
   hipLaunchKernelGGL((k_sampled<F, R>), dim3(nblocks), dim3(B), lds, s, d, diag);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sampled_fin(d, d.part, nblocks, diag, s);
 }
 
 template <typename F>

@@ -22,7 +22,6 @@
 // finishes the metric weights.
 #include "prgd_internal.hpp"
 #include "block_ops.hpp"
-#include "sampled_common.hpp"
 
 namespace prgd {
 
@@ -263,13 +262,9 @@ __global__ void __launch_bounds__(256) k_sampled3_reduce(Dev d, S3 q, int nbB, i
       else s[d.soff[1] + v] = (F)acc;
     }
   }
-  if (!arrive_last(&d.st->counter[C_SAMPLED])) return;
-  __shared__ double sbuf[16];
-  double v = 0.0;
-  for (int i = threadIdx.x; i < q.nwg; i += blockDim.x) v += q.part_rsq[i];
-  const double rs = block_sum(v, sbuf);
-  sampled_finish_total<F>(d, s, rs, diag);
 }
+
+hipError_t launch_sampled_fin(const Dev &d, const double *rsq_part, int nb, int diag, hipStream_t s);
 
 template <typename F, int R>
 static hipError_t launch3_t(const Dev &d, const S3 &q, int diag, hipStream_t st) {
@@ -290,7 +285,9 @@ static hipError_t launch3_t(const Dev &d, const S3 &q, int diag, hipStream_t st)
   const int nbB = (L + 63) / 64;
   const long long nbS = ((long long)d.n[1] * (R * R + 1) + 255) / 256;
   hipLaunchKernelGGL((k_sampled3_reduce<F, R>), dim3((int)(nbB + nbS)), dim3(256), 0, st, d, q, nbB, diag);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sampled_fin(d, q.part_rsq, q.nwg, diag, st);
 }
 
 template <typename F>
