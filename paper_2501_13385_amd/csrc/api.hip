@@ -15,22 +15,22 @@
 #include "prgd_internal.hpp"
 
 namespace prgd {
-hipError_t launch_sampled(const Dev &d, int diag, int nblocks, hipStream_t s);
+hipError_t launch_sampled(const Batch &bt, int diag, hipStream_t s);
 int sampled_block_size(int m, int R, int prec);
 hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *cores, const long long *coff_dev,
                        double *out, hipStream_t s);
-hipError_t launch_dense_iteration(const Dev &d, hipStream_t s, int init);
-hipError_t launch_project(const Dev &d, hipStream_t s);
-hipError_t launch_retract(const Dev &d, hipStream_t s);
-hipError_t launch_output(const Dev &d, hipStream_t s, int init);
-hipError_t launch_truth_sweep(const Dev &d, hipStream_t s, int mode);
+hipError_t launch_dense_iteration(const Batch &bt, hipStream_t s, int init);
+hipError_t launch_project(const Batch &bt, hipStream_t s);
+hipError_t launch_retract(const Batch &bt, hipStream_t s);
+hipError_t launch_output(const Batch &bt, hipStream_t s, int init);
+hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode);
 hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *idx_in, const void *values_in,
                          int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s);
 hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t s);
 hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream_t s);
 size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage);
-hipError_t launch_sampled3(const Dev &d, const S3 &q, int diag, hipStream_t st);
+hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st);
 }  // namespace prgd
 
 using namespace prgd;
@@ -101,9 +101,7 @@ struct prgd_solver_s {
   std::vector<long long> coff;
   long long N = 0;
   int64_t numel = 0;
-  int sampled_blocks = 0;
-  bool use3 = false;     // order-3 grouped sampled pass
-  S3 q3{};
+  Dev *d_dev = nullptr;  // device copy of d (constant after create)
   bool has_truth = false;
   std::vector<void *> allocs;
   double last_seconds = 0.0;
@@ -112,6 +110,14 @@ struct prgd_solver_s {
     if (stream) hipStreamSynchronize(stream);
     for (void *p : allocs) hipFree(p);
     if (own_stream && stream) hipStreamDestroy(stream);
+  }
+  Batch batch() const { return Batch{d_dev, &d, 1}; }
+  void release(void *p) {
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) {
+      hipFree(p);
+      allocs.erase(it);
+    }
   }
   template <typename T>
   hipError_t alloc(T **p, long long count) {
@@ -201,15 +207,15 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
 }
 
 hipError_t sampled_pass(prgd_solver s, int diag) {
-  if (s->use3) return launch_sampled3(s->d, s->q3, diag, s->stream);
-  return launch_sampled(s->d, diag, s->sampled_blocks, s->stream);
+  if (s->d.use3) return launch_sampled3(s->batch(), diag, s->stream);
+  return launch_sampled(s->batch(), diag, s->stream);
 }
 
 prgd_status enqueue_iterations(prgd_solver s, int iters) {
   for (int it = 0; it < iters; ++it) {
     HIPCHECK(sampled_pass(s, 0));
-    HIPCHECK(launch_dense_iteration(s->d, s->stream, 0));
-    if (s->has_truth) HIPCHECK(launch_truth_sweep(s->d, s->stream, 0));
+    HIPCHECK(launch_dense_iteration(s->batch(), s->stream, 0));
+    if (s->has_truth) HIPCHECK(launch_truth_sweep(s->batch(), s->stream, 0));
   }
   return PRGD_OK;
 }
@@ -446,7 +452,7 @@ prgd_status prgd_create(const prgd_desc *ds, prgd_solver *out) {
   }
   // order-3 grouped sampled pass: per-workgroup chunks of the samples sorted by the middle mode
   if (m == 3 && sm == 1 && sampled3_lds_bytes(s->n[0], s->n[2], R, d.prec, 0) <= 163840) {
-    S3 &q = s->q3;
+    S3 &q = d.q3;
     q.stage = sampled3_lds_bytes(s->n[0], s->n[2], R, d.prec, 1) <= 163840 ? 1 : 0;
     long long nwg = std::min<long long>(256, std::max<long long>(1, (N + 63) / 64));
     q.chunk = (N + nwg - 1) / nwg;
@@ -492,27 +498,31 @@ prgd_status prgd_create(const prgd_desc *ds, prgd_solver *out) {
     q.part_bnd = pbnd;
     q.part_seg = pseg;
     q.ovf = povf;
-    s->use3 = true;
+    d.use3 = 1;
   }
   // sampled-pass grid: enough waves to fill 256 CUs
   {
     const int B = sampled_block_size(m, R, d.prec);
     long long nb = (N + B - 1) / B;
     nb = std::min<long long>(nb, 2048);
-    s->sampled_blocks = (int)std::max<long long>(nb, 1);
+    d.nb_sampled = (int)std::max<long long>(nb, 1);
   }
+  if (!A(s->alloc(&s->d_dev, 1))) return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+  if (hipMemcpyAsync(s->d_dev, &d, sizeof(Dev), hipMemcpyHostToDevice, s->stream) != hipSuccess)
+    return cleanup(fail(PRGD_EDEVICE, "descriptor upload failed"));
   // left-orthogonalise T_0 (TT-SVD to its own ranks with a zero direction) and
   // measure ||T_0||, ||T*||
-  if (launch_dense_iteration(d, s->stream, 1) != hipSuccess) return cleanup(fail(PRGD_EDEVICE, "init launch failed"));
-  if (s->has_truth && launch_truth_sweep(d, s->stream, 1) != hipSuccess)
+  if (launch_dense_iteration(s->batch(), s->stream, 1) != hipSuccess) return cleanup(fail(PRGD_EDEVICE, "init launch failed"));
+  if (s->has_truth && launch_truth_sweep(s->batch(), s->stream, 1) != hipSuccess)
     return cleanup(fail(PRGD_EDEVICE, "truth norm launch failed"));
   if (mixed && convert_f64_f32(d.cores, d.cores32, pn, s->stream) != hipSuccess)
     return cleanup(fail(PRGD_EDEVICE, "convert failed"));
   State st;
   if (read_state(s, st) != PRGD_OK) return cleanup(PRGD_EDEVICE);
   if (st.status < 0) return cleanup(fail(PRGD_EBREAKDOWN, "left-orthogonalisation of init_cores broke down"));
-  if (idx_raw) {   // free the unsorted copies
-    hipStreamSynchronize(s->stream);
+  if (idx_raw) {   // the unsorted copies are no longer needed (read_state synchronised)
+    s->release(idx_raw);
+    s->release(val_raw);
   }
   *out = s;
   return PRGD_OK;
@@ -540,13 +550,13 @@ prgd_status prgd_iterate_profiled(prgd_solver s, int32_t iters, double *phase_ms
     chk(hipEventRecord(e[0], s->stream));
     chk(sampled_pass(s, 0));
     chk(hipEventRecord(e[1], s->stream));
-    chk(launch_project(s->d, s->stream));
+    chk(launch_project(s->batch(), s->stream));
     chk(hipEventRecord(e[2], s->stream));
-    chk(launch_retract(s->d, s->stream));
+    chk(launch_retract(s->batch(), s->stream));
     chk(hipEventRecord(e[3], s->stream));
-    chk(launch_output(s->d, s->stream, 0));
+    chk(launch_output(s->batch(), s->stream, 0));
     chk(hipEventRecord(e[4], s->stream));
-    if (s->has_truth) chk(launch_truth_sweep(s->d, s->stream, 0));
+    if (s->has_truth) chk(launch_truth_sweep(s->batch(), s->stream, 0));
     chk(hipEventRecord(e[5], s->stream));
     if (err != hipSuccess) rc = fail(PRGD_EDEVICE, std::string("launch: ") + hipGetErrorString(err));
   }

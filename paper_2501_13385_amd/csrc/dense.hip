@@ -33,6 +33,8 @@
 // Sigma^2 Z^T the new core is T'_{i-1} = B_i Tr_i with Tr_i = F Z_r Sigma_r^{-1},
 // and P_i = T'^{<=i,T} W^{<=i} = Tr_i^T (B^T B).  The last core is
 // P_{m-1} C_{m-1}.
+#include <algorithm>
+
 #include "prgd_internal.hpp"
 #include "block_ops.hpp"
 #include "small_la.hpp"
@@ -86,14 +88,16 @@ __device__ inline void block_core(const Dev &d, int &c, int &x0, int &x1) {
 // ---------------------------------------------------------------------------
 // blocks [0, nbL): core j-1 -> GL_j and Theta_{j-1}
 // blocks [nbL, nbL+nbH): core m-j -> H_{m-j}
-__global__ void __launch_bounds__(256) k_gram(Dev d, int j, int nbL) {
-  if (d.st->done) return;
-  __shared__ double smem[SMEM];
+__global__ void __launch_bounds__(256) k_gram(const Dev *__restrict__ dt, int j) {
+  const Dev &d = dt[blockIdx.y];
   const int R = d.R, RR = R * R, m = d.m;
+  const int nbL = nblocks_for(d.n[j - 1], 4), nbH = nblocks_for(d.n[m - j], 4);
+  if ((int)blockIdx.x >= nbL + nbH || d.st->done) return;
+  __shared__ double smem[SMEM];
   const bool left = (int)blockIdx.x < nbL;
   const int c = left ? j - 1 : m - j;
   const int lb = left ? (int)blockIdx.x : (int)blockIdx.x - nbL;
-  const int nbk = left ? nbL : (int)gridDim.x - nbL;
+  const int nbk = left ? nbL : nbH;
   const int per = (d.n[c] + nbk - 1) / nbk;
   const int x0 = lb * per;
   const int x1 = min(d.n[c], x0 + per);
@@ -172,10 +176,12 @@ __global__ void __launch_bounds__(256) k_gram(Dev d, int j, int nbL) {
 
 // finish of a Gram sweep step (one block): totals, inverses, and after the
 // last step the products Psi_c
-__global__ void __launch_bounds__(1024) k_gram_fin(Dev d, int j, int nbL, int nbT) {
+__global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, int j) {
+  const Dev &d = dt[blockIdx.y];
   if (d.st->done) return;
   __shared__ double smem[SMEM];
   const int R = d.R, RR = R * R, m = d.m;
+  const int nbL = nblocks_for(d.n[j - 1], 4), nbT = nbL + nblocks_for(d.n[m - j], 4);
 
   // last block: totals, inverses
   double *GLj = sm_slot(d, j, S_GL), *THc = sm_slot(d, j - 1, S_TH), *Hb = sm_slot(d, m - j, S_H);
@@ -233,8 +239,9 @@ __global__ void __launch_bounds__(1024) k_gram_fin(Dev d, int j, int nbL, int nb
 // ---------------------------------------------------------------------------
 // tangent components X_c(x) (all cores, slice-parallel); clears Y
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_tangent(Dev d) {
-  if (d.st->done) return;
+__global__ void __launch_bounds__(256) k_tangent(const Dev *__restrict__ dt) {
+  const Dev &d = dt[blockIdx.y];
+  if ((int)blockIdx.x >= d.blk_off[d.m] || d.st->done) return;
   __shared__ double smem[SMEM];
   int c, x0, x1;
   block_core(d, c, x0, x1);
@@ -304,11 +311,12 @@ __device__ inline void build_block(const Dev &d, int c, const double *sT, const 
 // right Grams of the block TT: GR_b = sum_x C_b(x) GR_{b+1} C_b(x)^T, b = m-1..1
 // last block: pivoted Cholesky factor F_b of GR_b on its active indices
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_rgram(Dev d, int b) {
-  if (d.st->done) return;
+__global__ void __launch_bounds__(256) k_rgram(const Dev *__restrict__ dt, int b) {
+  const Dev &d = dt[blockIdx.y];
+  const int nb = nblocks_for(d.n[b], 4);
+  if ((int)blockIdx.x >= nb || d.st->done) return;
   __shared__ double smem[SMEM];
   const int R = d.R, R2 = 2 * R, NE = R2 * R2, m = d.m;
-  const int nb = gridDim.x;
   const int per = (d.n[b] + nb - 1) / nb;
   const int x0 = blockIdx.x * per, x1 = min(d.n[b], x0 + per);
   const double alpha = d.st->alpha_n;
@@ -368,7 +376,9 @@ __global__ void __launch_bounds__(256) k_rgram(Dev d, int b) {
 }
 
 // finish of a right-Gram step (one block): total GR_b and its pivoted Cholesky factor
-__global__ void __launch_bounds__(1024) k_rgram_fin(Dev d, int b, int nb) {
+__global__ void __launch_bounds__(1024) k_rgram_fin(const Dev *__restrict__ dt, int b) {
+  const Dev &d = dt[blockIdx.y];
+  const int nb = nblocks_for(d.n[b], 4);
   if (d.st->done) return;
   __shared__ double smem[SMEM];
   const int R = d.R, R2 = 2 * R, NE = R2 * R2;
@@ -406,11 +416,12 @@ __global__ void __launch_bounds__(1024) k_rgram_fin(Dev d, int b, int nb) {
 // ---------------------------------------------------------------------------
 // left sweep of the retraction, cut i = 1..m-1 (core c = i-1)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_left(Dev d, int i) {
-  if (d.st->done) return;
+__global__ void __launch_bounds__(256) k_left(const Dev *__restrict__ dt, int i) {
+  const Dev &d = dt[blockIdx.y];
+  const int nb = nblocks_for(d.n[i - 1], 4);
+  if ((int)blockIdx.x >= nb || d.st->done) return;
   __shared__ double smem[SMEM];
   const int R = d.R, R2 = 2 * R, NE = R2 * R2, m = d.m, c = i - 1;
-  const int nb = gridDim.x;
   const int per = (d.n[c] + nb - 1) / nb;
   const int x0 = blockIdx.x * per, x1 = min(d.n[c], x0 + per);
   const double alpha = d.st->alpha_n;
@@ -471,7 +482,9 @@ __global__ void __launch_bounds__(256) k_left(Dev d, int i) {
 
 // finish of a left-sweep cut (one block): S = F^T (B^T B) F, eigen-decomposition,
 // truncation to r_i: Tr_i and P_i
-__global__ void __launch_bounds__(1024) k_left_fin(Dev d, int i, int nb) {
+__global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, int i) {
+  const Dev &d = dt[blockIdx.y];
+  const int nb = nblocks_for(d.n[i - 1], 4);
   if (d.st->done) return;
   __shared__ double smem[SMEM];
   const int R = d.R, R2 = 2 * R, NE = R2 * R2;
@@ -566,8 +579,9 @@ __global__ void __launch_bounds__(1024) k_left_fin(Dev d, int i, int nb) {
 // output: new cores T'_c(x) = P_c C_c(x) Tr_{c+1} (c < m-1), P_{m-1} C_{m-1}(x);
 // stop-test reductions ||T'||^2 = ||T'_{m-1}||^2 and <T', T>
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_output(Dev d, int init) {
-  if (d.st->done) return;
+__global__ void __launch_bounds__(256) k_output(const Dev *__restrict__ dt, int init) {
+  const Dev &d = dt[blockIdx.y];
+  if ((int)blockIdx.x >= d.blk_off[d.m] || d.st->done) return;
   __shared__ double smem[SMEM];
   int c, x0, x1;
   block_core(d, c, x0, x1);
@@ -656,7 +670,9 @@ __global__ void __launch_bounds__(256) k_output(Dev d, int init) {
 }
 
 // finish of the output step (one block): relative change, iteration count, stop test
-__global__ void __launch_bounds__(1024) k_output_fin(Dev d, int init, int nb) {
+__global__ void __launch_bounds__(1024) k_output_fin(const Dev *__restrict__ dt, int init) {
+  const Dev &d = dt[blockIdx.y];
+  const int nb = d.blk_off[d.m];
   if (d.st->done) return;
   __shared__ double sbuf[16];
   double a0 = 0.0, a1 = 0.0;
@@ -695,11 +711,12 @@ __global__ void __launch_bounds__(1024) k_output_fin(Dev d, int init, int nb) {
 // cross Gram sweep with the truth: Z_{c+1} = sum_x A_c(x)^T Z_c B_c(x)
 // mode 0: A = iterate, B = truth (relative error); mode 1: A = B = truth (||T*||^2)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_cross(Dev d, int c, int mode) {
-  if (mode == 0 && !d.st->upd) return;
+__global__ void __launch_bounds__(256) k_cross(const Dev *__restrict__ dt, int c, int mode) {
+  const Dev &d = dt[blockIdx.y];
+  const int nb = nblocks_for(d.n[c], 4);
+  if ((int)blockIdx.x >= nb || !d.has_truth || (mode == 0 && !d.st->upd)) return;
   __shared__ double smem[SMEM];
   const int R = d.R, RR = R * R, m = d.m;
-  const int nb = gridDim.x;
   const int per = (d.n[c] + nb - 1) / nb;
   const int x0 = blockIdx.x * per, x1 = min(d.n[c], x0 + per);
   const double *Acore = (mode == 0) ? d.cores : d.truth;
@@ -747,8 +764,10 @@ __global__ void __launch_bounds__(256) k_cross(Dev d, int c, int mode) {
 }
 
 // finish of a cross-Gram step (one block)
-__global__ void __launch_bounds__(1024) k_cross_fin(Dev d, int c, int mode, int nb) {
-  if (mode == 0 && !d.st->upd) return;
+__global__ void __launch_bounds__(1024) k_cross_fin(const Dev *__restrict__ dt, int c, int mode) {
+  const Dev &d = dt[blockIdx.y];
+  const int nb = nblocks_for(d.n[c], 4);
+  if (!d.has_truth || (mode == 0 && !d.st->upd)) return;
   __shared__ double smem[SMEM];
   const int R = d.R, RR = R * R, m = d.m;
   double *Zn = sm_slot(d, c + 1, S_ZT);
@@ -779,65 +798,70 @@ __global__ void __launch_bounds__(1024) k_cross_fin(Dev d, int c, int mode, int 
 }
 
 // ---------------------------------------------------------------------------
-// launchers
+// launchers (grids sized for the largest member of the batch)
 // ---------------------------------------------------------------------------
-// blocks for a slice-parallel reduction kernel over n slices: at least `target`
-// slices per block and at most 128 blocks, so the finishing block reads few partials
-static int nblocks_for(int n, int target) {
-  int per = (n + 127) / 128;
-  if (per < target) per = target;
-  int nb = (n + per - 1) / per;
-  if (nb < 1) nb = 1;
-  return nb;
+template <typename Fn>
+static int max_over(const Batch &b, Fn f) {
+  int v = 1;
+  for (int i = 0; i < b.ns; ++i) v = std::max(v, f(b.host[i]));
+  return v;
 }
 
 // phase 1: metric-weighted Gram sweeps and the tangent components
-hipError_t launch_project(const Dev &d, hipStream_t s) {
-  const int m = d.m;
+hipError_t launch_project(const Batch &bt, hipStream_t s) {
+  const int m = bt.host[0].m, ns = bt.ns;
   for (int j = 1; j <= m - 1; ++j) {
-    const int nbL = nblocks_for(d.n[j - 1], 4), nbH = nblocks_for(d.n[m - j], 4);
-    hipLaunchKernelGGL(k_gram, dim3(nbL + nbH), dim3(256), 0, s, d, j, nbL);
-    hipLaunchKernelGGL(k_gram_fin, dim3(1), dim3(1024), 0, s, d, j, nbL, nbL + nbH);
+    const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 4) + nblocks_for(d.n[m - j], 4); });
+    hipLaunchKernelGGL(k_gram, dim3(g, ns), dim3(256), 0, s, bt.dt, j);
+    hipLaunchKernelGGL(k_gram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, j);
   }
-  hipLaunchKernelGGL(k_tangent, dim3(d.blk_off[m]), dim3(256), 0, s, d);
+  const int g = max_over(bt, [&](const Dev &d) { return d.blk_off[m]; });
+  hipLaunchKernelGGL(k_tangent, dim3(g, ns), dim3(256), 0, s, bt.dt);
   return hipGetLastError();
 }
 
 // phase 2: retraction sweeps (right Grams of W_l, then the truncated left sweep)
-hipError_t launch_retract(const Dev &d, hipStream_t s) {
-  const int m = d.m;
+hipError_t launch_retract(const Batch &bt, hipStream_t s) {
+  const int m = bt.host[0].m, ns = bt.ns;
   for (int b = m - 1; b >= 1; --b) {
-    const int nb = nblocks_for(d.n[b], 4);
-    hipLaunchKernelGGL(k_rgram, dim3(nb), dim3(256), 0, s, d, b);
-    hipLaunchKernelGGL(k_rgram_fin, dim3(1), dim3(1024), 0, s, d, b, nb);
+    const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[b], 4); });
+    hipLaunchKernelGGL(k_rgram, dim3(g, ns), dim3(256), 0, s, bt.dt, b);
+    hipLaunchKernelGGL(k_rgram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, b);
   }
   for (int i = 1; i <= m - 1; ++i) {
-    const int nb = nblocks_for(d.n[i - 1], 4);
-    hipLaunchKernelGGL(k_left, dim3(nb), dim3(256), 0, s, d, i);
-    hipLaunchKernelGGL(k_left_fin, dim3(1), dim3(1024), 0, s, d, i, nb);
+    const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[i - 1], 4); });
+    hipLaunchKernelGGL(k_left, dim3(g, ns), dim3(256), 0, s, bt.dt, i);
+    hipLaunchKernelGGL(k_left_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, i);
   }
   return hipGetLastError();
 }
 
 // phase 3: new cores and the stopping-test reductions
-hipError_t launch_output(const Dev &d, hipStream_t s, int init) {
-  hipLaunchKernelGGL(k_output, dim3(d.blk_off[d.m]), dim3(256), 0, s, d, init);
-  hipLaunchKernelGGL(k_output_fin, dim3(1), dim3(1024), 0, s, d, init, d.blk_off[d.m]);
+hipError_t launch_output(const Batch &bt, hipStream_t s, int init) {
+  const int m = bt.host[0].m, ns = bt.ns;
+  const int g = max_over(bt, [&](const Dev &d) { return d.blk_off[m]; });
+  hipLaunchKernelGGL(k_output, dim3(g, ns), dim3(256), 0, s, bt.dt, init);
+  hipLaunchKernelGGL(k_output_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, init);
   return hipGetLastError();
 }
 
-hipError_t launch_dense_iteration(const Dev &d, hipStream_t s, int init) {
+hipError_t launch_dense_iteration(const Batch &bt, hipStream_t s, int init) {
   hipError_t e;
-  if (!init && (e = launch_project(d, s)) != hipSuccess) return e;
-  if ((e = launch_retract(d, s)) != hipSuccess) return e;
-  return launch_output(d, s, init);
+  if (!init && (e = launch_project(bt, s)) != hipSuccess) return e;
+  if ((e = launch_retract(bt, s)) != hipSuccess) return e;
+  return launch_output(bt, s, init);
 }
 
-hipError_t launch_truth_sweep(const Dev &d, hipStream_t s, int mode) {
-  for (int c = 0; c < d.m; ++c) {
-    const int nb = nblocks_for(d.n[c], 4);
-    hipLaunchKernelGGL(k_cross, dim3(nb), dim3(256), 0, s, d, c, mode);
-    hipLaunchKernelGGL(k_cross_fin, dim3(1), dim3(1024), 0, s, d, c, mode, nb);
+// relative error against the truth (members without truth cores skip it)
+hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode) {
+  const int m = bt.host[0].m, ns = bt.ns;
+  bool any = false;
+  for (int i = 0; i < ns; ++i) any = any || bt.host[i].has_truth;
+  if (!any) return hipSuccess;
+  for (int c = 0; c < m; ++c) {
+    const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[c], 4); });
+    hipLaunchKernelGGL(k_cross, dim3(g, ns), dim3(256), 0, s, bt.dt, c, mode);
+    hipLaunchKernelGGL(k_cross_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, c, mode);
   }
   return hipGetLastError();
 }

@@ -76,6 +76,22 @@ struct State {
   unsigned counter[C_COUNT];
 };
 
+// order-3 sampled pass: per-workgroup partials (see sampled3.hip)
+constexpr int KSEG = 8;   // segment slots per workgroup table
+
+struct S3 {
+  long long chunk;       // samples per workgroup
+  int nwg;
+  int stage;             // 1: boundary vectors staged in LDS
+  const int *vfirst;     // [nwg] first segment (middle-mode index) of each workgroup's chunk
+  const int *blo;        // [n_1] first workgroup covering segment v (blo > bhi: empty segment)
+  const int *bhi;        // [n_1]
+  void *part_bnd;        // [nwg][L]: dT_0 [n_0 R] | dT_2 [n_2 R] | s_0 [n_0] | s_2 [n_2]
+  void *part_seg;        // [nwg][KSEG][R*R + 1]: middle-core gradient pieces and s_1
+  void *ovf;             // [n_1][R*R + 1] overflow accumulator (zero between passes)
+  double *part_rsq;      // [nwg]
+};
+
 struct Dev {
   int m;
   int R;                       // padded slice dimension
@@ -113,22 +129,29 @@ struct Dev {
   State *st;
   IterRecord *hist;
   int hist_cap;
+  int use3;                    // 1: order-3 grouped sampled pass with the tables in q3
+  int nb_sampled;              // grid of the any-order sampled pass
+  S3 q3;
 };
 
-// order-3 sampled pass: per-workgroup partials (see sampled3.hip)
-constexpr int KSEG = 8;   // segment slots per workgroup table
+// Blocks of a slice-parallel reduction kernel over n slices: at least
+// `target` slices per block and at most 128 blocks, so that the finishing
+// block reads few partials.
+__host__ __device__ inline int nblocks_for(int n, int target) {
+  int per = (n + 127) / 128;
+  if (per < target) per = target;
+  int nb = (n + per - 1) / per;
+  return nb < 1 ? 1 : nb;
+}
 
-struct S3 {
-  long long chunk;       // samples per workgroup
-  int nwg;
-  int stage;             // 1: boundary vectors staged in LDS
-  const int *vfirst;     // [nwg] first segment (middle-mode index) of each workgroup's chunk
-  const int *blo;        // [n_1] first workgroup covering segment v (blo > bhi: empty segment)
-  const int *bhi;        // [n_1]
-  void *part_bnd;        // [nwg][L]: dT_0 [n_0 R] | dT_2 [n_2 R] | s_0 [n_0] | s_2 [n_2]
-  void *part_seg;        // [nwg][KSEG][R*R + 1]: middle-core gradient pieces and s_1
-  void *ovf;             // [n_1][R*R + 1] overflow accumulator (zero between passes)
-  double *part_rsq;      // [nwg]
+// A set of solves advanced by the same launches.  Every kernel takes the
+// device array `dt` of their descriptors and serves solve blockIdx.y; grids
+// are sized for the largest member and surplus blocks return at once.  All
+// members share m, R, the precision and the sampled-pass variant.
+struct Batch {
+  const Dev *dt;     // device array [ns]
+  const Dev *host;   // host copies [ns] (grid sizing)
+  int ns;
 };
 
 __host__ __device__ inline double *sm_slot(const Dev &d, int bond, int slot) {

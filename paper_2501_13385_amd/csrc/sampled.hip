@@ -25,8 +25,10 @@ __device__ inline void atomic_add(F *p, F v) {
 // computed first and kept in LDS (thread-interleaved, conflict-free); the
 // left vector is then carried left to right while scattering.
 template <typename F, int R>
-__global__ void __launch_bounds__(256) k_sampled(Dev d, int diag) {
-  if (!diag && d.st->done) return;
+__global__ void __launch_bounds__(256) k_sampled(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
+  const int nbs = d.nb_sampled;
+  if ((int)blockIdx.x >= nbs || (!diag && d.st->done)) return;
   extern __shared__ unsigned char lds_raw[];
   F *stack = reinterpret_cast<F *>(lds_raw);
   const F *cores = (d.prec == PREC_MIXED) ? (const F *)d.cores32 : (const F *)d.cores;
@@ -38,7 +40,7 @@ __global__ void __launch_bounds__(256) k_sampled(Dev d, int diag) {
   const int B = blockDim.x, t = threadIdx.x;
   constexpr int RR = R * R;
   double rsq = 0.0;
-  for (long long j = (long long)blockIdx.x * B + t; j < N; j += (long long)gridDim.x * B) {
+  for (long long j = (long long)blockIdx.x * B + t; j < N; j += (long long)nbs * B) {
     F rho[R];
     {
       const int x = d.idx[(long long)(m - 1) * N + j];
@@ -125,19 +127,22 @@ __global__ void __launch_bounds__(256) k_sampled(Dev d, int diag) {
 // finish of the sampled pass (one block): total ||R||^2 from the per-block
 // partials, then the weights and the residual stopping test
 template <typename F>
-__global__ void __launch_bounds__(256) k_sampled_fin(Dev d, const double *rsq_part, int nb, int diag) {
+__global__ void __launch_bounds__(256) k_sampled_fin(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
   if (!diag && d.st->done) return;
+  const double *rsq_part = d.use3 ? d.q3.part_rsq : d.part;
+  const int nb = d.use3 ? d.q3.nwg : d.nb_sampled;
   __shared__ double sbuf[16];
   double v = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) v += rsq_part[i];
   sampled_finish_total<F>(d, (F *)d.s, block_sum(v, sbuf), diag);
 }
 
-hipError_t launch_sampled_fin(const Dev &d, const double *rsq_part, int nb, int diag, hipStream_t s) {
-  if (d.prec == PREC_MIXED)
-    hipLaunchKernelGGL(k_sampled_fin<float>, dim3(1), dim3(256), 0, s, d, rsq_part, nb, diag);
+hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s) {
+  if (bt.host[0].prec == PREC_MIXED)
+    hipLaunchKernelGGL(k_sampled_fin<float>, dim3(1, bt.ns), dim3(256), 0, s, bt.dt, diag);
   else
-    hipLaunchKernelGGL(k_sampled_fin<double>, dim3(1), dim3(256), 0, s, d, rsq_part, nb, diag);
+    hipLaunchKernelGGL(k_sampled_fin<double>, dim3(1, bt.ns), dim3(256), 0, s, bt.dt, diag);
   return hipGetLastError();
 }
 
@@ -177,7 +182,7 @@ __global__ void __launch_bounds__(256) k_eval(int m, long long N, const int *__r
 // host-side launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_sampled_fin(const Dev &d, const double *rsq_part, int nb, int diag, hipStream_t s);
+hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s);
 
 static int lds_block(int m, int R, int elem) {
   // choose the largest block (multiple of 64, <= 256) whose interface stack fits 63 KiB
@@ -188,26 +193,29 @@ static int lds_block(int m, int R, int elem) {
 }
 
 template <typename F, int R>
-static hipError_t launch_sampled_t(const Dev &d, int diag, int nblocks, hipStream_t s) {
-  const int B = lds_block(d.m, R, (int)sizeof(F));
+static hipError_t launch_sampled_t(const Batch &bt, int diag, hipStream_t s) {
+  const int m = bt.host[0].m;
+  const int B = lds_block(m, R, (int)sizeof(F));
   if (B == 0) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(d.m - 1) * R * sizeof(F) * B;
-  hipLaunchKernelGGL((k_sampled<F, R>), dim3(nblocks), dim3(B), lds, s, d, diag);
+  int g = 1;
+  for (int i = 0; i < bt.ns; ++i) g = g > bt.host[i].nb_sampled ? g : bt.host[i].nb_sampled;
+  const size_t lds = (size_t)(m - 1) * R * sizeof(F) * B;
+  hipLaunchKernelGGL((k_sampled<F, R>), dim3(g, bt.ns), dim3(B), lds, s, bt.dt, diag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_sampled_fin(d, d.part, nblocks, diag, s);
+  return launch_sampled_fin(bt, diag, s);
 }
 
 template <typename F>
-static hipError_t launch_sampled_f(const Dev &d, int diag, int nblocks, hipStream_t s) {
-  switch (d.R) {
-    case 2: return launch_sampled_t<F, 2>(d, diag, nblocks, s);
-    case 4: return launch_sampled_t<F, 4>(d, diag, nblocks, s);
-    case 6: return launch_sampled_t<F, 6>(d, diag, nblocks, s);
-    case 8: return launch_sampled_t<F, 8>(d, diag, nblocks, s);
-    case 10: return launch_sampled_t<F, 10>(d, diag, nblocks, s);
-    case 12: return launch_sampled_t<F, 12>(d, diag, nblocks, s);
-    case 16: return launch_sampled_t<F, 16>(d, diag, nblocks, s);
+static hipError_t launch_sampled_f(const Batch &bt, int diag, hipStream_t s) {
+  switch (bt.host[0].R) {
+    case 2: return launch_sampled_t<F, 2>(bt, diag, s);
+    case 4: return launch_sampled_t<F, 4>(bt, diag, s);
+    case 6: return launch_sampled_t<F, 6>(bt, diag, s);
+    case 8: return launch_sampled_t<F, 8>(bt, diag, s);
+    case 10: return launch_sampled_t<F, 10>(bt, diag, s);
+    case 12: return launch_sampled_t<F, 12>(bt, diag, s);
+    case 16: return launch_sampled_t<F, 16>(bt, diag, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -216,9 +224,9 @@ int sampled_block_size(int m, int R, int prec) {
   return lds_block(m, R, prec == PREC_MIXED ? 4 : 8);
 }
 
-hipError_t launch_sampled(const Dev &d, int diag, int nblocks, hipStream_t s) {
-  if (d.prec == PREC_MIXED) return launch_sampled_f<float>(d, diag, nblocks, s);
-  return launch_sampled_f<double>(d, diag, nblocks, s);
+hipError_t launch_sampled(const Batch &bt, int diag, hipStream_t s) {
+  if (bt.host[0].prec == PREC_MIXED) return launch_sampled_f<float>(bt, diag, s);
+  return launch_sampled_f<double>(bt, diag, s);
 }
 
 hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *cores, const long long *coff_dev,

@@ -20,6 +20,8 @@
 //     segment table in LDS when the segment changes.
 // A second kernel sums the partials in a fixed order (deterministic) and
 // finishes the metric weights.
+#include <algorithm>
+
 #include "prgd_internal.hpp"
 #include "block_ops.hpp"
 
@@ -54,9 +56,13 @@ __device__ inline double ld_shfl(double v, int src) { return __shfl(v, src, 64);
 __device__ inline float ld_shfl(float v, int src) { return __shfl(v, src, 64); }
 
 template <typename F, int R, int NT, bool STAGE>
-__global__ void __launch_bounds__(NT) k_sampled3(Dev d, S3 q, const F *__restrict__ cores, const F *__restrict__ bnd,
-                                                 const F *__restrict__ y, int diag) {
-  if (!diag && d.st->done) return;
+__global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
+  const S3 &q = d.q3;
+  if ((int)blockIdx.x >= q.nwg || (!diag && d.st->done)) return;
+  const F *__restrict__ cores = (const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores);
+  const F *__restrict__ bnd = (const F *)d.bnd;
+  const F *__restrict__ y = (const F *)(d.prec == PREC_MIXED ? (const void *)d.y32 : (const void *)d.y64);
   typedef Mma<F> M;
   constexpr int RR = R * R;
   constexpr int SEGW = RR + 1;
@@ -204,12 +210,16 @@ __global__ void __launch_bounds__(NT) k_sampled3(Dev d, S3 q, const F *__restric
 // workgroup partials; blocks [nbB, grid): middle-core segments, one output
 // per thread (2-3 pieces each).
 template <typename F, int R>
-__global__ void __launch_bounds__(256) k_sampled3_reduce(Dev d, S3 q, int nbB, int diag) {
-  if (!diag && d.st->done) return;
+__global__ void __launch_bounds__(256) k_sampled3_reduce(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
+  const S3 &q = d.q3;
   constexpr int RR = R * R;
   constexpr int SEGW = RR + 1;
   const int n1 = d.n[0], n2 = d.n[1], n3 = d.n[2];
   const int L = n1 * R + n3 * R + n1 + n3;
+  const int nbB = (L + 63) / 64;
+  const int nbS = (int)(((long long)n2 * SEGW + 255) / 256);
+  if ((int)blockIdx.x >= nbB + nbS || (!diag && d.st->done)) return;
   F *Y = (F *)d.Y;
   F *s = (F *)d.s;
   const F *pb = (const F *)q.part_bnd;
@@ -264,42 +274,46 @@ __global__ void __launch_bounds__(256) k_sampled3_reduce(Dev d, S3 q, int nbB, i
   }
 }
 
-hipError_t launch_sampled_fin(const Dev &d, const double *rsq_part, int nb, int diag, hipStream_t s);
+hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s);
 
 template <typename F, int R>
-static hipError_t launch3_t(const Dev &d, const S3 &q, int diag, hipStream_t st) {
-  const int n1 = d.n[0], n3 = d.n[2];
-  const size_t base = (size_t)(n1 * R + n3 * R + n1 + n3 + KSEG * (R * R + 1)) * sizeof(F);
-  const size_t lds = base + (q.stage ? (size_t)(n1 + n3) * R * sizeof(F) : 0);
-  const F *cores = (d.prec == PREC_MIXED) ? (const F *)d.cores32 : (const F *)d.cores;
-  const F *y = (d.prec == PREC_MIXED) ? (const F *)d.y32 : (const F *)d.y64;
-  const F *bnd = (const F *)d.bnd;
+static hipError_t launch3_t(const Batch &bt, int diag, hipStream_t st) {
+  size_t lds = 0;
+  int nwg = 1, nred = 1;
+  const int stage = bt.host[0].q3.stage;
+  for (int i = 0; i < bt.ns; ++i) {
+    const Dev &d = bt.host[i];
+    const int n1 = d.n[0], n3 = d.n[2];
+    const size_t base = (size_t)(n1 * R + n3 * R + n1 + n3 + KSEG * (R * R + 1)) * sizeof(F);
+    lds = std::max(lds, base + (stage ? (size_t)(n1 + n3) * R * sizeof(F) : 0));
+    nwg = std::max(nwg, d.q3.nwg);
+    const int L = n1 * R + n3 * R + n1 + n3;
+    const long long nbS = ((long long)d.n[1] * (R * R + 1) + 255) / 256;
+    nred = std::max(nred, (int)((L + 63) / 64 + nbS));
+  }
   constexpr int NT = (sizeof(F) == 8 && R >= 10) ? 512 : 1024;
-  if (q.stage)
-    hipLaunchKernelGGL((k_sampled3<F, R, NT, true>), dim3(q.nwg), dim3(NT), lds, st, d, q, cores, bnd, y, diag);
+  if (stage)
+    hipLaunchKernelGGL((k_sampled3<F, R, NT, true>), dim3(nwg, bt.ns), dim3(NT), lds, st, bt.dt, diag);
   else
-    hipLaunchKernelGGL((k_sampled3<F, R, NT, false>), dim3(q.nwg), dim3(NT), lds, st, d, q, cores, bnd, y, diag);
+    hipLaunchKernelGGL((k_sampled3<F, R, NT, false>), dim3(nwg, bt.ns), dim3(NT), lds, st, bt.dt, diag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int L = n1 * R + n3 * R + n1 + n3;
-  const int nbB = (L + 63) / 64;
-  const long long nbS = ((long long)d.n[1] * (R * R + 1) + 255) / 256;
-  hipLaunchKernelGGL((k_sampled3_reduce<F, R>), dim3((int)(nbB + nbS)), dim3(256), 0, st, d, q, nbB, diag);
+  hipLaunchKernelGGL((k_sampled3_reduce<F, R>), dim3(nred, bt.ns), dim3(256), 0, st, bt.dt, diag);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_sampled_fin(d, q.part_rsq, q.nwg, diag, st);
+  return launch_sampled_fin(bt, diag, st);
 }
 
 template <typename F>
-static hipError_t launch3_f(const Dev &d, const S3 &q, int diag, hipStream_t st) {
-  switch (d.R) {
-    case 2: return launch3_t<F, 2>(d, q, diag, st);
-    case 4: return launch3_t<F, 4>(d, q, diag, st);
-    case 6: return launch3_t<F, 6>(d, q, diag, st);
-    case 8: return launch3_t<F, 8>(d, q, diag, st);
-    case 10: return launch3_t<F, 10>(d, q, diag, st);
-    case 12: return launch3_t<F, 12>(d, q, diag, st);
-    case 16: return launch3_t<F, 16>(d, q, diag, st);
+static hipError_t launch3_f(const Batch &bt, int diag, hipStream_t st) {
+  switch (bt.host[0].R) {
+    case 2: return launch3_t<F, 2>(bt, diag, st);
+    case 4: return launch3_t<F, 4>(bt, diag, st);
+    case 6: return launch3_t<F, 6>(bt, diag, st);
+    case 8: return launch3_t<F, 8>(bt, diag, st);
+    case 10: return launch3_t<F, 10>(bt, diag, st);
+    case 12: return launch3_t<F, 12>(bt, diag, st);
+    case 16: return launch3_t<F, 16>(bt, diag, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -314,9 +328,9 @@ size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage) {
 
 int sampled3_kseg() { return KSEG; }
 
-hipError_t launch_sampled3(const Dev &d, const S3 &q, int diag, hipStream_t st) {
-  if (d.prec == PREC_MIXED) return launch3_f<float>(d, q, diag, st);
-  return launch3_f<double>(d, q, diag, st);
+hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st) {
+  if (bt.host[0].prec == PREC_MIXED) return launch3_f<float>(bt, diag, st);
+  return launch3_f<double>(bt, diag, st);
 }
 
 }  // namespace prgd
