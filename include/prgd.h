@@ -188,6 +188,75 @@ prgd_status prgd_eval(int32_t m, const int32_t *n, const int32_t *r, const doubl
 
 prgd_status prgd_destroy(prgd_solver s);
 
+/* ------------------------------------------------------------------------
+ * Request server: many independent completion problems on one device.
+ *
+ * Serves callers that solve streams of independent problems (different
+ * orders, mode sizes, ranks and |Omega|).  Each request is one PRGD solve with
+ * exactly the semantics of prgd_create + prgd_run on the same descriptor.  A
+ * scheduler thread owned by the server admits queued requests in arrival
+ * order while their device footprint fits the memory budget and a slot is
+ * free, keeps every admitted solve's cores, observations and preconditioner
+ * state resident, and advances all live solves that share order, padded rank,
+ * precision and sampled-pass variant with the same kernel launches (one
+ * launch serves every member, blockIdx.y selecting the solve).  Finished
+ * solves leave the batch between rounds and queued requests join as memory
+ * frees up (continuous batching).  Results do not depend on which other
+ * requests were live: every kernel computes each solve from its own data only.
+ * ------------------------------------------------------------------------ */
+typedef struct prgd_server_s *prgd_server;
+
+typedef struct {
+  int64_t hbm_budget_bytes;    /* device bytes the live solves may hold together;
+                                  <= 0: three quarters of the free device memory        */
+  int32_t max_slots;           /* live solves at once, 1..4096                            */
+  int32_t iters_per_tick;      /* iterations launched for the live solves per scheduling
+                                  round; <= 0: 4.  Does not change any result.            */
+} prgd_server_desc;
+
+typedef struct {
+  prgd_report report;          /* as prgd_run's; seconds = admission to completion       */
+  double submit_s;             /* server clock (seconds since prgd_server_create)        */
+  double admit_s;              /* solve created on the device                             */
+  double finish_s;             /* completion observed by the scheduler                    */
+  int64_t footprint_bytes;     /* admission estimate of the device bytes it held          */
+} prgd_ticket_info;
+
+/* Start a server on the current HIP device.  *out owns a scheduler thread and
+   every device buffer of the solves it admits. */
+prgd_status prgd_server_create(const prgd_server_desc *desc, prgd_server *out);
+
+/* Queue one problem.  desc is read during the call only: host or device
+   inputs are copied into server-owned host memory; desc->stream is ignored.
+   Shapes, ranks, sizes and options are checked here (PRGD_EINVAL,
+   PRGD_ENOTSUP); a request whose footprint exceeds the whole budget returns
+   PRGD_ENOMEM.  Index ranges, duplicates and values are checked at admission
+   and reported by poll.  *ticket identifies the request (thread-safe). */
+prgd_status prgd_server_submit(prgd_server sv, const prgd_desc *desc, uint64_t *ticket);
+
+/* Non-blocking.  PRGD_PENDING while the request is queued or running.  Once it
+   has finished: fills *info (may be NULL), copies the packed final cores into
+   cores[cap] (may be NULL; cap >= prgd_cores_numel or PRGD_EINVAL and the
+   result is kept), releases the ticket and returns the solve's status
+   (PRGD_OK, PRGD_NOT_CONVERGED or a negative error).  Unknown or released
+   ticket: PRGD_ESTATE.  Thread-safe. */
+prgd_status prgd_server_poll(prgd_server sv, uint64_t ticket, prgd_ticket_info *info, double *cores,
+                             int64_t cap);
+
+/* Block until the request has finished (PRGD_OK) or timeout_s seconds have
+   passed (PRGD_PENDING); timeout_s < 0 waits without limit.  Does not release
+   the ticket.  Thread-safe. */
+prgd_status prgd_server_wait(prgd_server sv, uint64_t ticket, double timeout_s);
+
+/* Counters: requests queued, live on the device, finished and not yet polled,
+   and the device bytes the live solves hold by their admission estimates. */
+prgd_status prgd_server_stats(prgd_server sv, int32_t *queued, int32_t *live, int32_t *finished,
+                              int64_t *bytes_in_use);
+
+/* Stop the scheduler, wait for the device, free everything.  Requests still
+   queued or running are abandoned. */
+prgd_status prgd_server_destroy(prgd_server sv);
+
 const char *prgd_status_str(prgd_status st);
 const char *prgd_last_error(void);
 

@@ -77,6 +77,24 @@ class prgd_report(C.Structure):
     ]
 
 
+class prgd_server_desc(C.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", C.c_int64),
+        ("max_slots", C.c_int32),
+        ("iters_per_tick", C.c_int32),
+    ]
+
+
+class prgd_ticket_info(C.Structure):
+    _fields_ = [
+        ("report", prgd_report),
+        ("submit_s", C.c_double),
+        ("admit_s", C.c_double),
+        ("finish_s", C.c_double),
+        ("footprint_bytes", C.c_int64),
+    ]
+
+
 _lib = None
 
 
@@ -104,6 +122,12 @@ def load() -> C.CDLL:
         "prgd_destroy": (i32, [vp]),
         "prgd_status_str": (C.c_char_p, [i32]),
         "prgd_last_error": (C.c_char_p, []),
+        "prgd_server_create": (i32, [C.POINTER(prgd_server_desc), C.POINTER(vp)]),
+        "prgd_server_submit": (i32, [vp, C.POINTER(prgd_desc), C.POINTER(C.c_uint64)]),
+        "prgd_server_poll": (i32, [vp, C.c_uint64, C.POINTER(prgd_ticket_info), dp, i64]),
+        "prgd_server_wait": (i32, [vp, C.c_uint64, C.c_double]),
+        "prgd_server_stats": (i32, [vp, i32p, i32p, i32p, C.POINTER(C.c_int64)]),
+        "prgd_server_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -117,7 +141,9 @@ def exported_symbols() -> List[str]:
     return [n for n in ("prgd_cores_numel", "prgd_create", "prgd_iterate", "prgd_iterate_profiled",
                         "prgd_sync", "prgd_run",
                         "prgd_get_report", "prgd_get_cores", "prgd_get_history", "prgd_sampled_pass",
-                        "prgd_eval", "prgd_destroy", "prgd_status_str", "prgd_last_error")]
+                        "prgd_eval", "prgd_destroy", "prgd_status_str", "prgd_last_error",
+                        "prgd_server_create", "prgd_server_submit", "prgd_server_poll", "prgd_server_wait",
+                        "prgd_server_stats", "prgd_server_destroy")]
 
 
 def _check(st: int, allow=(OK,)) -> int:
@@ -165,12 +191,10 @@ def _ptr_of(a):
     return a.ctypes.data, False
 
 
-def prgd_create(shape, ranks, indices, values, init_cores, *, truth_cores=None, precision="fp64",
-                step_policy="theory", step=1.0, eps_fixed=0.0, stop_rule="residual", tol=1e-10,
-                max_iter=500, sort_mode=-1, stream=None):
-    """Create a solver.  ``indices`` (m, N) int32 and ``values`` (N,) float64/float32 are numpy
-    arrays (host) or torch CUDA tensors (device).  Returns an opaque handle (int)."""
-    lib = load()
+def _make_desc(shape, ranks, indices, values, init_cores, *, truth_cores=None, precision="fp64",
+               step_policy="theory", step=1.0, eps_fixed=0.0, stop_rule="residual", tol=1e-10,
+               max_iter=500, sort_mode=-1, stream=None):
+    """prgd_desc for the arguments, plus the objects that must outlive the call."""
     m = len(shape)
     keep = []
     if hasattr(indices, "data_ptr"):
@@ -216,8 +240,18 @@ def prgd_create(shape, ranks, indices, values, init_cores, *, truth_cores=None, 
     d.max_iter = int(max_iter)
     d.sort_mode = int(sort_mode)
     d.stream = stream
+    keep += [ns, rs]
+    return d, keep
+
+
+def prgd_create(shape, ranks, indices, values, init_cores, **kw):
+    """Create a solver.  ``indices`` (m, N) int32 and ``values`` (N,) float64/float32 are numpy
+    arrays (host) or torch CUDA tensors (device).  Returns an opaque handle (int)."""
+    lib = load()
+    d, keep = _make_desc(shape, ranks, indices, values, init_cores, **kw)
     h = C.c_void_p()
     _check(lib.prgd_create(C.byref(d), C.byref(h)))
+    del keep
     return h.value
 
 
@@ -352,6 +386,116 @@ class Solver:
     def close(self):
         if self.h:
             prgd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+# ---------------------------------------------------------------------------
+# request server
+# ---------------------------------------------------------------------------
+
+def prgd_server_create(hbm_budget_bytes: int = 0, max_slots: int = 256, iters_per_tick: int = 4):
+    d = prgd_server_desc()
+    d.hbm_budget_bytes = int(hbm_budget_bytes)
+    d.max_slots = int(max_slots)
+    d.iters_per_tick = int(iters_per_tick)
+    h = C.c_void_p()
+    _check(load().prgd_server_create(C.byref(d), C.byref(h)))
+    return h.value
+
+
+def prgd_server_submit(sv, shape, ranks, indices, values, init_cores, **kw) -> int:
+    d, keep = _make_desc(shape, ranks, indices, values, init_cores, **kw)
+    t = C.c_uint64(0)
+    _check(load().prgd_server_submit(sv, C.byref(d), C.byref(t)))
+    del keep
+    return int(t.value)
+
+
+def prgd_server_poll(sv, ticket: int, shape=None, ranks=None):
+    """None while pending; else (status, info dict, cores or None) and the ticket is released."""
+    info = prgd_ticket_info()
+    out = None
+    ptr, cap = None, 0
+    if shape is not None:
+        cap = prgd_cores_numel(shape, ranks)
+        out = np.empty(cap, dtype=np.float64)
+        ptr = out.ctypes.data_as(C.POINTER(C.c_double))
+    st = load().prgd_server_poll(sv, C.c_uint64(ticket), C.byref(info), ptr, cap)
+    if st == PENDING:
+        return None
+    if st == ESTATE or st == EINVAL:
+        _check(st)
+    res = _report(info.report)
+    res.update({"submit_s": info.submit_s, "admit_s": info.admit_s, "finish_s": info.finish_s,
+                "footprint_bytes": int(info.footprint_bytes)})
+    cores = unpack(out, shape, ranks) if (out is not None and st >= 0) else None
+    return st, res, cores
+
+
+def prgd_server_wait(sv, ticket: int, timeout_s: float = -1.0) -> bool:
+    st = load().prgd_server_wait(sv, C.c_uint64(ticket), float(timeout_s))
+    if st == PENDING:
+        return False
+    _check(st)
+    return True
+
+
+def prgd_server_stats(sv) -> dict:
+    q, l, f = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+    b = C.c_int64(0)
+    _check(load().prgd_server_stats(sv, C.byref(q), C.byref(l), C.byref(f), C.byref(b)))
+    return {"queued": q.value, "live": l.value, "finished": f.value, "bytes_in_use": b.value}
+
+
+def prgd_server_destroy(sv) -> None:
+    _check(load().prgd_server_destroy(sv))
+
+
+class Server:
+    """Convenience owner of one request server."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, max_slots: int = 256, iters_per_tick: int = 4):
+        self.h = prgd_server_create(hbm_budget_bytes, max_slots, iters_per_tick)
+        self.meta = {}
+
+    def submit(self, shape, ranks, indices, values, init_cores, **kw) -> int:
+        t = prgd_server_submit(self.h, shape, ranks, indices, values, init_cores, **kw)
+        self.meta[t] = ([int(s) for s in shape], [int(r) for r in ranks])
+        return t
+
+    def poll(self, ticket: int):
+        shape, ranks = self.meta[ticket]
+        res = prgd_server_poll(self.h, ticket, shape, ranks)
+        if res is not None:
+            del self.meta[ticket]
+        return res
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> bool:
+        return prgd_server_wait(self.h, ticket, timeout_s)
+
+    def result(self, ticket: int, timeout_s: float = -1.0):
+        if not self.wait(ticket, timeout_s):
+            return None
+        return self.poll(ticket)
+
+    def stats(self) -> dict:
+        return prgd_server_stats(self.h)
+
+    def close(self):
+        if self.h:
+            prgd_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

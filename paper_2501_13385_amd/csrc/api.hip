@@ -13,25 +13,8 @@
 
 #include "../../include/prgd.h"
 #include "prgd_internal.hpp"
+#include "solver.hpp"
 
-namespace prgd {
-hipError_t launch_sampled(const Batch &bt, int diag, hipStream_t s);
-int sampled_block_size(int m, int R, int prec);
-hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *cores, const long long *coff_dev,
-                       double *out, hipStream_t s);
-hipError_t launch_dense_iteration(const Batch &bt, hipStream_t s, int init);
-hipError_t launch_project(const Batch &bt, hipStream_t s);
-hipError_t launch_retract(const Batch &bt, hipStream_t s);
-hipError_t launch_output(const Batch &bt, hipStream_t s, int init);
-hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode);
-hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *idx_in, const void *values_in,
-                         int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s);
-hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
-hipError_t fill_f32(float *p, long long n, float v, hipStream_t s);
-hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream_t s);
-size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage);
-hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st);
-}  // namespace prgd
 
 using namespace prgd;
 
@@ -90,46 +73,6 @@ void unpack_cores(int m, const int *n, const int *r, int R, const double *src, d
 }
 
 }  // namespace
-
-struct prgd_solver_s {
-  Dev d{};
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int m = 0, R = 0;
-  std::vector<int> n, r;
-  std::vector<long long> coff;
-  long long N = 0;
-  int64_t numel = 0;
-  Dev *d_dev = nullptr;  // device copy of d (constant after create)
-  bool has_truth = false;
-  std::vector<void *> allocs;
-  double last_seconds = 0.0;
-
-  ~prgd_solver_s() {
-    if (stream) hipStreamSynchronize(stream);
-    for (void *p : allocs) hipFree(p);
-    if (own_stream && stream) hipStreamDestroy(stream);
-  }
-  Batch batch() const { return Batch{d_dev, &d, 1}; }
-  void release(void *p) {
-    auto it = std::find(allocs.begin(), allocs.end(), p);
-    if (it != allocs.end()) {
-      hipFree(p);
-      allocs.erase(it);
-    }
-  }
-  template <typename T>
-  hipError_t alloc(T **p, long long count) {
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, (size_t)std::max<long long>(count, 1) * sizeof(T));
-    if (e == hipSuccess) {
-      allocs.push_back(q);
-      *p = (T *)q;
-    }
-    return e;
-  }
-};
 
 namespace {
 
@@ -212,11 +155,7 @@ hipError_t sampled_pass(prgd_solver s, int diag) {
 }
 
 prgd_status enqueue_iterations(prgd_solver s, int iters) {
-  for (int it = 0; it < iters; ++it) {
-    HIPCHECK(sampled_pass(s, 0));
-    HIPCHECK(launch_dense_iteration(s->batch(), s->stream, 0));
-    if (s->has_truth) HIPCHECK(launch_truth_sweep(s->batch(), s->stream, 0));
-  }
+  HIPCHECK(enqueue_batch_iterations(s->batch(), iters, s->stream));
   return PRGD_OK;
 }
 
@@ -239,6 +178,65 @@ void fill_report(prgd_solver s, const State &st, prgd_report *rep) {
 }
 
 }  // namespace
+
+namespace prgd {
+
+prgd_status set_error(prgd_status st, const char *msg) { return fail(st, msg); }
+
+hipError_t enqueue_batch_iterations(const Batch &bt, int iters, hipStream_t s) {
+  const bool use3 = bt.host[0].use3 != 0;
+  bool truth = false;
+  for (int i = 0; i < bt.ns; ++i) truth = truth || bt.host[i].has_truth;
+  for (int it = 0; it < iters; ++it) {
+    hipError_t e = use3 ? launch_sampled3(bt, 0, s) : launch_sampled(bt, 0, s);
+    if (e != hipSuccess) return e;
+    if ((e = launch_dense_iteration(bt, s, 0)) != hipSuccess) return e;
+    if (truth && (e = launch_truth_sweep(bt, s, 0)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+int64_t solver_footprint(const prgd_desc *ds) {
+  if (!ds) return -1;
+  const int m = ds->order;
+  int64_t numel = 0;
+  if (!checked_numel(m, ds->mode_sizes, ds->tt_ranks, numel)) return -1;
+  int rmax = 1;
+  for (int k = 0; k <= m; ++k) rmax = std::max(rmax, (int)ds->tt_ranks[k]);
+  const int R = padded_dim(rmax);
+  if (R < 0) return -1;
+  const int64_t N = ds->n_obs;
+  int64_t pn = 0, soff = 0;
+  for (int k = 0; k < m; ++k) {
+    pn += (int64_t)ds->mode_sizes[k] * R * R;
+    soff += ds->mode_sizes[k];
+  }
+  const bool mixed = ds->precision == PRGD_PREC_MIXED;
+  const int64_t f = mixed ? 4 : 8, vb = ds->values_fp64 ? 8 : 4;
+  int64_t b = 0;
+  b += 4 * m * N;                                     // grouped indices
+  b += 8 * pn * 2 + (mixed ? 4 * pn * 2 : 8 * pn);    // cores, X, (cores32,) Y
+  b += 8 * soff + f * soff;                           // omega, s
+  b += 8LL * (m + 1) * SM_SLOTS * SLOT;               // small matrices
+  b += 8LL << 20;                                     // partials
+  b += (int64_t)sizeof(State) + (int64_t)sizeof(Dev) + (int64_t)sizeof(IterRecord) * (ds->max_iter + 1);
+  b += f * N;                                         // values in the working precision
+  b += f * (int64_t)(ds->mode_sizes[0] + ds->mode_sizes[m - 1]) * R;   // boundary vectors
+  if (ds->truth_cores) b += 8 * pn;
+  if (m == 3) {                                       // order-3 tables (upper bound)
+    const int64_t L = (int64_t)(ds->mode_sizes[0] + ds->mode_sizes[2]) * (R + 1);
+    const int64_t segw = (int64_t)R * R + 1;
+    b += 256 * (L + KSEG * segw) * f + (int64_t)ds->mode_sizes[1] * (segw * f + 8) + 256 * 12;
+  }
+  // transient during creation: unsorted copies, sort keys/permutations and
+  // the radix-sort scratch
+  if (!ds->mem_device) b += 4 * m * N + vb * N;
+  b += 12 * N + 16 * N + (1LL << 20);
+  b += 64 * 256;                                      // allocation granularity slack per buffer
+  return b;
+}
+
+}  // namespace prgd
 
 extern "C" {
 
@@ -265,7 +263,18 @@ const char *prgd_status_str(prgd_status st) {
   }
 }
 
-prgd_status prgd_create(const prgd_desc *ds, prgd_solver *out) {
+prgd_status prgd_create(const prgd_desc *ds, prgd_solver *out) { return solver_create(ds, out, false); }
+
+}  // extern "C"
+
+namespace prgd {
+
+prgd_status validate_desc(const prgd_desc *ds, const int32_t *idx_host, const void *vals_host) {
+  int64_t numel = 0;
+  return validate_host(ds, idx_host, vals_host, numel);
+}
+
+prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated) {
   if (!ds || !out) return fail(PRGD_EINVAL, "null descriptor or output handle");
   *out = nullptr;
   if (!ds->indices || !ds->values) return fail(PRGD_EINVAL, "indices and values are required");
@@ -289,8 +298,12 @@ prgd_status prgd_create(const prgd_desc *ds, prgd_solver *out) {
     val_h = hval.data();
   }
   int64_t numel = 0;
-  prgd_status vs = validate_host(ds, idx_h, val_h, numel);
-  if (vs != PRGD_OK) return vs;
+  if (validated) {
+    if (!checked_numel(m, ds->mode_sizes, ds->tt_ranks, numel)) return fail(PRGD_EINVAL, "invalid mode sizes or ranks");
+  } else {
+    prgd_status vs = validate_host(ds, idx_h, val_h, numel);
+    if (vs != PRGD_OK) return vs;
+  }
 
   prgd_solver s = new (std::nothrow) prgd_solver_s();
   if (!s) return fail(PRGD_ENOMEM, "host allocation failed");
@@ -527,6 +540,10 @@ prgd_status prgd_create(const prgd_desc *ds, prgd_solver *out) {
   *out = s;
   return PRGD_OK;
 }
+
+}  // namespace prgd
+
+extern "C" {
 
 prgd_status prgd_iterate(prgd_solver s, int32_t iters) {
   if (!s) return fail(PRGD_ESTATE, "null solver");

@@ -108,4 +108,15 @@ hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *id
   return hipGetLastError();
 }
 
+// copy each batch member's State to out[i] (thread i)
+__global__ void k_gather_state(const Dev *__restrict__ dt, int ns, State *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ns) out[i] = *dt[i].st;
+}
+
+hipError_t launch_gather_state(const Batch &bt, State *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_state, dim3((bt.ns + 63) / 64), dim3(64), 0, s, bt.dt, bt.ns, out);
+  return hipGetLastError();
+}
+
 }  // namespace prgd

@@ -1,0 +1,98 @@
+// Host-side state of one solve and the internal entry points shared by the
+// single-solve API and the request server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/prgd.h"
+#include "prgd_internal.hpp"
+
+namespace prgd {
+hipError_t launch_sampled(const Batch &bt, int diag, hipStream_t s);
+int sampled_block_size(int m, int R, int prec);
+hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *cores, const long long *coff_dev,
+                       double *out, hipStream_t s);
+hipError_t launch_dense_iteration(const Batch &bt, hipStream_t s, int init);
+hipError_t launch_project(const Batch &bt, hipStream_t s);
+hipError_t launch_retract(const Batch &bt, hipStream_t s);
+hipError_t launch_output(const Batch &bt, hipStream_t s, int init);
+hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode);
+hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *idx_in, const void *values_in,
+                         int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s);
+hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
+hipError_t fill_f32(float *p, long long n, float v, hipStream_t s);
+hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream_t s);
+size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage);
+hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st);
+// one PRGD iteration for every member of the batch (sampled pass, dense stage,
+// truth sweep where a member has truth cores)
+hipError_t enqueue_batch_iterations(const Batch &bt, int iters, hipStream_t s);
+// copy each member's State into out[ns] (device)
+hipError_t launch_gather_state(const Batch &bt, State *out, hipStream_t s);
+}  // namespace prgd
+
+struct prgd_solver_s {
+  prgd::Dev d{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int m = 0, R = 0;
+  std::vector<int> n, r;
+  std::vector<long long> coff;
+  long long N = 0;
+  int64_t numel = 0;
+  prgd::Dev *d_dev = nullptr;  // device copy of d (constant after create)
+  bool has_truth = false;
+  std::vector<void *> allocs;
+  std::vector<size_t> sizes;  // bytes of each allocation
+  size_t bytes = 0;           // device bytes held now
+  size_t peak_bytes = 0;      // largest bytes held at once
+  double last_seconds = 0.0;
+
+  ~prgd_solver_s() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void *p : allocs) (void)hipFree(p);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+  prgd::Batch batch() const { return prgd::Batch{d_dev, &d, 1}; }
+  void release(void *p) {
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == p) {
+        (void)hipFree(p);
+        bytes -= sizes[i];
+        allocs.erase(allocs.begin() + i);
+        sizes.erase(sizes.begin() + i);
+        return;
+      }
+  }
+  template <typename T>
+  hipError_t alloc(T **p, long long count) {
+    void *q = nullptr;
+    const size_t nb = (size_t)std::max<long long>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, nb);
+    if (e == hipSuccess) {
+      allocs.push_back(q);
+      sizes.push_back(nb);
+      bytes += nb;
+      peak_bytes = std::max(peak_bytes, bytes);
+      *p = (T *)q;
+    }
+    return e;
+  }
+};
+
+namespace prgd {
+// prgd_create's body; `validated` skips the host validation (already done).
+prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated);
+// prgd_create's host validation of shapes, ranks, options, index ranges,
+// distinct multi-indices and finite values (host arrays).
+prgd_status validate_desc(const prgd_desc *ds, const int32_t *idx_host, const void *vals_host);
+// Upper bound of the device bytes a solve described by ds holds at any time
+// during creation and iteration (-1 if the descriptor is invalid).
+int64_t solver_footprint(const prgd_desc *ds);
+// Record a failure message for prgd_last_error() and return st.
+prgd_status set_error(prgd_status st, const char *msg);
+}  // namespace prgd

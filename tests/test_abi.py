@@ -84,3 +84,18 @@ def test_status_strings_and_eval_validation():
     with pytest.raises(L.PrgdError):
         L.prgd_eval([3, 3], [1, 2, 1], [np.ones((1, 3, 2)), np.ones((2, 3, 1))],
                     np.array([[0], [5]], dtype=np.int32))
+
+
+def test_server_rejects_bad_arguments_before_device_work():
+    lib = L.load()
+    d = L.prgd_server_desc()
+    d.hbm_budget_bytes = 0
+    d.max_slots = 0
+    h = ctypes.c_void_p()
+    assert lib.prgd_server_create(ctypes.byref(d), ctypes.byref(h)) == L.EINVAL
+    assert lib.prgd_server_create(None, ctypes.byref(h)) == L.EINVAL
+    t = ctypes.c_uint64(0)
+    assert lib.prgd_server_submit(None, None, ctypes.byref(t)) == L.ESTATE
+    assert lib.prgd_server_poll(None, 1, None, None, 0) == L.ESTATE
+    assert lib.prgd_server_wait(None, 1, 0.0) == L.ESTATE
+    assert lib.prgd_server_destroy(None) == L.ESTATE
