@@ -136,16 +136,18 @@ prgd_status prgd_create(const prgd_desc *desc, prgd_solver *out);
 prgd_status prgd_iterate(prgd_solver s, int32_t iters);
 
 /* Number of phases reported by prgd_iterate_profiled. */
-#define PRGD_NPHASES 5
+#define PRGD_NPHASES 6
 
 /* Like prgd_iterate, with HIP events recorded on the solver's stream around
    each phase of every iteration; waits for completion and writes the summed
    elapsed milliseconds per phase into phase_ms[PRGD_NPHASES]:
-     0 sampled pass (evaluation, residual, slice sums, gradient scatter)
-     1 metric-weighted Gram sweeps and tangent components (projection)
-     2 retraction sweeps (right Grams of W_l, truncated left sweep)
-     3 new cores and stopping-test reductions
-     4 relative error against the truth (0 without truth_cores)            */
+     0 sampled pass, main kernel (evaluation, residual, slice sums, gradient
+       scatter)
+     1 sampled pass, reduction of the partials and the weights/step finish
+     2 metric-weighted Gram sweeps and tangent components (projection)
+     3 retraction sweeps (right Grams of W_l, truncated left sweep)
+     4 new cores and stopping-test reductions
+     5 relative error against the truth (0 without truth_cores)            */
 prgd_status prgd_iterate_profiled(prgd_solver s, int32_t iters, double *phase_ms);
 
 /* Wait for the solver's stream. */

@@ -259,8 +259,8 @@ def prgd_iterate(h, iters: int) -> None:
     _check(load().prgd_iterate(h, int(iters)))
 
 
-NPHASES = 5
-PHASES = ["sampled", "project", "retract", "output", "truth"]
+NPHASES = 6
+PHASES = ["sampled_main", "sampled_finish", "project", "retract", "output", "truth"]
 
 
 def prgd_iterate_profiled(h, iters: int) -> dict:

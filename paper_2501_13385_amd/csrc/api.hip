@@ -149,9 +149,9 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
   return PRGD_OK;
 }
 
-hipError_t sampled_pass(prgd_solver s, int diag) {
-  if (s->d.use3) return launch_sampled3(s->batch(), diag, s->stream);
-  return launch_sampled(s->batch(), diag, s->stream);
+hipError_t sampled_pass(prgd_solver s, int diag, hipEvent_t after_main = nullptr) {
+  if (s->d.use3) return launch_sampled3(s->batch(), diag, s->stream, after_main);
+  return launch_sampled(s->batch(), diag, s->stream, after_main);
 }
 
 prgd_status enqueue_iterations(prgd_solver s, int iters) {
@@ -565,16 +565,16 @@ prgd_status prgd_iterate_profiled(prgd_solver s, int32_t iters, double *phase_ms
     hipError_t err = hipSuccess;
     auto chk = [&](hipError_t x) { if (x != hipSuccess && err == hipSuccess) err = x; };
     chk(hipEventRecord(e[0], s->stream));
-    chk(sampled_pass(s, 0));
-    chk(hipEventRecord(e[1], s->stream));
-    chk(launch_project(s->batch(), s->stream));
+    chk(sampled_pass(s, 0, e[1]));
     chk(hipEventRecord(e[2], s->stream));
-    chk(launch_retract(s->batch(), s->stream));
+    chk(launch_project(s->batch(), s->stream));
     chk(hipEventRecord(e[3], s->stream));
-    chk(launch_output(s->batch(), s->stream, 0));
+    chk(launch_retract(s->batch(), s->stream));
     chk(hipEventRecord(e[4], s->stream));
-    if (s->has_truth) chk(launch_truth_sweep(s->batch(), s->stream, 0));
+    chk(launch_output(s->batch(), s->stream, 0));
     chk(hipEventRecord(e[5], s->stream));
+    if (s->has_truth) chk(launch_truth_sweep(s->batch(), s->stream, 0));
+    chk(hipEventRecord(e[6], s->stream));
     if (err != hipSuccess) rc = fail(PRGD_EDEVICE, std::string("launch: ") + hipGetErrorString(err));
   }
   if (rc == PRGD_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = fail(PRGD_EDEVICE, "sync failed");

@@ -193,7 +193,7 @@ static int lds_block(int m, int R, int elem) {
 }
 
 template <typename F, int R>
-static hipError_t launch_sampled_t(const Batch &bt, int diag, hipStream_t s) {
+static hipError_t launch_sampled_t(const Batch &bt, int diag, hipStream_t s, hipEvent_t after_main) {
   const int m = bt.host[0].m;
   const int B = lds_block(m, R, (int)sizeof(F));
   if (B == 0) return hipErrorInvalidValue;
@@ -203,19 +203,20 @@ static hipError_t launch_sampled_t(const Batch &bt, int diag, hipStream_t s) {
   hipLaunchKernelGGL((k_sampled<F, R>), dim3(g, bt.ns), dim3(B), lds, s, bt.dt, diag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (after_main && (e = hipEventRecord(after_main, s)) != hipSuccess) return e;
   return launch_sampled_fin(bt, diag, s);
 }
 
 template <typename F>
-static hipError_t launch_sampled_f(const Batch &bt, int diag, hipStream_t s) {
+static hipError_t launch_sampled_f(const Batch &bt, int diag, hipStream_t s, hipEvent_t ev) {
   switch (bt.host[0].R) {
-    case 2: return launch_sampled_t<F, 2>(bt, diag, s);
-    case 4: return launch_sampled_t<F, 4>(bt, diag, s);
-    case 6: return launch_sampled_t<F, 6>(bt, diag, s);
-    case 8: return launch_sampled_t<F, 8>(bt, diag, s);
-    case 10: return launch_sampled_t<F, 10>(bt, diag, s);
-    case 12: return launch_sampled_t<F, 12>(bt, diag, s);
-    case 16: return launch_sampled_t<F, 16>(bt, diag, s);
+    case 2: return launch_sampled_t<F, 2>(bt, diag, s, ev);
+    case 4: return launch_sampled_t<F, 4>(bt, diag, s, ev);
+    case 6: return launch_sampled_t<F, 6>(bt, diag, s, ev);
+    case 8: return launch_sampled_t<F, 8>(bt, diag, s, ev);
+    case 10: return launch_sampled_t<F, 10>(bt, diag, s, ev);
+    case 12: return launch_sampled_t<F, 12>(bt, diag, s, ev);
+    case 16: return launch_sampled_t<F, 16>(bt, diag, s, ev);
     default: return hipErrorInvalidValue;
   }
 }
@@ -224,9 +225,9 @@ int sampled_block_size(int m, int R, int prec) {
   return lds_block(m, R, prec == PREC_MIXED ? 4 : 8);
 }
 
-hipError_t launch_sampled(const Batch &bt, int diag, hipStream_t s) {
-  if (bt.host[0].prec == PREC_MIXED) return launch_sampled_f<float>(bt, diag, s);
-  return launch_sampled_f<double>(bt, diag, s);
+hipError_t launch_sampled(const Batch &bt, int diag, hipStream_t s, hipEvent_t after_main) {
+  if (bt.host[0].prec == PREC_MIXED) return launch_sampled_f<float>(bt, diag, s, after_main);
+  return launch_sampled_f<double>(bt, diag, s, after_main);
 }
 
 hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *cores, const long long *coff_dev,

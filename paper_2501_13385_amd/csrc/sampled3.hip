@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) k_sampled3_reduce(const Dev *__restrict__
 hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s);
 
 template <typename F, int R>
-static hipError_t launch3_t(const Batch &bt, int diag, hipStream_t st) {
+static hipError_t launch3_t(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main) {
   size_t lds = 0;
   int nwg = 1, nred = 1;
   const int stage = bt.host[0].q3.stage;
@@ -298,6 +298,7 @@ static hipError_t launch3_t(const Batch &bt, int diag, hipStream_t st) {
     hipLaunchKernelGGL((k_sampled3<F, R, NT, false>), dim3(nwg, bt.ns), dim3(NT), lds, st, bt.dt, diag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (after_main && (e = hipEventRecord(after_main, st)) != hipSuccess) return e;
   hipLaunchKernelGGL((k_sampled3_reduce<F, R>), dim3(nred, bt.ns), dim3(256), 0, st, bt.dt, diag);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -305,15 +306,15 @@ static hipError_t launch3_t(const Batch &bt, int diag, hipStream_t st) {
 }
 
 template <typename F>
-static hipError_t launch3_f(const Batch &bt, int diag, hipStream_t st) {
+static hipError_t launch3_f(const Batch &bt, int diag, hipStream_t st, hipEvent_t ev) {
   switch (bt.host[0].R) {
-    case 2: return launch3_t<F, 2>(bt, diag, st);
-    case 4: return launch3_t<F, 4>(bt, diag, st);
-    case 6: return launch3_t<F, 6>(bt, diag, st);
-    case 8: return launch3_t<F, 8>(bt, diag, st);
-    case 10: return launch3_t<F, 10>(bt, diag, st);
-    case 12: return launch3_t<F, 12>(bt, diag, st);
-    case 16: return launch3_t<F, 16>(bt, diag, st);
+    case 2: return launch3_t<F, 2>(bt, diag, st, ev);
+    case 4: return launch3_t<F, 4>(bt, diag, st, ev);
+    case 6: return launch3_t<F, 6>(bt, diag, st, ev);
+    case 8: return launch3_t<F, 8>(bt, diag, st, ev);
+    case 10: return launch3_t<F, 10>(bt, diag, st, ev);
+    case 12: return launch3_t<F, 12>(bt, diag, st, ev);
+    case 16: return launch3_t<F, 16>(bt, diag, st, ev);
     default: return hipErrorInvalidValue;
   }
 }
@@ -328,9 +329,9 @@ size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage) {
 
 int sampled3_kseg() { return KSEG; }
 
-hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st) {
-  if (bt.host[0].prec == PREC_MIXED) return launch3_f<float>(bt, diag, st);
-  return launch3_f<double>(bt, diag, st);
+hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main) {
+  if (bt.host[0].prec == PREC_MIXED) return launch3_f<float>(bt, diag, st, after_main);
+  return launch3_f<double>(bt, diag, st, after_main);
 }
 
 }  // namespace prgd

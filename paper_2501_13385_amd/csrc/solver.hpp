@@ -11,7 +11,8 @@
 #include "prgd_internal.hpp"
 
 namespace prgd {
-hipError_t launch_sampled(const Batch &bt, int diag, hipStream_t s);
+// the sampled pass; `after_main` (may be null) is recorded after its main kernel
+hipError_t launch_sampled(const Batch &bt, int diag, hipStream_t s, hipEvent_t after_main = nullptr);
 int sampled_block_size(int m, int R, int prec);
 hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *cores, const long long *coff_dev,
                        double *out, hipStream_t s);
@@ -26,7 +27,7 @@ hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t s);
 hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream_t s);
 size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage);
-hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st);
+hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main = nullptr);
 // one PRGD iteration for every member of the batch (sampled pass, dense stage,
 // truth sweep where a member has truth cores)
 hipError_t enqueue_batch_iterations(const Batch &bt, int iters, hipStream_t s);
