@@ -84,24 +84,4 @@ __device__ inline void reduce_partials(const double *part, int nb, int ne, doubl
   __syncthreads();
 }
 
-// "Last block" pattern: every block publishes its partial results, then
-// increments a counter; the block that brings the counter to gridDim.x sees
-// all partials (release/acquire fences at device scope) and finishes the
-// reduction.  The last block resets the counter for the next launch.
-__device__ inline bool arrive_last(unsigned *counter) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0) atomicExch(counter, 0u);
-  }
-  return last != 0;
-}
-
 }  // namespace prgd

@@ -201,9 +201,9 @@ __global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, i
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
-  const bool ok1 = block_spd_inverse(GLj, R, d.r[j], sm_slot(d, j, S_GLI), R, R, smem);
-  const bool ok2 = block_spd_inverse(Hb, R, d.r[m - j], sm_slot(d, m - j, S_HI), R, R, smem);
-  if (threadIdx.x == 0 && !(ok1 && ok2)) bad = 1;
+  const bool ok = block_spd_inverse_pair(GLj, R, d.r[j], sm_slot(d, j, S_GLI), Hb, R, d.r[m - j],
+                                         sm_slot(d, m - j, S_HI), R, R, smem);
+  if (threadIdx.x == 0 && !ok) bad = 1;
   __syncthreads();
   if (bad) {
     if (threadIdx.x == 0) {

@@ -125,13 +125,31 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
     ws2 = (F)0;
   };
 
+  // software pipeline: the next batch's indices and value are in flight while
+  // the current batch is processed
+  int nx1 = 0, nx2 = -1, nx3 = 0;
+  F ny = (F)0;
+  if (ws + lane < we) {
+    nx1 = ix1[ws + lane];
+    nx2 = ix2[ws + lane];
+    nx3 = ix3[ws + lane];
+    ny = y[ws + lane];
+  }
   for (long long jb = ws; jb < we; jb += 64) {
     const long long j = jb + lane;
     const bool act = j < we;
-    const int x1 = act ? ix1[j] : 0;
-    const int x2 = act ? ix2[j] : -1;
-    const int x3 = act ? ix3[j] : 0;
-    const F yv = act ? y[j] : (F)0;
+    const int x1 = nx1, x2 = act ? nx2 : -1, x3 = nx3;
+    const F yv = ny;
+    {
+      const long long jn = j + 64;
+      nx2 = -1;
+      if (jn < we) {
+        nx1 = ix1[jn];
+        nx2 = ix2[jn];
+        nx3 = ix3[jn];
+        ny = y[jn];
+      }
+    }
     unsigned long long pending = __ballot(act);
     while (pending) {
       const int first = __ffsll((long long)pending) - 1;

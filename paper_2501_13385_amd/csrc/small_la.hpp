@@ -13,47 +13,6 @@
 
 namespace prgd {
 
-// Inverse of the SPD leading n x n block of A (ld lda) by Gauss-Jordan
-// elimination on [A | I] (no pivoting needed for SPD), written to Ainv (ld ldo)
-// with zeros in the rest of its R x R block.  scratch: 2 n n + 3 n doubles.
-// Returns false (in every thread) if a pivot is not positive.
-__device__ inline bool block_spd_inverse(const double *A, int lda, int n, double *Ainv, int ldo, int R,
-                                         double *scratch) {
-  __shared__ int fail;
-  const int t = threadIdx.x, nt = blockDim.x, w = 2 * n;
-  double *M = scratch, *f = scratch + n * w, *prow = f + n;
-  for (int e = t; e < n * w; e += nt) {
-    const int i = e / w, j = e % w;
-    M[e] = (j < n) ? A[i * lda + j] : (j - n == i ? 1.0 : 0.0);
-  }
-  if (t == 0) fail = 0;
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    // snapshot the pivot column and row, so the update phase reads no entry it writes
-    if (t < n) f[t] = M[t * w + k];
-    else if (t >= 64 && t < 64 + w) prow[t - 64] = M[k * w + (t - 64)];
-    if (t == 0) {
-      const double pk = M[k * w + k];
-      if (!(pk > 0.0) || !isfinite(pk)) fail = 1;
-    }
-    __syncthreads();
-    if (fail) return false;
-    const double pinv = 1.0 / f[k];
-    for (int e = t; e < n * w; e += nt) {
-      const int i = e / w, j = e % w;
-      if (i == k) M[e] = prow[j] * pinv;
-      else M[e] -= f[i] * pinv * prow[j];
-    }
-    __syncthreads();
-  }
-  for (int e = t; e < R * R; e += nt) {
-    const int i = e / R, j = e % R;
-    Ainv[i * ldo + j] = (i < n && j < n) ? 0.5 * (M[i * w + n + j] + M[j * w + n + i]) : 0.0;
-  }
-  __syncthreads();
-  return true;
-}
-
 // Pivoted Cholesky of a symmetric positive semidefinite n x n matrix A (ld n,
 // destroyed): F (ld n) gets columns 0..rank-1 with F F^T = A up to pivots
 // below n * 2.3e-16 * max diag.  Returns the rank.
@@ -226,6 +185,72 @@ __device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, 
   __syncthreads();
   for (int e = t; e < n * n; e += nt) V[e] = Vs[e];
   __syncthreads();
+}
+
+
+// Inverses of two SPD matrices by Gauss-Jordan elimination on [A | I] (no
+// pivoting needed for SPD), the two eliminations advancing in lockstep.  The
+// working matrices are double-buffered: every step reads the previous state
+// from one LDS buffer and writes the next to the other, so a step costs one
+// barrier: A1 (n1 x n1, ld lda1) -> O1, A2 (n2 x n2, ld lda2) -> O2, each
+// written with ld ldo and zeros in the rest of its R x R block.
+// scratch: 2 * 2 * (n1 * 2 n1 + n2 * 2 n2) doubles.  Returns false if a pivot
+// of either matrix is not positive.
+__device__ inline bool block_spd_inverse_pair(const double *A1, int lda1, int n1, double *O1, const double *A2,
+                                              int lda2, int n2, double *O2, int ldo, int R, double *scratch) {
+  __shared__ int bad;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int w1 = 2 * n1, w2 = 2 * n2, s1 = n1 * w1, s2 = n2 * w2, tot = s1 + s2;
+  double *buf[2] = {scratch, scratch + tot};
+  for (int e = t; e < tot; e += nt) {
+    double v;
+    if (e < s1) {
+      const int i = e / w1, j = e % w1;
+      v = (j < n1) ? A1[i * lda1 + j] : (j - n1 == i ? 1.0 : 0.0);
+    } else {
+      const int f = e - s1, i = f / w2, j = f % w2;
+      v = (j < n2) ? A2[i * lda2 + j] : (j - n2 == i ? 1.0 : 0.0);
+    }
+    buf[0][e] = v;
+  }
+  if (t == 0) bad = 0;
+  __syncthreads();
+  const int nmax = n1 > n2 ? n1 : n2;
+  int cur = 0;
+  for (int k = 0; k < nmax; ++k) {
+    const double *M = buf[cur];
+    double *Mn = buf[cur ^ 1];
+    for (int e = t; e < tot; e += nt) {
+      const bool first = e < s1;
+      const int w = first ? w1 : w2, n = first ? n1 : n2, base = first ? 0 : s1;
+      const int f = e - base, i = f / w, j = f % w;
+      if (k >= n) {
+        Mn[e] = M[e];
+        continue;
+      }
+      const double pk = M[base + k * w + k];
+      const double pj = M[base + k * w + j];
+      if (i == k) {
+        Mn[e] = pj / pk;
+      } else {
+        const double fi = M[base + i * w + k];
+        Mn[e] = M[e] - fi * (pj / pk);
+      }
+      if (j == k && i == k && (!(pk > 0.0) || !isfinite(pk))) bad = 1;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const double *M = buf[cur];
+  for (int e = t; e < 2 * R * R; e += nt) {
+    const bool first = e < R * R;
+    const int f = first ? e : e - R * R, i = f / R, j = f % R;
+    const int n = first ? n1 : n2, w = first ? w1 : w2, base = first ? 0 : s1;
+    double *O = first ? O1 : O2;
+    O[i * ldo + j] = (i < n && j < n) ? 0.5 * (M[base + i * w + n + j] + M[base + j * w + n + i]) : 0.0;
+  }
+  __syncthreads();
+  return bad == 0;
 }
 
 }  // namespace prgd
