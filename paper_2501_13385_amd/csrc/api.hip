@@ -76,6 +76,39 @@ void unpack_cores(int m, const int *n, const int *r, int R, const double *src, d
 
 namespace {
 
+// Any-order sampled pass: the modes whose gradient and slice sums are
+// accumulated per workgroup in LDS (smallest first, while they fit next to
+// the interface stack), their offsets in the private area, and the grid.
+void sampled_plan(int m, const int *n, int R, int prec, long long N, int *off, long long &tot, int &nbs) {
+  const int B = sampled_block_size(m, R, prec);
+  const size_t f = prec == PREC_MIXED ? sizeof(float) : sizeof(double);
+  const size_t stack = (size_t)(m - 1) * R * B * f;
+  const size_t budget = (size_t)160 * 1024 - stack - 1024;
+  std::vector<std::pair<long long, int>> sz;
+  for (int k = 0; k < m; ++k) {
+    const long long w = (k == 0 || k == m - 1) ? R : (long long)R * R;
+    sz.push_back({(long long)n[k] * (w + 1), k});
+  }
+  std::sort(sz.begin(), sz.end());
+  tot = 0;
+  for (int k = 0; k < m; ++k) off[k] = -1;
+  for (auto &p : sz)
+    if ((size_t)(tot + p.first) * f <= budget) {
+      off[p.second] = (int)tot;
+      tot += p.first;
+    }
+  long long nb = (N + B - 1) / B;
+  if (tot > 0) {
+    // fewer, longer workgroups when each one writes a private area
+    nb = (N + 4LL * B - 1) / (4LL * B);
+    nb = std::min<long long>(nb, 1024);
+    while (nb > 1 && (size_t)nb * tot * f > ((size_t)64 << 20)) nb /= 2;
+  } else {
+    nb = std::min<long long>(nb, 2048);
+  }
+  nbs = (int)std::max<long long>(nb, 1);
+}
+
 prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *vals, int64_t &numel) {
   const int m = ds->order;
   if (m < 2 || m > MAXM) return fail(m < 2 ? PRGD_EINVAL : PRGD_ENOTSUP, "order must be in [2, 32]");
@@ -223,6 +256,16 @@ int64_t solver_footprint(const prgd_desc *ds) {
   b += f * N;                                         // values in the working precision
   b += f * (int64_t)(ds->mode_sizes[0] + ds->mode_sizes[m - 1]) * R;   // boundary vectors
   if (ds->truth_cores) b += 8 * pn;
+  {                                                   // any-order private partials (upper bound)
+    int off[MAXM];
+    long long tot = 0;
+    int nbs = 1;
+    std::vector<int> nv(ds->mode_sizes, ds->mode_sizes + m);
+    if (sampled_block_size(m, R, ds->precision) > 0) {
+      sampled_plan(m, nv.data(), R, ds->precision, N, off, tot, nbs);
+      b += (int64_t)nbs * tot * f;
+    }
+  }
   if (m == 3) {                                       // order-3 tables (upper bound)
     const int64_t L = (int64_t)(ds->mode_sizes[0] + ds->mode_sizes[2]) * (R + 1);
     const int64_t segw = (int64_t)R * R + 1;
@@ -513,12 +556,23 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     q.ovf = povf;
     d.use3 = 1;
   }
-  // sampled-pass grid: enough waves to fill 256 CUs
-  {
-    const int B = sampled_block_size(m, R, d.prec);
-    long long nb = (N + B - 1) / B;
-    nb = std::min<long long>(nb, 2048);
-    d.nb_sampled = (int)std::max<long long>(nb, 1);
+  // any-order sampled pass: grid, and the modes accumulated per workgroup in LDS
+  for (int k = 0; k < MAXM; ++k) d.priv_off[k] = -1;
+  d.priv_len = 0;
+  d.part_priv = nullptr;
+  d.nb_sampled = 1;
+  if (!d.use3) {
+    long long tot = 0;
+    int nbs = 1;
+    sampled_plan(m, s->n.data(), R, d.prec, N, d.priv_off, tot, nbs);
+    d.priv_len = (int)tot;
+    d.nb_sampled = nbs;
+    if (tot > 0) {
+      unsigned char *pp = nullptr;
+      const long long f = mixed ? 4 : 8;
+      if (!A(s->alloc(&pp, (long long)nbs * tot * f))) return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+      d.part_priv = pp;
+    }
   }
   if (!A(s->alloc(&s->d_dev, 1))) return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
   if (hipMemcpyAsync(s->d_dev, &d, sizeof(Dev), hipMemcpyHostToDevice, s->stream) != hipSuccess)

@@ -131,6 +131,12 @@ struct Dev {
   int hist_cap;
   int use3;                    // 1: order-3 grouped sampled pass with the tables in q3
   int nb_sampled;              // grid of the any-order sampled pass
+  // any-order sampled pass: modes whose gradient and slice sums fit in LDS are
+  // accumulated per workgroup there (priv_off[k] = offset in the private
+  // area, -1: global atomics) and reduced in a fixed order afterwards
+  int priv_off[MAXM];
+  int priv_len;                // elements of the private area per workgroup
+  void *part_priv;             // [nb_sampled][priv_len] in the working precision
   S3 q3;
 };
 

@@ -21,7 +21,28 @@ __device__ inline void atomic_add(F *p, F v) {
   atomicAdd(p, v);
 }
 
-// One thread per sample.  The right interface vectors rho_k (k = m..2) are
+// Per-mode gradient width in the private area: row 0 of the first core, column
+// 0 of the last core, the whole R x R slice of a middle core.
+__host__ __device__ inline int priv_width(int k, int m, int R) { return (k == 0 || k == m - 1) ? R : R * R; }
+
+// Gradient entry i (compact index within the mode's width) of slice x of
+// core k: into the workgroup's LDS area when the mode is privatised, else a
+// global atomic into the padded gradient.
+template <typename F>
+__device__ inline void scatter(const Dev &d, F *lp, F *Yg, int k, int x, int i, long long gofs, F v) {
+  const int po = d.priv_off[k];
+  if (po >= 0) atomicAdd(&lp[po + x * priv_width(k, d.m, d.R) + i], v);
+  else atomic_add(&Yg[gofs], v);
+}
+template <typename F>
+__device__ inline void scatter_s(const Dev &d, F *lp, F *sacc, int k, int x, F v) {
+  const int po = d.priv_off[k];
+  if (po >= 0) atomicAdd(&lp[po + d.n[k] * priv_width(k, d.m, d.R) + x], v);
+  else atomic_add(&sacc[d.soff[k] + x], v);
+}
+
+// One thread per sample, each workgroup a contiguous chunk of Omega (grouped
+// by the sort mode).  The right interface vectors rho_k (k = m..2) are
 // computed first and kept in LDS (thread-interleaved, conflict-free); the
 // left vector is then carried left to right while scattering.
 template <typename F, int R>
@@ -39,8 +60,13 @@ __global__ void __launch_bounds__(256) k_sampled(const Dev *__restrict__ dt, int
   const long long N = d.N;
   const int B = blockDim.x, t = threadIdx.x;
   constexpr int RR = R * R;
+  F *lp = stack + (long long)(m - 1) * R * B;     // private accumulators
+  for (int i = t; i < d.priv_len; i += B) lp[i] = (F)0;
+  __syncthreads();
+  const long long chunk = (N + nbs - 1) / nbs;
+  const long long jlo = (long long)blockIdx.x * chunk, jhi = min(N, jlo + chunk);
   double rsq = 0.0;
-  for (long long j = (long long)blockIdx.x * B + t; j < N; j += (long long)nbs * B) {
+  for (long long j = jlo + t; j < jhi; j += B) {
     F rho[R];
     {
       const int x = d.idx[(long long)(m - 1) * N + j];
@@ -81,15 +107,15 @@ __global__ void __launch_bounds__(256) k_sampled(const Dev *__restrict__ dt, int
     const F r2 = res * res;
     rsq += (double)r2;
     {
-      F *yg = Yg + d.coff[0] + (long long)x0 * RR;
+      const long long g0 = d.coff[0] + (long long)x0 * RR;
 #pragma unroll
-      for (int b = 0; b < R; ++b) atomic_add(&yg[b], res * rho[b]);
-      atomic_add(&sacc[d.soff[0] + x0], r2);
+      for (int b = 0; b < R; ++b) scatter(d, lp, Yg, 0, x0, b, g0 + b, res * rho[b]);
+      scatter_s(d, lp, sacc, 0, x0, r2);
     }
     for (int k = 1; k <= m - 2; ++k) {
       const int x = d.idx[(long long)k * N + j];
       const F *sl = cores + d.coff[k] + (long long)x * RR;
-      F *yg = Yg + d.coff[k] + (long long)x * RR;
+      const long long gk = d.coff[k] + (long long)x * RR;
       F rr[R];
 #pragma unroll
       for (int b = 0; b < R; ++b) rr[b] = stack[(k * R + b) * B + t];
@@ -97,7 +123,7 @@ __global__ void __launch_bounds__(256) k_sampled(const Dev *__restrict__ dt, int
       for (int a = 0; a < R; ++a) {
         const F ra = res * l[a];
 #pragma unroll
-        for (int b = 0; b < R; ++b) atomic_add(&yg[a * R + b], ra * rr[b]);
+        for (int b = 0; b < R; ++b) scatter(d, lp, Yg, k, x, a * R + b, gk + a * R + b, ra * rr[b]);
       }
       F nl[R];
 #pragma unroll
@@ -109,19 +135,55 @@ __global__ void __launch_bounds__(256) k_sampled(const Dev *__restrict__ dt, int
       }
 #pragma unroll
       for (int b = 0; b < R; ++b) l[b] = nl[b];
-      atomic_add(&sacc[d.soff[k] + x], r2);
+      scatter_s(d, lp, sacc, k, x, r2);
     }
     {
       const int x = d.idx[(long long)(m - 1) * N + j];
-      F *yg = Yg + d.coff[m - 1] + (long long)x * RR;
+      const long long gl = d.coff[m - 1] + (long long)x * RR;
 #pragma unroll
-      for (int a = 0; a < R; ++a) atomic_add(&yg[a * R], res * l[a]);
-      atomic_add(&sacc[d.soff[m - 1] + x], r2);
+      for (int a = 0; a < R; ++a) scatter(d, lp, Yg, m - 1, x, a, gl + a * R, res * l[a]);
+      scatter_s(d, lp, sacc, m - 1, x, r2);
     }
   }
   __shared__ double sbuf[16];
-  const double bs = block_sum(rsq, sbuf);
+  const double bs = block_sum(rsq, sbuf);     // ends with a barrier: lp is complete
   if (threadIdx.x == 0) d.part[blockIdx.x] = bs;
+  F *pp = (F *)d.part_priv + (long long)blockIdx.x * d.priv_len;
+  for (int i = t; i < d.priv_len; i += B) pp[i] = lp[i];
+}
+
+// Sum the workgroups' private accumulators in a fixed order into the padded
+// gradient and the slice sums (one output per thread).
+template <typename F, int R>
+__global__ void __launch_bounds__(256) k_sampled_priv_reduce(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= d.priv_len || (!diag && d.st->done)) return;
+  const int m = d.m, nbs = d.nb_sampled;
+  constexpr int RR = R * R;
+  const F *pp = (const F *)d.part_priv;
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int b = 0;
+  for (; b + 8 <= nbs; b += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += (double)pp[(long long)(b + u) * d.priv_len + o];
+  }
+  for (; b < nbs; ++b) a[0] += (double)pp[(long long)b * d.priv_len + o];
+  const double v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  int k = -1;      // the privatised mode whose area holds o (largest offset <= o)
+  for (int kk = 0; kk < m; ++kk) {
+    const int po = d.priv_off[kk];
+    if (po >= 0 && po <= o && (k < 0 || po > d.priv_off[k])) k = kk;
+  }
+  const int W = priv_width(k, m, R), rel = o - d.priv_off[k];
+  if (rel < d.n[k] * W) {
+    const int x = rel / W, i = rel % W;
+    long long g = d.coff[k] + (long long)x * RR;
+    g += (k == m - 1 && k != 0) ? (long long)i * R : (long long)i;
+    ((F *)d.Y)[g] = (F)v;
+  } else {
+    ((F *)d.s)[d.soff[k] + rel - d.n[k] * W] = (F)v;
+  }
 }
 
 // finish of the sampled pass (one block): total ||R||^2 from the per-block
@@ -197,13 +259,20 @@ static hipError_t launch_sampled_t(const Batch &bt, int diag, hipStream_t s, hip
   const int m = bt.host[0].m;
   const int B = lds_block(m, R, (int)sizeof(F));
   if (B == 0) return hipErrorInvalidValue;
-  int g = 1;
-  for (int i = 0; i < bt.ns; ++i) g = g > bt.host[i].nb_sampled ? g : bt.host[i].nb_sampled;
-  const size_t lds = (size_t)(m - 1) * R * sizeof(F) * B;
+  int g = 1, pl = 0;
+  for (int i = 0; i < bt.ns; ++i) {
+    g = g > bt.host[i].nb_sampled ? g : bt.host[i].nb_sampled;
+    pl = pl > bt.host[i].priv_len ? pl : bt.host[i].priv_len;
+  }
+  const size_t lds = ((size_t)(m - 1) * R * B + (size_t)pl) * sizeof(F);
   hipLaunchKernelGGL((k_sampled<F, R>), dim3(g, bt.ns), dim3(B), lds, s, bt.dt, diag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (after_main && (e = hipEventRecord(after_main, s)) != hipSuccess) return e;
+  if (pl > 0) {
+    hipLaunchKernelGGL((k_sampled_priv_reduce<F, R>), dim3((pl + 255) / 256, bt.ns), dim3(256), 0, s, bt.dt, diag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   return launch_sampled_fin(bt, diag, s);
 }
 
