@@ -65,7 +65,18 @@ typedef int32_t prgd_status;
 /* step policy (section 3.2.2 and Theorem 1) */
 #define PRGD_STEP_THEORY 0   /* alpha_l = step * eps_l^{1/2} / p, p = N / (n_1...n_m);
                                 Theorem 1 uses step = 1.001                                 */
-#define PRGD_STEP_CONST  1   /* alpha_l = step for every l; requires eps_fixed > 0          */
+#define PRGD_STEP_CONST  1   /* alpha_l = step for every l; with the data-driven metric it
+                                requires eps_fixed > 0                                      */
+#define PRGD_STEP_ADAPTIVE 2 /* steepest step along the direction in the tangent space
+                                (equation of the PRGD step size, section 3.2.2; for the
+                                Euclidean metric the RGD step of section 3.1):
+                                alpha_l = ||xi||_W^2 / ||P_Omega xi||_F^2, evaluated as
+                                <G_l, xi> / ||P_Omega xi||^2 by a second pass over Omega  */
+/* metric of the tangent space */
+#define PRGD_METRIC_DATA      0 /* data-driven metric G_{l,i} = eps I + diag(M_i M_i^T)
+                                   (section 3.2.1): PRGD                                    */
+#define PRGD_METRIC_EUCLIDEAN 1 /* Euclidean metric: Riemannian gradient descent (RGD,
+                                   section 3.1); THEORY then means alpha_l = step / p       */
 /* stopping rule, tested with tolerance tol */
 #define PRGD_STOP_RESIDUAL 0 /* ||P_Omega(T_l) - y||_2 / ||y||_2 <= tol, tested on T_l      */
 #define PRGD_STOP_CHANGE   1 /* ||T_{l+1} - T_l||_F <= tol * max(1, ||T_l||_F)
@@ -99,6 +110,7 @@ typedef struct {
   int32_t sort_mode;           /* mode (0-based) by which Omega is grouped on the device;
                                   -1 chooses the mode with the largest r_{k-1} r_k         */
   void *stream;                /* hipStream_t to run on; NULL: a stream owned by the solver */
+  int32_t metric;              /* PRGD_METRIC_* (0 = PRGD)                                  */
 } prgd_desc;
 
 /* One row of the per-iteration record kept on the device. */

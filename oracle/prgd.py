@@ -123,12 +123,15 @@ def scale_mode(core: np.ndarray, w: np.ndarray) -> np.ndarray:
 
 
 def tangent_direction(cores: Sequence[np.ndarray], idx: np.ndarray, r: np.ndarray,
-                      eps: Optional[float] = None) -> Direction:
+                      eps: Optional[float] = None, metric: str = "data") -> Direction:
     """The Riemannian gradient under the data-driven metric, ``P~_T W^{-1} G_l``.
 
     Steps (section 3.3 and Lemma 3):
 
     1. ``g_i = eps + s_i`` (metric diagonals); ``eps = ||G||_vee^2`` unless given.
+       With ``metric="euclidean"`` every ``g_i`` is 1, so ``W`` is the identity and
+       the direction is the Euclidean tangent projection of ``G`` used by RGD
+       (section 3.1).
     2. ``W^{1/2} T = [T_1 x_2 g_1^{1/(4m)}, ...]`` (Proposition 1), then its
        left-orthogonal decomposition ``[T^_1, ..., T^_m]`` by Householder QR.
     3. ``W^{-1/2} G`` on Omega: ``R_j prod_k g_k(x_k)^{-1/(4m)}``.
@@ -144,7 +147,12 @@ def tangent_direction(cores: Sequence[np.ndarray], idx: np.ndarray, r: np.ndarra
     s = slice_norms(idx, r, shape)
     if eps is None:
         eps = eps_vee(s)
-    g = metric_diagonals(s, eps)
+    if metric == "euclidean":
+        g = [np.ones_like(x) for x in s]
+    elif metric == "data":
+        g = metric_diagonals(s, eps)
+    else:
+        raise ValueError(metric)
     e = 1.0 / (4.0 * m)
     shat = [scale_mode(cores[k], g[k] ** e) for k in range(m)]
     that, _ = tt.left_orthogonalize(shat)
@@ -255,6 +263,7 @@ class Policy:
     stop_rule: str = "residual"      # "residual" | "change" | "error"
     tol: float = 1e-10
     max_iter: int = 500
+    metric: str = "data"             # "data" (PRGD, section 3.2.1) | "euclidean" (RGD, section 3.1)
 
 
 @dataclasses.dataclass
@@ -280,9 +289,14 @@ def prgd_step(cores: Sequence[np.ndarray], idx: np.ndarray, y: np.ndarray, polic
     info["eps"] = eps
     if eps_vee(s) == 0.0:
         return None, info
-    d = tangent_direction(cores, idx, r, eps)
+    euclid = policy.metric == "euclidean"
+    if euclid:
+        eps = 1.0        # the Euclidean metric has no eps
+        info["eps"] = eps
+    d = tangent_direction(cores, idx, r, eps, policy.metric)
     p = sampling_ratio(idx.shape[1], shape)
     if policy.step_rule == "theory":
+        # RGD's constant step in the same units: c / p (eps = 1)
         alpha = step_theory(policy.c, eps, p)
     elif policy.step_rule == "const":
         alpha = float(policy.alpha)

@@ -20,7 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libprgd.so")
 OK, NOT_CONVERGED, PENDING = 0, 1, 2
 EINVAL, EDUPLICATE, ENOMEM, EDEVICE, EBREAKDOWN, ESTATE, ENOTSUP = -1, -2, -3, -4, -5, -6, -7
 PREC = {"fp64": 0, "mixed": 1}
-STEP = {"theory": 0, "const": 1}
+STEP = {"theory": 0, "const": 1, "adaptive": 2}
+METRIC = {"data": 0, "euclidean": 1}
 STOP = {"residual": 0, "change": 1, "error": 2, "none": 3}
 
 
@@ -51,6 +52,7 @@ class prgd_desc(C.Structure):
         ("max_iter", C.c_int32),
         ("sort_mode", C.c_int32),
         ("stream", C.c_void_p),
+        ("metric", C.c_int32),
     ]
 
 
@@ -193,7 +195,7 @@ def _ptr_of(a):
 
 def _make_desc(shape, ranks, indices, values, init_cores, *, truth_cores=None, precision="fp64",
                step_policy="theory", step=1.0, eps_fixed=0.0, stop_rule="residual", tol=1e-10,
-               max_iter=500, sort_mode=-1, stream=None):
+               max_iter=500, sort_mode=-1, stream=None, metric="data"):
     """prgd_desc for the arguments, plus the objects that must outlive the call."""
     m = len(shape)
     keep = []
@@ -240,6 +242,7 @@ def _make_desc(shape, ranks, indices, values, init_cores, *, truth_cores=None, p
     d.max_iter = int(max_iter)
     d.sort_mode = int(sort_mode)
     d.stream = stream
+    d.metric = METRIC[metric]
     keep += [ns, rs]
     return d, keep
 

@@ -128,9 +128,11 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
   if (!(ds->tol >= 0.0) || ds->max_iter < 0) return fail(PRGD_EINVAL, "tol must be >= 0 and max_iter >= 0");
   if (!(ds->step > 0.0) || !std::isfinite(ds->step)) return fail(PRGD_EINVAL, "step must be positive");
   if (ds->precision != PRGD_PREC_FP64 && ds->precision != PRGD_PREC_MIXED) return fail(PRGD_EINVAL, "precision");
-  if (ds->step_policy != PRGD_STEP_THEORY && ds->step_policy != PRGD_STEP_CONST)
+  if (ds->step_policy != PRGD_STEP_THEORY && ds->step_policy != PRGD_STEP_CONST &&
+      ds->step_policy != PRGD_STEP_ADAPTIVE)
     return fail(PRGD_EINVAL, "step_policy");
-  if (ds->step_policy == PRGD_STEP_CONST && !(ds->eps_fixed > 0.0))
+  if (ds->metric != PRGD_METRIC_DATA && ds->metric != PRGD_METRIC_EUCLIDEAN) return fail(PRGD_EINVAL, "metric");
+  if (ds->step_policy == PRGD_STEP_CONST && ds->metric == PRGD_METRIC_DATA && !(ds->eps_fixed > 0.0))
     return fail(PRGD_EINVAL, "the constant step policy needs eps_fixed > 0");
   if (ds->stop_rule < PRGD_STOP_RESIDUAL || ds->stop_rule > PRGD_STOP_NONE) return fail(PRGD_EINVAL, "stop_rule");
   if (ds->stop_rule == PRGD_STOP_ERROR && !ds->truth_cores) return fail(PRGD_EINVAL, "STOP_ERROR needs truth_cores");
@@ -380,6 +382,7 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   d.R = R;
   d.prec = ds->precision;
   d.step_policy = ds->step_policy;
+  d.metric = ds->metric;
   d.stop_rule = ds->stop_rule;
   d.max_iter = ds->max_iter;
   d.N = N;

@@ -800,6 +800,8 @@ __global__ void __launch_bounds__(1024) k_cross_fin(const Dev *__restrict__ dt, 
 // ---------------------------------------------------------------------------
 // launchers (grids sized for the largest member of the batch)
 // ---------------------------------------------------------------------------
+hipError_t launch_adaptive_step(const Batch &bt, hipStream_t s);
+
 template <typename Fn>
 static int max_over(const Batch &b, Fn f) {
   int v = 1;
@@ -817,7 +819,9 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
   }
   const int g = max_over(bt, [&](const Dev &d) { return d.blk_off[m]; });
   hipLaunchKernelGGL(k_tangent, dim3(g, ns), dim3(256), 0, s, bt.dt);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_adaptive_step(bt, s);    // members with the adaptive step only
 }
 
 // phase 2: retraction sweeps (right Grams of W_l, then the truncated left sweep)

@@ -40,7 +40,8 @@ enum Slot {
 };
 
 enum Precision { PREC_FP64 = 0, PREC_MIXED = 1 };
-enum StepPolicy { STEP_THEORY = 0, STEP_CONST = 1 };
+enum StepPolicy { STEP_THEORY = 0, STEP_CONST = 1, STEP_ADAPTIVE = 2 };
+enum Metric { METRIC_DATA = 0, METRIC_EUCLIDEAN = 1 };
 enum StopRule { STOP_RESIDUAL = 0, STOP_CHANGE = 1, STOP_ERROR = 2, STOP_NONE = 3 };
 
 // counters used by the "last block finishes the reduction" pattern
@@ -97,6 +98,7 @@ struct Dev {
   int R;                       // padded slice dimension
   int prec;
   int step_policy;
+  int metric;                  // Metric
   int stop_rule;
   int max_iter;
   int sort_mode;

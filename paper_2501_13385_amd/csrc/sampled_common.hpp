@@ -6,9 +6,13 @@
 
 namespace prgd {
 
-// Finish the pass in the last block: total ||R||^2, residual stopping test,
+// Finish the pass in one block: total ||R||^2, residual stopping test,
 // eps_l = max_{k,x} s_k(x) (= ||G_l||_vee^2), metric factors
-// omega_k(x) = (1 + s_k(x)/eps)^{1/(2m)} and the normalised step.
+// omega_k(x) = (1 + s_k(x)/eps)^{1/(2m)} (all 1 for the Euclidean metric) and
+// the normalised step (the adaptive step is set after the direction is known).
+// In units normalised by eps the direction is eps^{1/2} times the paper's, so
+// alpha = c eps^{1/2} / p becomes c / p and a constant alpha becomes
+// alpha / eps^{1/2}; with the Euclidean metric eps plays no part (eps_n = 1).
 template <typename F>
 __device__ void sampled_finish_total(const Dev &d, F *sacc, double rs, int diag) {
   __shared__ double sbuf[16];
@@ -50,9 +54,10 @@ __device__ void sampled_finish_total(const Dev &d, F *sacc, double rs, int diag)
       st->status = 0;      // G_l = 0: T_l fits every observation
       st->done = 1;
     } else {
-      const double epsn = d.eps_fixed > 0.0 ? d.eps_fixed : emax;
+      const double epsn = (d.metric == METRIC_EUCLIDEAN) ? 1.0 : (d.eps_fixed > 0.0 ? d.eps_fixed : emax);
       st->eps_n = epsn;
-      st->alpha_n = (d.step_policy == STEP_THEORY) ? d.step / d.p : d.step / sqrt(epsn);
+      st->alpha_n = (d.step_policy == STEP_THEORY) ? d.step / d.p
+                    : (d.step_policy == STEP_CONST) ? d.step / sqrt(epsn) : 0.0;
       rec.eps = epsn;
       rec.alpha = st->alpha_n * sqrt(epsn);
       st->upd = 0;
@@ -64,8 +69,9 @@ __device__ void sampled_finish_total(const Dev &d, F *sacc, double rs, int diag)
   if (go) {
     const double inv = 1.0 / st->eps_n;
     const double ex = 1.0 / (2.0 * m);
+    const bool euclid = d.metric == METRIC_EUCLIDEAN;
     for (int i = threadIdx.x; i < stot; i += blockDim.x) {
-      d.omega[i] = pow(1.0 + (double)sacc[i] * inv, ex);
+      d.omega[i] = euclid ? 1.0 : pow(1.0 + (double)sacc[i] * inv, ex);
       sacc[i] = (F)0;
     }
   }

@@ -225,3 +225,34 @@ def test_device_inputs_and_sort_modes_agree(L):
     s.close()
     for o in outs[1:]:
         assert rel_dist(o, outs[0]) < 1e-12
+
+
+@pytest.mark.parametrize("name,metric,rule,c,iters", [
+    ("c1", "data", "adaptive", 1.0, 12), ("c2_small", "data", "adaptive", 1.0, 8),
+    ("ragged", "data", "adaptive", 1.0, 8), ("o3_rank16", "data", "adaptive", 1.0, 4),
+    ("c2_small", "euclidean", "theory", 0.8, 8), ("order6", "euclidean", "theory", 0.8, 6),
+    ("c2_small", "euclidean", "adaptive", 1.0, 8), ("ragged", "euclidean", "adaptive", 1.0, 8)])
+def test_other_policies_match_reference_each_iteration(L, name, metric, rule, c, iters):
+    """Adaptive step (section 3.2.2) and the Euclidean metric (RGD, section 3.1): every
+    iterate within 1e-10 of the reference, and the same step sizes."""
+    pb = make_case(name)
+    say("case", name, metric, rule)
+    y = observed(pb)
+    pol = prgd.Policy(step_rule=rule, c=c, metric=metric)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, step=c, step_policy=rule, metric=metric,
+                 stop_rule="none", max_iter=iters)
+    ref = [x.copy() for x in pb.init]
+    alphas = []
+    try:
+        for it in range(iters):
+            s.iterate(1)
+            got = s.cores()
+            ref, info = prgd.prgd_step(ref, pb.indices, y, pol, pb.ranks)
+            alphas.append(info["alpha"])
+            d = rel_dist(got, ref)
+            assert d <= 1e-10, (it, d)
+        hist = s.history()
+    finally:
+        s.close()
+    for h, a in zip(hist, alphas):
+        assert abs(h["alpha"] - a) <= 1e-9 * abs(a), (h, a)

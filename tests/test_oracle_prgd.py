@@ -249,3 +249,52 @@ def test_spectral_init_is_rank_r_and_closer_than_zero():
     t0 = prgd.spectral_init_dense(idx, y, shape, ranks)
     assert tt.ranks_of(t0) == ranks
     assert tt.tt_dist(t0, truth) < tt.tt_norm(truth)
+
+
+def test_euclidean_metric_is_the_euclidean_tangent_projection():
+    """metric="euclidean" (RGD, section 3.1): the direction is the orthogonal projection
+    of the dense gradient onto the tangent space, computed here by least squares on the
+    tangent-space Jacobian (no weights, no eps)."""
+    shape, ranks, truth, cores, idx, y = tiny_problem(11, (3, 4, 3), (1, 2, 2, 1))
+    r = prgd.residual(cores, idx, y)
+    d = prgd.tangent_direction(cores, idx, r, metric="euclidean")
+    got = tt.tt_full(prgd.tangent_tt(d.base, d.comps)).ravel()
+    jac = jacobian(cores)
+    gd = dense_gradient(shape, idx, r).ravel()
+    theta, *_ = np.linalg.lstsq(jac, gd, rcond=None)
+    ref = jac @ theta
+    assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_rgd_adaptive_step_minimises_linearised_objective():
+    """Section 3.1: alpha = ||P_T G||^2 / ||P_Omega P_T G||^2 minimises f(T - a P_T G)."""
+    shape, ranks, truth, cores, idx, y = tiny_problem(12)
+    r = prgd.residual(cores, idx, y)
+    d = prgd.tangent_direction(cores, idx, r, metric="euclidean")
+    a = prgd.step_adaptive(d, idx)
+    xi = tt.tt_full(prgd.tangent_tt(d.base, d.comps))
+    full = tt.tt_full(cores)
+
+    def f(al):
+        v = (full - al * xi)[tuple(idx)] - y
+        return 0.5 * float(v @ v)
+
+    f0, f1, f2 = f(0.0), f(1.0), f(2.0)
+    amin = (3 * f0 - 4 * f1 + f2) / (2 * (f0 - 2 * f1 + f2))
+    assert abs(a - amin) <= 1e-9 * abs(amin)
+    pg = float(np.sum(xi * xi))
+    pog = float(np.sum(xi[tuple(idx)] ** 2))
+    assert abs(a - pg / pog) <= 1e-11 * a
+
+
+@pytest.mark.parametrize("metric,rule,c", [("euclidean", "adaptive", 1.0), ("euclidean", "theory", 0.8),
+                                           ("data", "adaptive", 1.0)])
+def test_noiseless_c1_recovery_other_policies(metric, rule, c):
+    """RGD (adaptive and constant step) and PRGD with the adaptive step also recover the
+    noiseless order-4 problem to 1e-10."""
+    pb = wl.named("c1")
+    y = tt.tt_eval(pb.truth, pb.indices)
+    pol = prgd.Policy(step_rule=rule, c=c, metric=metric, stop_rule="residual", tol=1e-10, max_iter=500)
+    res = prgd.prgd(pb.init, pb.indices, y, pol, truth=pb.truth)
+    assert res.status == "converged"
+    assert tt.tt_dist(res.cores, pb.truth) / tt.tt_norm(pb.truth) <= 1e-9
