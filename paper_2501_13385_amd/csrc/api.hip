@@ -109,6 +109,23 @@ void sampled_plan(int m, const int *n, int R, int prec, long long N, int *off, l
   nbs = (int)std::max<long long>(nb, 1);
 }
 
+// The mode-by-mode sampled pass replaces the single pass when a middle mode
+// would need global atomics (its accumulators do not fit in LDS) or has so
+// few slices that LDS atomics from a whole workgroup would collide.
+bool use_mode_passes(int m, const int *n, int R, int prec, long long N) {
+  if (m < 3) return false;
+  int off[MAXM];
+  long long tot = 0;
+  int nbs = 1;
+  sampled_plan(m, n, R, prec, N, off, tot, nbs);
+  for (int k = 1; k < m - 1; ++k)
+    if (off[k] < 0 || n[k] < 32) return true;
+  return false;
+}
+
+// workgroups of one mode's pass
+long long mode_pass_wgs(long long N) { return std::min<long long>(1024, std::max<long long>(1, (N + 2047) / 2048)); }
+
 prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *vals, int64_t &numel) {
   const int m = ds->order;
   if (m < 2 || m > MAXM) return fail(m < 2 ? PRGD_EINVAL : PRGD_ENOTSUP, "order must be in [2, 32]");
@@ -186,6 +203,7 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
 
 hipError_t sampled_pass(prgd_solver s, int diag, hipEvent_t after_main = nullptr) {
   if (s->d.use3) return launch_sampled3(s->batch(), diag, s->stream, after_main);
+  if (s->d.use_modes) return launch_sampled_modes(s->batch(), diag, s->stream, after_main);
   return launch_sampled(s->batch(), diag, s->stream, after_main);
 }
 
@@ -219,11 +237,11 @@ namespace prgd {
 prgd_status set_error(prgd_status st, const char *msg) { return fail(st, msg); }
 
 hipError_t enqueue_batch_iterations(const Batch &bt, int iters, hipStream_t s) {
-  const bool use3 = bt.host[0].use3 != 0;
+  const bool use3 = bt.host[0].use3 != 0, modes = bt.host[0].use_modes != 0;
   bool truth = false;
   for (int i = 0; i < bt.ns; ++i) truth = truth || bt.host[i].has_truth;
   for (int it = 0; it < iters; ++it) {
-    hipError_t e = use3 ? launch_sampled3(bt, 0, s) : launch_sampled(bt, 0, s);
+    hipError_t e = use3 ? launch_sampled3(bt, 0, s) : (modes ? launch_sampled_modes(bt, 0, s) : launch_sampled(bt, 0, s));
     if (e != hipSuccess) return e;
     if ((e = launch_dense_iteration(bt, s, 0)) != hipSuccess) return e;
     if (truth && (e = launch_truth_sweep(bt, s, 0)) != hipSuccess) return e;
@@ -258,14 +276,21 @@ int64_t solver_footprint(const prgd_desc *ds) {
   b += f * N;                                         // values in the working precision
   b += f * (int64_t)(ds->mode_sizes[0] + ds->mode_sizes[m - 1]) * R;   // boundary vectors
   if (ds->truth_cores) b += 8 * pn;
-  {                                                   // any-order private partials (upper bound)
+  {                                                   // any-order pass (upper bound)
     int off[MAXM];
     long long tot = 0;
     int nbs = 1;
     std::vector<int> nv(ds->mode_sizes, ds->mode_sizes + m);
     if (sampled_block_size(m, R, ds->precision) > 0) {
-      sampled_plan(m, nv.data(), R, ds->precision, N, off, tot, nbs);
-      b += (int64_t)nbs * tot * f;
+      if (use_mode_passes(m, nv.data(), R, ds->precision, N)) {
+        const int64_t segw = (int64_t)R * R + 1, nwg = mode_pass_wgs(N);
+        b += (int64_t)(m - 1) * (4 * m * N + f * N);      // sorted copies per mode
+        for (int k = 0; k < m; ++k) b += nwg * (KSEG * segw * f + 4) + (int64_t)nv[k] * (segw * f + 8);
+        b += 8 * nwg + (int64_t)m * (int64_t)sizeof(ModeTab) + 64 * 256 * 6 * m;
+      } else {
+        sampled_plan(m, nv.data(), R, ds->precision, N, off, tot, nbs);
+        b += (int64_t)nbs * tot * f;
+      }
     }
   }
   if (m == 3) {                                       // order-3 tables (upper bound)
@@ -564,7 +589,85 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   d.priv_len = 0;
   d.part_priv = nullptr;
   d.nb_sampled = 1;
-  if (!d.use3) {
+  d.use_modes = 0;
+  d.mt = nullptr;
+  d.mp_rsq = nullptr;
+  d.mt_wg = 0;
+  d.mt_out = 0;
+  if (!d.use3 && use_mode_passes(m, s->n.data(), R, d.prec, N)) {
+    const long long f = mixed ? 4 : 8;
+    const long long segw = (long long)R * R + 1;
+    std::vector<ModeTab> mt(m);
+    int wg0 = 0;
+    long long out0 = 0;
+    for (int k = 0; k < m; ++k) {
+      ModeTab &t = mt[k];
+      const int nk = s->n[k];
+      if (k == sm) {
+        t.idx = idx_sorted;
+        t.y = mixed ? (const void *)y32 : (const void *)y64;
+      } else {
+        int *ip = nullptr;
+        double *y6 = nullptr;
+        float *y3 = nullptr;
+        if (!A(s->alloc(&ip, (long long)m * N)) || !(mixed ? A(s->alloc(&y3, N)) : A(s->alloc(&y6, N))))
+          return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+        hipError_t e = group_by_mode(m, N, k, nk, idx_dev, val_dev, ds->values_fp64, ip, y6, y3, s->stream);
+        if (e != hipSuccess) return cleanup(fail(PRGD_EDEVICE, std::string("grouping Omega: ") + hipGetErrorString(e)));
+        t.idx = ip;
+        t.y = mixed ? (const void *)y3 : (const void *)y6;
+      }
+      long long nwg = mode_pass_wgs(N);
+      t.chunk = (N + nwg - 1) / nwg;
+      nwg = (N + t.chunk - 1) / t.chunk;
+      t.nwg = (int)nwg;
+      t.wg0 = wg0;
+      wg0 += (int)nwg;
+      t.out0 = out0;
+      out0 += (long long)nk * segw;
+      std::vector<long long> seg(nk + 1, 0);
+      for (long long j = 0; j < N; ++j) seg[idx_h[(long long)k * N + j] + 1]++;
+      for (int v = 0; v < nk; ++v) seg[v + 1] += seg[v];
+      std::vector<int> vfirst(nwg), blo(nk), bhi(nk);
+      for (long long b = 0; b < nwg; ++b)
+        vfirst[b] = (int)(std::upper_bound(seg.begin(), seg.end(), b * t.chunk) - seg.begin()) - 1;
+      for (int v = 0; v < nk; ++v) {
+        if (seg[v + 1] > seg[v]) {
+          blo[v] = (int)(seg[v] / t.chunk);
+          bhi[v] = (int)((seg[v + 1] - 1) / t.chunk);
+        } else {
+          blo[v] = 1;
+          bhi[v] = 0;
+        }
+      }
+      int *dvf = nullptr, *dlo = nullptr, *dhi = nullptr;
+      unsigned char *pseg = nullptr, *povf = nullptr;
+      if (!A(s->alloc(&dvf, nwg)) || !A(s->alloc(&dlo, nk)) || !A(s->alloc(&dhi, nk)) ||
+          !A(s->alloc(&pseg, nwg * KSEG * segw * f)) || !A(s->alloc(&povf, (long long)nk * segw * f)))
+        return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+      if (hipMemcpy(dvf, vfirst.data(), nwg * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(dlo, blo.data(), nk * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(dhi, bhi.data(), nk * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(PRGD_EDEVICE, "upload of the segment maps failed"));
+      hipError_t fe = mixed ? fill_f32((float *)povf, (long long)nk * segw, 0.0f, s->stream)
+                            : fill_f64((double *)povf, (long long)nk * segw, 0.0, s->stream);
+      if (fe != hipSuccess) return cleanup(fail(PRGD_EDEVICE, "fill failed"));
+      t.vfirst = dvf;
+      t.blo = dlo;
+      t.bhi = dhi;
+      t.part_seg = pseg;
+      t.ovf = povf;
+    }
+    ModeTab *dmt = nullptr;
+    if (!A(s->alloc(&dmt, m)) || !A(s->alloc(&d.mp_rsq, mt[0].nwg)))
+      return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+    if (hipMemcpy(dmt, mt.data(), m * sizeof(ModeTab), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(PRGD_EDEVICE, "upload of the mode tables failed"));
+    d.mt = dmt;
+    d.mt_wg = wg0;
+    d.mt_out = out0;
+    d.use_modes = 1;
+  } else if (!d.use3) {
     long long tot = 0;
     int nbs = 1;
     sampled_plan(m, s->n.data(), R, d.prec, N, d.priv_off, tot, nbs);

@@ -93,6 +93,21 @@ struct S3 {
   double *part_rsq;      // [nwg]
 };
 
+// one mode of the mode-by-mode sampled pass (see sampled_modes.hip)
+struct ModeTab {
+  const int *idx;        // [m][N] Omega stably sorted by this mode
+  const void *y;         // [N] observed values in that order (working precision)
+  long long chunk;       // samples per workgroup
+  int nwg;               // workgroups of this mode
+  int wg0;               // first workgroup of this mode in the merged grid
+  long long out0;        // first output of this mode in the merged reduction
+  const int *vfirst;     // [nwg] first segment of each workgroup's chunk
+  const int *blo;        // [n_k] first workgroup covering segment v (blo > bhi: empty)
+  const int *bhi;        // [n_k]
+  void *part_seg;        // [nwg][KSEG][R*R + 1] segment tables
+  void *ovf;             // [n_k][R*R + 1] overflow accumulator (zero between passes)
+};
+
 struct Dev {
   int m;
   int R;                       // padded slice dimension
@@ -139,6 +154,12 @@ struct Dev {
   int priv_off[MAXM];
   int priv_len;                // elements of the private area per workgroup
   void *part_priv;             // [nb_sampled][priv_len] in the working precision
+  // mode-by-mode sampled pass (no atomics; see sampled_modes.hip)
+  int use_modes;
+  int mt_wg;                   // workgroups of all modes together
+  long long mt_out;            // outputs of all modes together (n_k (R*R + 1) each)
+  const ModeTab *mt;           // device array [m]
+  double *mp_rsq;              // [mt[0].nwg] partial ||R||^2
   S3 q3;
 };
 

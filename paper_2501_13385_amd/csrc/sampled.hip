@@ -192,8 +192,8 @@ template <typename F>
 __global__ void __launch_bounds__(256) k_sampled_fin(const Dev *__restrict__ dt, int diag) {
   const Dev &d = dt[blockIdx.y];
   if (!diag && d.st->done) return;
-  const double *rsq_part = d.use3 ? d.q3.part_rsq : d.part;
-  const int nb = d.use3 ? d.q3.nwg : d.nb_sampled;
+  const double *rsq_part = d.use3 ? d.q3.part_rsq : (d.use_modes ? d.mp_rsq : d.part);
+  const int nb = d.use3 ? d.q3.nwg : (d.use_modes ? d.mt[0].nwg : d.nb_sampled);
   __shared__ double sbuf[16];
   double v = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) v += rsq_part[i];
