@@ -37,6 +37,8 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
+import hashlib  # noqa: E402
+
 METRIC = "|Ω|·iterations/s, time to 1e-6 rel. error; served solves/s + p99 latency"
 WORKLOAD = "c2"
 # MI355X peaks (published): HBM 8 TB/s; FP64 vector 78.6 TFLOP/s.  Non-packed FP32
@@ -173,6 +175,41 @@ def serving_leg(L, n_req, max_obs, seed=0, max_iter=150, precisions=("fp64", "mi
     return out
 
 
+COPY_BYTES = 256 << 20     # bytes read and written by one calibration copy
+
+
+def copy_calibration(reps=5):
+    """A plain device copy of known size (COPY_BYTES read + written per launch), run
+    under the same counters as the bench to scale FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    src_t = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst_t = torch.empty_like(src_t)
+    for _ in range(reps):
+        dst_t.copy_(src_t)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "reps": reps}), flush=True)
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_2501_13385_amd", "csrc", "sampled3.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(precision):
+    """HBM bytes per launch of the order-3 sampled kernel from the committed PMC summary,
+    or None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_sampled3_c2.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != kernel_source_hash():
+        return None
+    leg = rec.get(precision)
+    return None if leg is None else leg.get("bytes_per_launch")
+
+
 def cpu_baseline(pb, iters):
     """The reference implementation, as it stands, on the host cores (one BLAS thread)."""
     from threadpoolctl import threadpool_limits
@@ -205,7 +242,12 @@ def main():
     ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed iterations (for kernel profilers); prints the phase times")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
@@ -232,7 +274,7 @@ def main():
     t_k1 = h["phase_ms_per_step"]["sampled_main"] * 1e-3
     roof = {"kernel": "sampled pass, main kernel (k_sampled3)", "bound": "alu",
             "achieved": flops / t_k1 / 1e12, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": flops / t_k1 / 1e12 / PEAK_ALU_TFLOPS, "traffic": None,
+            "frac": flops / t_k1 / 1e12 / PEAK_ALU_TFLOPS, "traffic": measured_traffic(head),
             "hbm_GBs": sampled_pass_bytes(pb.shape, pb.n_obs, 8 if head == "fp64" else 4) / t_k1 / 1e9,
             "flops_per_launch": flops}
     line = {

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "prgd_internal.hpp"
+
 namespace prgd {
 
 __device__ inline double wave_sum(double v) {
@@ -48,8 +50,9 @@ __device__ inline double block_max(double v, double *sbuf) {
 // independent accumulators each, so many loads are in flight at once (the
 // partials were written by blocks on other XCDs and arrive with long latency).
 // scratch: LDS of at least blockDim.x doubles.  Ends with a barrier.
-__device__ inline void reduce_partials(const double *part, int nb, int ne, double *out, double *scratch) {
+__device__ inline void reduce_partials(const double *part_, int nb, int ne, double *out, double *scratch) {
   const int nt = blockDim.x, t = threadIdx.x;
+  const auto part = glb(part_);
   if (ne <= nt) {
     const int G = nt / ne;                 // groups per entry
     const int g = t / ne, e = t % ne;

@@ -59,13 +59,13 @@ __device__ inline Grp make_grp(int ne) {
 }
 
 __device__ inline double load_grad(const Dev &d, long long i) {
-  return d.prec == PREC_MIXED ? (double)((const float *)d.Y)[i] : ((const double *)d.Y)[i];
+  return d.prec == PREC_MIXED ? (double)glb((const float *)d.Y)[i] : glb((const double *)d.Y)[i];
 }
 __device__ inline void zero_grad(const Dev &d, long long i) {
   if (d.prec == PREC_MIXED)
-    ((float *)d.Y)[i] = 0.0f;
+    glb((float *)d.Y)[i] = 0.0f;
   else
-    ((double *)d.Y)[i] = 0.0;
+    glb((double *)d.Y)[i] = 0.0;
 }
 
 // core index and slice range of this block for slice-parallel kernels over all cores
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(256) k_gram(const Dev *__restrict__ dt, int j)
     if (act) {
       const long long off = d.coff[c] + (long long)x * RR;
       for (int t = q.tl; t < RR; t += q.TPG) {
-        sT[t] = d.cores[off + t];
+        sT[t] = glb(d.cores)[off + t];
         if (want_th) sY[t] = load_grad(d, off + t);
       }
     }
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(256) k_gram(const Dev *__restrict__ dt, int j)
     }
     __syncthreads();
     if (act && e < RR) {
-      const double w = d.omega[d.soff[c] + x];
+      const double w = glb(d.omega)[d.soff[c] + x];
       double v = 0.0;
       if (left) {
         for (int k = 0; k < R; ++k) v += sT[k * R + ea] * tmp[k * R + eb];
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(256) k_gram(const Dev *__restrict__ dt, int j)
     red[(q.g * 2 + 1) * RR + e] = acct;
   }
   __syncthreads();
-  double *mypart = d.part + (long long)blockIdx.x * 2 * RR;
+  auto mypart = glb(d.part) + (long long)blockIdx.x * 2 * RR;
   for (int t = threadIdx.x; t < RR; t += blockDim.x) {
     double a0 = 0.0, a1 = 0.0;
     for (int g = 0; g < q.G; ++g) {
@@ -264,7 +264,7 @@ __global__ void __launch_bounds__(256) k_tangent(const Dev *__restrict__ dt) {
     const long long off = d.coff[c] + (long long)x * RR;
     if (act)
       for (int t = q.tl; t < RR; t += q.TPG) {
-        sT[t] = d.cores[off + t];
+        sT[t] = glb(d.cores)[off + t];
         sY[t] = load_grad(d, off + t);
         zero_grad(d, off + t);
       }
@@ -276,13 +276,13 @@ __global__ void __launch_bounds__(256) k_tangent(const Dev *__restrict__ dt) {
     }
     __syncthreads();
     if (act && e < RR) {
-      const double iw = 1.0 / d.omega[d.soff[c] + x];
+      const double iw = 1.0 / glb(d.omega)[d.soff[c] + x];
       double v = 0.0;
       for (int k = 0; k < R; ++k) v += tmp[ea * R + k] * HI[k * R + eb];
       v *= iw;
       double u = 0.0;
       for (int k = 0; k < R; ++k) u += sT[ea * R + k] * PS[k * R + eb];
-      d.X[off + e] = v - u;
+      glb(d.X)[off + e] = v - u;
     }
     __syncthreads();
   }
@@ -335,8 +335,8 @@ __global__ void __launch_bounds__(256) k_rgram(const Dev *__restrict__ dt, int b
     const long long off = d.coff[b] + (long long)x * R * R;
     if (act)
       for (int t = q.tl; t < R * R; t += q.TPG) {
-        sT[t] = d.cores[off + t];
-        sX[t] = d.X[off + t];
+        sT[t] = glb(d.cores)[off + t];
+        sX[t] = glb(d.X)[off + t];
       }
     __syncthreads();
     if (act) build_block(d, b, sT, sX, alpha, C, q.tl, q.TPG);
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(256) k_rgram(const Dev *__restrict__ dt, int b
     for (int t = q.tl; t < NE; t += q.TPG, ++u) red[q.g * NE + t] = acc[u];
   }
   __syncthreads();
-  double *mypart = d.part + (long long)blockIdx.x * NE;
+  auto mypart = glb(d.part) + (long long)blockIdx.x * NE;
   for (int t = threadIdx.x; t < NE; t += blockDim.x) {
     double v = 0.0;
     for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
@@ -440,8 +440,8 @@ __global__ void __launch_bounds__(256) k_left(const Dev *__restrict__ dt, int i)
     const long long off = d.coff[c] + (long long)x * R * R;
     if (act)
       for (int t = q.tl; t < R * R; t += q.TPG) {
-        sT[t] = d.cores[off + t];
-        sX[t] = d.X[off + t];
+        sT[t] = glb(d.cores)[off + t];
+        sX[t] = glb(d.X)[off + t];
       }
     __syncthreads();
     if (act) build_block(d, c, sT, sX, alpha, C, q.tl, q.TPG);
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(256) k_left(const Dev *__restrict__ dt, int i)
     for (int t = q.tl; t < NE; t += q.TPG, ++u) red[q.g * NE + t] = acc[u];
   }
   __syncthreads();
-  double *mypart = d.part + (long long)blockIdx.x * NE;
+  auto mypart = glb(d.part) + (long long)blockIdx.x * NE;
   for (int t = threadIdx.x; t < NE; t += blockDim.x) {
     double v = 0.0;
     for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
@@ -610,8 +610,8 @@ __global__ void __launch_bounds__(256) k_output(const Dev *__restrict__ dt, int 
     const long long off = d.coff[c] + (long long)x * RR;
     if (act)
       for (int t = q.tl; t < RR; t += q.TPG) {
-        sT[t] = d.cores[off + t];
-        sX[t] = d.X[off + t];
+        sT[t] = glb(d.cores)[off + t];
+        sX[t] = glb(d.X)[off + t];
       }
     __syncthreads();
     if (act) build_block(d, c, sT, sX, alpha, C, q.tl, q.TPG);
@@ -638,15 +638,15 @@ __global__ void __launch_bounds__(256) k_output(const Dev *__restrict__ dt, int 
     __syncthreads();
     if (act) {
       for (int t = q.tl; t < RR; t += q.TPG) {
-        d.cores[off + t] = out[t];
-        if (d.prec == PREC_MIXED) d.cores32[off + t] = (float)out[t];
+        glb(d.cores)[off + t] = out[t];
+        if (d.prec == PREC_MIXED) glb(d.cores32)[off + t] = (float)out[t];
       }
       if (c == 0 || c == m - 1) {
         const long long bo = (c == 0) ? (long long)x * R : (long long)d.n[0] * R + (long long)x * R;
         for (int a = q.tl; a < R; a += q.TPG) {
           const double v = (c == 0) ? out[a] : out[a * R];
-          if (d.prec == PREC_MIXED) ((float *)d.bnd)[bo + a] = (float)v;
-          else ((double *)d.bnd)[bo + a] = v;
+          if (d.prec == PREC_MIXED) glb((float *)d.bnd)[bo + a] = (float)v;
+          else glb((double *)d.bnd)[bo + a] = v;
         }
       }
       if (c == m - 1)
@@ -664,8 +664,8 @@ __global__ void __launch_bounds__(256) k_output(const Dev *__restrict__ dt, int 
   nn = block_sum(nn, sbuf);
   cr = block_sum(cr, sbuf);
   if (threadIdx.x == 0) {
-    d.part[2 * blockIdx.x] = nn;
-    d.part[2 * blockIdx.x + 1] = cr;
+    glb(d.part)[2 * blockIdx.x] = nn;
+    glb(d.part)[2 * blockIdx.x + 1] = cr;
   }
 }
 
@@ -677,8 +677,8 @@ __global__ void __launch_bounds__(1024) k_output_fin(const Dev *__restrict__ dt,
   __shared__ double sbuf[16];
   double a0 = 0.0, a1 = 0.0;
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
-    a0 += d.part[2 * k];
-    a1 += d.part[2 * k + 1];
+    a0 += glb(d.part)[2 * k];
+    a1 += glb(d.part)[2 * k + 1];
   }
   a0 = block_sum(a0, sbuf);
   a1 = block_sum(a1, sbuf);
@@ -734,8 +734,8 @@ __global__ void __launch_bounds__(256) k_cross(const Dev *__restrict__ dt, int c
     const long long off = d.coff[c] + (long long)x * RR;
     if (act)
       for (int t = q.tl; t < RR; t += q.TPG) {
-        sA[t] = Acore[off + t];
-        sB[t] = d.truth[off + t];
+        sA[t] = glb(Acore)[off + t];
+        sB[t] = glb(d.truth)[off + t];
       }
     __syncthreads();
     if (act && e < RR) {
@@ -755,7 +755,7 @@ __global__ void __launch_bounds__(256) k_cross(const Dev *__restrict__ dt, int c
   __syncthreads();
   if (q.g < q.G && e < RR) red[q.g * RR + e] = acc;
   __syncthreads();
-  double *mypart = d.part + (long long)blockIdx.x * RR;
+  auto mypart = glb(d.part) + (long long)blockIdx.x * RR;
   for (int t = threadIdx.x; t < RR; t += blockDim.x) {
     double v = 0.0;
     for (int g = 0; g < q.G; ++g) v += red[g * RR + t];

@@ -31,14 +31,15 @@ __global__ void __launch_bounds__(256) k_xi(const Dev *__restrict__ dt) {
   if ((int)blockIdx.x >= nb || d.step_policy != STEP_ADAPTIVE || d.st->done) return;
   constexpr int RR = R * R;
   const int m = d.m;
-  const double *T = d.cores, *X = d.X;
+  const auto T = glb(d.cores), X = glb(d.X);
+  const auto idx = glb(d.idx);
   const long long chunk = (N + nb - 1) / nb;
   const long long jlo = (long long)blockIdx.x * chunk, jhi = min(N, jlo + chunk);
   double num = 0.0, den = 0.0;
   for (long long j = jlo + threadIdx.x; j < jhi; j += blockDim.x) {
     double la[R], lb[R];
     {
-      const long long s = d.coff[0] + (long long)d.idx[j] * RR;
+      const long long s = d.coff[0] + (long long)idx[j] * RR;
 #pragma unroll
       for (int b = 0; b < R; ++b) {
         la[b] = X[s + b];
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(256) k_xi(const Dev *__restrict__ dt) {
       }
     }
     for (int c = 1; c < m - 1; ++c) {
-      const long long s = d.coff[c] + (long long)d.idx[(long long)c * N + j] * RR;
+      const long long s = d.coff[c] + (long long)idx[(long long)c * N + j] * RR;
       double na[R], nv[R];
 #pragma unroll
       for (int b = 0; b < R; ++b) {
@@ -66,7 +67,7 @@ __global__ void __launch_bounds__(256) k_xi(const Dev *__restrict__ dt) {
         lb[b] = nv[b];
       }
     }
-    const long long s = d.coff[m - 1] + (long long)d.idx[(long long)(m - 1) * N + j] * RR;
+    const long long s = d.coff[m - 1] + (long long)idx[(long long)(m - 1) * N + j] * RR;
     double xv = 0.0, tv = 0.0;
 #pragma unroll
     for (int a = 0; a < R; ++a) {
@@ -74,7 +75,7 @@ __global__ void __launch_bounds__(256) k_xi(const Dev *__restrict__ dt) {
       xv = fma(la[a], ta, fma(lb[a], xa, xv));
       tv = fma(lb[a], ta, tv);
     }
-    const double yv = d.prec == PREC_MIXED ? (double)d.y32[j] : d.y64[j];
+    const double yv = d.prec == PREC_MIXED ? (double)glb(d.y32)[j] : glb(d.y64)[j];
     const double res = tv - yv;
     num = fma(res, xv, num);
     den = fma(xv, xv, den);

@@ -183,6 +183,15 @@ struct Batch {
   int ns;
 };
 
+// The kernels read their pointers from the descriptor table in device memory,
+// so the compiler cannot tell that they point to global memory and would use
+// flat (generic) instructions, which also occupy the LDS wait counter.  Hot
+// accesses go through glb(), which states the address space.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *glb(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
 __host__ __device__ inline double *sm_slot(const Dev &d, int bond, int slot) {
   return d.sm + ((long long)bond * SM_SLOTS + slot) * SLOT;
 }

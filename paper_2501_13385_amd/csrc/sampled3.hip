@@ -60,9 +60,9 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
   const Dev &d = dt[blockIdx.y];
   const S3 &q = d.q3;
   if ((int)blockIdx.x >= q.nwg || (!diag && d.st->done)) return;
-  const F *__restrict__ cores = (const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores);
-  const F *__restrict__ bnd = (const F *)d.bnd;
-  const F *__restrict__ y = (const F *)(d.prec == PREC_MIXED ? (const void *)d.y32 : (const void *)d.y64);
+  const auto cores = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores));
+  const auto bnd = glb((const F *)d.bnd);
+  const auto y = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.y32 : (const void *)d.y64));
   typedef Mma<F> M;
   constexpr int RR = R * R;
   constexpr int SEGW = RR + 1;
@@ -78,8 +78,8 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
   F *lT3 = lT1 + n1 * R;
   const int L = n1 * R + n3 * R + n1 + n3;
   for (int i = threadIdx.x; i < L + KSEG * SEGW; i += NT) lY1[i] = (F)0;
-  const F *gT1 = bnd;
-  const F *gT3 = bnd + (long long)n1 * R;
+  const F *gT1 = (const F *)bnd;
+  const F *gT3 = (const F *)bnd + (long long)n1 * R;
   if (STAGE)
     for (int i = threadIdx.x; i < (n1 + n3) * R; i += NT) lT1[i] = bnd[i];
   const F *T1 = STAGE ? lT1 : gT1;
@@ -88,12 +88,12 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
 
   const long long j0 = (long long)blockIdx.x * q.chunk;
   const long long j1 = min(N, j0 + q.chunk);
-  const int vfirst = q.vfirst[blockIdx.x];
+  const int vfirst = glb(q.vfirst)[blockIdx.x];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int NW = NT / 64;
   const long long per = ((j1 - j0) + NW - 1) / NW;
   const long long ws = j0 + w * per, we = min(j1, ws + per);
-  const int *ix1 = d.idx, *ix2 = d.idx + N, *ix3 = d.idx + 2 * N;
+  const auto ix1 = glb(d.idx), ix2 = glb(d.idx) + N, ix3 = glb(d.idx) + 2 * N;
   const long long co2 = d.coff[1];
   F *ovf = (F *)q.ovf;
 
@@ -160,7 +160,7 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
         flush();
         wv = v;
       }
-      const F *S = cores + co2 + (long long)v * RR;
+      const auto S = cores + co2 + (long long)v * RR;
       F res = (F)0;
       if (me) {
         F l1[R], r3[R], u[R], l2[R];
@@ -215,11 +215,11 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
   __shared__ double sbuf[16];
   const double bs = block_sum(rsq, sbuf);
   __syncthreads();
-  F *pb = (F *)q.part_bnd + (long long)blockIdx.x * L;
+  auto pb = glb((F *)q.part_bnd) + (long long)blockIdx.x * L;
   for (int i = threadIdx.x; i < L; i += NT) pb[i] = lY1[i];
-  F *ps = (F *)q.part_seg + (long long)blockIdx.x * KSEG * SEGW;
+  auto ps = glb((F *)q.part_seg) + (long long)blockIdx.x * KSEG * SEGW;
   for (int i = threadIdx.x; i < KSEG * SEGW; i += NT) ps[i] = lseg[i];
-  if (threadIdx.x == 0) q.part_rsq[blockIdx.x] = bs;
+  if (threadIdx.x == 0) glb(q.part_rsq)[blockIdx.x] = bs;
 }
 
 // Deterministic reduction of the per-workgroup partials into the gradient
@@ -238,11 +238,11 @@ __global__ void __launch_bounds__(256) k_sampled3_reduce(const Dev *__restrict__
   const int nbB = (L + 63) / 64;
   const int nbS = (int)(((long long)n2 * SEGW + 255) / 256);
   if ((int)blockIdx.x >= nbB + nbS || (!diag && d.st->done)) return;
-  F *Y = (F *)d.Y;
-  F *s = (F *)d.s;
-  const F *pb = (const F *)q.part_bnd;
-  const F *ps = (const F *)q.part_seg;
-  F *ovf = (F *)q.ovf;
+  const auto Y = glb((F *)d.Y);
+  const auto s = glb((F *)d.s);
+  const auto pb = glb((const F *)q.part_bnd);
+  const auto ps = glb((const F *)q.part_seg);
+  const auto ovf = glb((F *)q.ovf);
   __shared__ double red[4][64];
   if ((int)blockIdx.x < nbB) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -282,8 +282,8 @@ __global__ void __launch_bounds__(256) k_sampled3_reduce(const Dev *__restrict__
       const int v = (int)(oo / SEGW), e = (int)(oo % SEGW);
       double acc = (double)ovf[oo];
       ovf[oo] = (F)0;
-      for (int b = q.blo[v]; b <= q.bhi[v]; ++b) {
-        const int slot = v - q.vfirst[b];
+      for (int b = glb(q.blo)[v]; b <= glb(q.bhi)[v]; ++b) {
+        const int slot = v - glb(q.vfirst)[b];
         if (slot >= 0 && slot < KSEG) acc += (double)ps[((long long)b * KSEG + slot) * SEGW + e];
       }
       if (e < RR) Y[d.coff[1] + (long long)v * RR + e] = (F)acc;

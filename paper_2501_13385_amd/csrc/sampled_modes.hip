@@ -80,12 +80,12 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
   for (int i = threadIdx.x; i < KSEG * SEGW; i += NT) lseg[i] = (F)0;
   __syncthreads();
 
-  const F *__restrict__ cores = (const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores);
-  const F *__restrict__ y = (const F *)q.y;
+  const auto cores = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores));
+  const auto y = glb((const F *)q.y);
   const long long N = d.N;
-  const int *idx = q.idx;
+  const auto idx = glb(q.idx);
   const long long j0 = (long long)wg * q.chunk, j1 = min(N, j0 + q.chunk);
-  const int vfirst = q.vfirst[wg];
+  const int vfirst = glb(q.vfirst)[wg];
   const long long per = ((j1 - j0) + NW - 1) / NW;
   const long long ws = j0 + w * per, we = min(j1, ws + per);
   const long long cok = d.coff[k];
@@ -130,12 +130,12 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
       for (int a = 0; a < R; ++a) lv[a] = (a == 0) ? (F)1 : (F)0;
     } else {
       const int x0 = act ? idx[j] : 0;
-      const F *sl = cores + d.coff[0] + (long long)x0 * RR;
+      const auto sl = cores + d.coff[0] + (long long)x0 * RR;
 #pragma unroll
       for (int b = 0; b < R; ++b) lv[b] = sl[b];
       for (int cc = 1; cc < k; ++cc) {
         const int x = act ? idx[(long long)cc * N + j] : 0;
-        const F *s2 = cores + d.coff[cc] + (long long)x * RR;
+        const auto s2 = cores + d.coff[cc] + (long long)x * RR;
         F nl[R];
 #pragma unroll
         for (int b = 0; b < R; ++b) {
@@ -153,12 +153,12 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
       for (int a = 0; a < R; ++a) rv[a] = (a == 0) ? (F)1 : (F)0;
     } else {
       const int xl = act ? idx[(long long)(m - 1) * N + j] : 0;
-      const F *sl = cores + d.coff[m - 1] + (long long)xl * RR;
+      const auto sl = cores + d.coff[m - 1] + (long long)xl * RR;
 #pragma unroll
       for (int a = 0; a < R; ++a) rv[a] = sl[a * R];
       for (int cc = m - 2; cc > k; --cc) {
         const int x = act ? idx[(long long)cc * N + j] : 0;
-        const F *s2 = cores + d.coff[cc] + (long long)x * RR;
+        const auto s2 = cores + d.coff[cc] + (long long)x * RR;
         F nr[R];
 #pragma unroll
         for (int a = 0; a < R; ++a) {
@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
         flush();
         wv = v;
       }
-      const F *S = cores + cok + (long long)v * RR;
+      const auto S = cores + cok + (long long)v * RR;
       F res = (F)0;
       if (me) {
         F t = (F)0;
@@ -221,9 +221,9 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
   flush();
   __shared__ double sbuf[16];
   const double bs = block_sum(rsq, sbuf);   // ends with a barrier: the table is complete
-  F *ps = (F *)q.part_seg + (long long)wg * KSEG * SEGW;
+  auto ps = glb((F *)q.part_seg) + (long long)wg * KSEG * SEGW;
   for (int i = threadIdx.x; i < KSEG * SEGW; i += NT) ps[i] = lseg[i];
-  if (k == 0 && threadIdx.x == 0) d.mp_rsq[wg] = bs;
+  if (k == 0 && threadIdx.x == 0) glb(d.mp_rsq)[wg] = bs;
 }
 
 // Sum the segment tables of every mode in a fixed order into the padded
@@ -240,16 +240,16 @@ __global__ void __launch_bounds__(256) k_modes_reduce(const Dev *__restrict__ dt
   const ModeTab &q = d.mt[k];
   const long long oo = o - q.out0;
   const int v = (int)(oo / SEGW), e = (int)(oo % SEGW);
-  F *ovf = (F *)q.ovf;
-  const F *ps = (const F *)q.part_seg;
+  const auto ovf = glb((F *)q.ovf);
+  const auto ps = glb((const F *)q.part_seg);
   double acc = (double)ovf[oo];
   ovf[oo] = (F)0;
-  for (int b = q.blo[v]; b <= q.bhi[v]; ++b) {
-    const int slot = v - q.vfirst[b];
+  for (int b = glb(q.blo)[v]; b <= glb(q.bhi)[v]; ++b) {
+    const int slot = v - glb(q.vfirst)[b];
     if (slot >= 0 && slot < KSEG) acc += (double)ps[((long long)b * KSEG + slot) * SEGW + e];
   }
-  if (e < RR) ((F *)d.Y)[d.coff[k] + (long long)v * RR + e] = (F)acc;
-  else ((F *)d.s)[d.soff[k] + v] = (F)acc;
+  if (e < RR) glb((F *)d.Y)[d.coff[k] + (long long)v * RR + e] = (F)acc;
+  else glb((F *)d.s)[d.soff[k] + v] = (F)acc;
 }
 
 hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s);
