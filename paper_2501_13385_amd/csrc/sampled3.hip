@@ -70,16 +70,19 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
   const int n1 = d.n[0], n3 = d.n[2];
   const long long N = d.N;
   // boundary accumulators in float64 for both precisions (LDS float64 atomics
-  // measured several times faster than float32 ones for this scatter)
+  // measured several times faster than float32 ones for this scatter); rows
+  // padded to an odd number of doubles so random rows spread over more banks
+  constexpr int RS = R + 1;
   double *lY1 = reinterpret_cast<double *>(lds_raw);
-  double *lY3 = lY1 + n1 * R;
-  double *ls1 = lY3 + n3 * R;
+  double *lY3 = lY1 + n1 * RS;
+  double *ls1 = lY3 + n3 * RS;
   double *ls3 = ls1 + n1;
-  const int L = n1 * R + n3 * R + n1 + n3;
-  F *lseg = reinterpret_cast<F *>(lY1 + L);
+  const int L = n1 * R + n3 * R + n1 + n3;            // compact partial layout
+  const int LA = n1 * RS + n3 * RS + n1 + n3;         // padded accumulator layout
+  F *lseg = reinterpret_cast<F *>(lY1 + LA);
   F *lT1 = lseg + KSEG * SEGW;
   F *lT3 = lT1 + n1 * R;
-  for (int i = threadIdx.x; i < L; i += NT) lY1[i] = 0.0;
+  for (int i = threadIdx.x; i < LA; i += NT) lY1[i] = 0.0;
   for (int i = threadIdx.x; i < KSEG * SEGW; i += NT) lseg[i] = (F)0;
   const F *gT1 = (const F *)bnd;
   const F *gT3 = (const F *)bnd + (long long)n1 * R;
@@ -192,8 +195,8 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
         ws2 += r2;
 #pragma unroll
         for (int a = 0; a < R; ++a) {
-          atomicAdd(&lY1[x1 * R + a], (double)(res * u[a]));
-          atomicAdd(&lY3[x3 * R + a], (double)(res * l2[a]));
+          atomicAdd(&lY1[x1 * RS + a], (double)(res * u[a]));
+          atomicAdd(&lY3[x3 * RS + a], (double)(res * l2[a]));
         }
         atomicAdd(&ls1[x1], (double)r2);
         atomicAdd(&ls3[x3], (double)r2);
@@ -219,7 +222,13 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
   const double bs = block_sum(rsq, sbuf);
   __syncthreads();
   auto pb = glb((F *)q.part_bnd) + (long long)blockIdx.x * L;
-  for (int i = threadIdx.x; i < L; i += NT) pb[i] = (F)lY1[i];
+  for (int i = threadIdx.x; i < L; i += NT) {
+    int p;
+    if (i < n1 * R) p = (i / R) * RS + i % R;
+    else if (i < (n1 + n3) * R) p = n1 * RS + ((i - n1 * R) / R) * RS + (i - n1 * R) % R;
+    else p = (n1 + n3) * RS + (i - (n1 + n3) * R);
+    pb[i] = (F)lY1[p];
+  }
   auto ps = glb((F *)q.part_seg) + (long long)blockIdx.x * KSEG * SEGW;
   for (int i = threadIdx.x; i < KSEG * SEGW; i += NT) ps[i] = lseg[i];
   if (threadIdx.x == 0) glb(q.part_rsq)[blockIdx.x] = bs;
@@ -305,7 +314,7 @@ static hipError_t launch3_t(const Batch &bt, int diag, hipStream_t st, hipEvent_
   for (int i = 0; i < bt.ns; ++i) {
     const Dev &d = bt.host[i];
     const int n1 = d.n[0], n3 = d.n[2];
-    const size_t base = (size_t)(n1 * R + n3 * R + n1 + n3) * 8 + (size_t)KSEG * (R * R + 1) * sizeof(F);
+    const size_t base = (size_t)(n1 * (R + 1) + n3 * (R + 1) + n1 + n3) * 8 + (size_t)KSEG * (R * R + 1) * sizeof(F);
     lds = std::max(lds, base + (stage ? (size_t)(n1 + n3) * R * sizeof(F) : 0));
     nwg = std::max(nwg, d.q3.nwg);
     const int L = n1 * R + n3 * R + n1 + n3;
@@ -343,7 +352,7 @@ static hipError_t launch3_f(const Batch &bt, int diag, hipStream_t st, hipEvent_
 // LDS bytes the order-3 pass needs (without / with staged boundary vectors)
 size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage) {
   const size_t f = prec == PREC_MIXED ? 4 : 8;
-  size_t b = (size_t)(n1 * R + n3 * R + n1 + n3) * 8 + (size_t)KSEG * (R * R + 1) * f;
+  size_t b = (size_t)(n1 * (R + 1) + n3 * (R + 1) + n1 + n3) * 8 + (size_t)KSEG * (R * R + 1) * f;
   if (stage) b += (size_t)(n1 + n3) * R * f;
   return b;
 }
