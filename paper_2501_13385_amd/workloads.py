@@ -329,3 +329,17 @@ def serving_mix(n_requests: int = 512, seed: int = 0, *, max_obs: int = 4_194_30
         reqs.append({"shape": shape, "ranks": ranks, "n_obs": n_obs,
                      "seed": int(rng.integers(0, 2**31 - 1)), "arrival": t, "redraws": redraws})
     return reqs
+
+
+def random_mps(n_sites: int, bond: int, rng: np.random.Generator, local: int = 2) -> List[np.ndarray]:
+    """Random matrix product state for the quantum-state-tomography workload (section
+    5.3): complex cores ``U_k`` of shape ``(s_{k-1}, local, s_k)`` with i.i.d. standard
+    complex normal entries, ``s_k = min(bond, local^k, local^(n-k))``, ``s_0 = s_n = 1``."""
+    out = []
+    for k in range(n_sites):
+        sl = min(bond, local ** k, local ** (n_sites - k))
+        sr = min(bond, local ** (k + 1), local ** (n_sites - k - 1))
+        re = rng.standard_normal((sl, local, sr))
+        im = rng.standard_normal((sl, local, sr))
+        out.append((re + 1j * im) / math.sqrt(2.0))
+    return out
