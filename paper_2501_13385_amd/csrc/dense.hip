@@ -88,7 +88,7 @@ __device__ inline void block_core(const Dev &d, int &c, int &x0, int &x1) {
 // ---------------------------------------------------------------------------
 // blocks [0, nbL): core j-1 -> GL_j and Theta_{j-1}
 // blocks [nbL, nbL+nbH): core m-j -> H_{m-j}
-__global__ void __launch_bounds__(256) k_gram(const Dev *__restrict__ dt, int j) {
+__global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j) {
   const Dev &d = dt[blockIdx.y];
   const int R = d.R, RR = R * R, m = d.m;
   const int nbL = nblocks_for(d.n[j - 1], 4), nbH = nblocks_for(d.n[m - j], 4);
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, i
 // ---------------------------------------------------------------------------
 // tangent components X_c(x) (all cores, slice-parallel); clears Y
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_tangent(const Dev *__restrict__ dt) {
+__global__ void __launch_bounds__(1024) k_tangent(const Dev *__restrict__ dt) {
   const Dev &d = dt[blockIdx.y];
   if ((int)blockIdx.x >= d.blk_off[d.m] || d.st->done) return;
   __shared__ double smem[SMEM];
@@ -311,7 +311,7 @@ __device__ inline void build_block(const Dev &d, int c, const double *sT, const 
 // right Grams of the block TT: GR_b = sum_x C_b(x) GR_{b+1} C_b(x)^T, b = m-1..1
 // last block: pivoted Cholesky factor F_b of GR_b on its active indices
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_rgram(const Dev *__restrict__ dt, int b) {
+__global__ void __launch_bounds__(1024) k_rgram(const Dev *__restrict__ dt, int b) {
   const Dev &d = dt[blockIdx.y];
   const int nb = nblocks_for(d.n[b], 4);
   if ((int)blockIdx.x >= nb || d.st->done) return;
@@ -416,7 +416,7 @@ __global__ void __launch_bounds__(1024) k_rgram_fin(const Dev *__restrict__ dt, 
 // ---------------------------------------------------------------------------
 // left sweep of the retraction, cut i = 1..m-1 (core c = i-1)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_left(const Dev *__restrict__ dt, int i) {
+__global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i) {
   const Dev &d = dt[blockIdx.y];
   const int nb = nblocks_for(d.n[i - 1], 4);
   if ((int)blockIdx.x >= nb || d.st->done) return;
@@ -579,7 +579,7 @@ __global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, i
 // output: new cores T'_c(x) = P_c C_c(x) Tr_{c+1} (c < m-1), P_{m-1} C_{m-1}(x);
 // stop-test reductions ||T'||^2 = ||T'_{m-1}||^2 and <T', T>
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_output(const Dev *__restrict__ dt, int init) {
+__global__ void __launch_bounds__(1024) k_output(const Dev *__restrict__ dt, int init) {
   const Dev &d = dt[blockIdx.y];
   if ((int)blockIdx.x >= d.blk_off[d.m] || d.st->done) return;
   __shared__ double smem[SMEM];
@@ -711,7 +711,7 @@ __global__ void __launch_bounds__(1024) k_output_fin(const Dev *__restrict__ dt,
 // cross Gram sweep with the truth: Z_{c+1} = sum_x A_c(x)^T Z_c B_c(x)
 // mode 0: A = iterate, B = truth (relative error); mode 1: A = B = truth (||T*||^2)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_cross(const Dev *__restrict__ dt, int c, int mode) {
+__global__ void __launch_bounds__(1024) k_cross(const Dev *__restrict__ dt, int c, int mode) {
   const Dev &d = dt[blockIdx.y];
   const int nb = nblocks_for(d.n[c], 4);
   if ((int)blockIdx.x >= nb || !d.has_truth || (mode == 0 && !d.st->upd)) return;
@@ -814,11 +814,11 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
   const int m = bt.host[0].m, ns = bt.ns;
   for (int j = 1; j <= m - 1; ++j) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 4) + nblocks_for(d.n[m - j], 4); });
-    hipLaunchKernelGGL(k_gram, dim3(g, ns), dim3(256), 0, s, bt.dt, j);
+    hipLaunchKernelGGL(k_gram, dim3(g, ns), dim3(1024), 0, s, bt.dt, j);
     hipLaunchKernelGGL(k_gram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, j);
   }
   const int g = max_over(bt, [&](const Dev &d) { return d.blk_off[m]; });
-  hipLaunchKernelGGL(k_tangent, dim3(g, ns), dim3(256), 0, s, bt.dt);
+  hipLaunchKernelGGL(k_tangent, dim3(g, ns), dim3(1024), 0, s, bt.dt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_adaptive_step(bt, s);    // members with the adaptive step only
@@ -829,12 +829,12 @@ hipError_t launch_retract(const Batch &bt, hipStream_t s) {
   const int m = bt.host[0].m, ns = bt.ns;
   for (int b = m - 1; b >= 1; --b) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[b], 4); });
-    hipLaunchKernelGGL(k_rgram, dim3(g, ns), dim3(256), 0, s, bt.dt, b);
+    hipLaunchKernelGGL(k_rgram, dim3(g, ns), dim3(1024), 0, s, bt.dt, b);
     hipLaunchKernelGGL(k_rgram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, b);
   }
   for (int i = 1; i <= m - 1; ++i) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[i - 1], 4); });
-    hipLaunchKernelGGL(k_left, dim3(g, ns), dim3(256), 0, s, bt.dt, i);
+    hipLaunchKernelGGL(k_left, dim3(g, ns), dim3(1024), 0, s, bt.dt, i);
     hipLaunchKernelGGL(k_left_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, i);
   }
   return hipGetLastError();
@@ -844,7 +844,7 @@ hipError_t launch_retract(const Batch &bt, hipStream_t s) {
 hipError_t launch_output(const Batch &bt, hipStream_t s, int init) {
   const int m = bt.host[0].m, ns = bt.ns;
   const int g = max_over(bt, [&](const Dev &d) { return d.blk_off[m]; });
-  hipLaunchKernelGGL(k_output, dim3(g, ns), dim3(256), 0, s, bt.dt, init);
+  hipLaunchKernelGGL(k_output, dim3(g, ns), dim3(1024), 0, s, bt.dt, init);
   hipLaunchKernelGGL(k_output_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, init);
   return hipGetLastError();
 }
@@ -864,7 +864,7 @@ hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode) {
   if (!any) return hipSuccess;
   for (int c = 0; c < m; ++c) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[c], 4); });
-    hipLaunchKernelGGL(k_cross, dim3(g, ns), dim3(256), 0, s, bt.dt, c, mode);
+    hipLaunchKernelGGL(k_cross, dim3(g, ns), dim3(1024), 0, s, bt.dt, c, mode);
     hipLaunchKernelGGL(k_cross_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, c, mode);
   }
   return hipGetLastError();
