@@ -91,7 +91,7 @@ __device__ inline void block_core(const Dev &d, int &c, int &x0, int &x1) {
 __global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j) {
   const Dev &d = dt[blockIdx.y];
   const int R = d.R, RR = R * R, m = d.m;
-  const int nbL = nblocks_for(d.n[j - 1], 4), nbH = nblocks_for(d.n[m - j], 4);
+  const int nbL = nblocks_for(d.n[j - 1], 8), nbH = nblocks_for(d.n[m - j], 8);
   if ((int)blockIdx.x >= nbL + nbH || d.st->done) return;
   __shared__ double smem[SMEM];
   const bool left = (int)blockIdx.x < nbL;
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, i
   if (d.st->done) return;
   __shared__ double smem[SMEM];
   const int R = d.R, RR = R * R, m = d.m;
-  const int nbL = nblocks_for(d.n[j - 1], 4), nbT = nbL + nblocks_for(d.n[m - j], 4);
+  const int nbL = nblocks_for(d.n[j - 1], 8), nbT = nbL + nblocks_for(d.n[m - j], 8);
 
   // last block: totals, inverses
   double *GLj = sm_slot(d, j, S_GL), *THc = sm_slot(d, j - 1, S_TH), *Hb = sm_slot(d, m - j, S_H);
@@ -813,7 +813,7 @@ static int max_over(const Batch &b, Fn f) {
 hipError_t launch_project(const Batch &bt, hipStream_t s) {
   const int m = bt.host[0].m, ns = bt.ns;
   for (int j = 1; j <= m - 1; ++j) {
-    const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 4) + nblocks_for(d.n[m - j], 4); });
+    const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 8) + nblocks_for(d.n[m - j], 8); });
     hipLaunchKernelGGL(k_gram, dim3(g, ns), dim3(1024), 0, s, bt.dt, j);
     hipLaunchKernelGGL(k_gram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, j);
   }
