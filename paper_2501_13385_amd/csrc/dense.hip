@@ -311,12 +311,46 @@ __device__ inline void build_block(const Dev &d, int c, const double *sT, const 
 // right Grams of the block TT: GR_b = sum_x C_b(x) GR_{b+1} C_b(x)^T, b = m-1..1
 // last block: pivoted Cholesky factor F_b of GR_b on its active indices
 // ---------------------------------------------------------------------------
+// Gram of the first left cut, G_B = sum_x B(x)^T B(x) with B(x) = row 0 of
+// C_0(x) (P_0 = 1): it does not depend on the right sweep, so the first
+// right-Gram launch computes its partials in extra blocks (at GB1_OFF of the
+// partial buffer) and the finish of the last right-Gram step uses them.
+constexpr long long GB1_OFF = 1LL << 19;
+
+__device__ void left_cut(const Dev &d, int i, double *smem);
+
+__device__ void gram_first_cut(const Dev &d, int lb) {
+  const int R = d.R, R2 = 2 * R, NE = R2 * R2, RR = R * R;
+  const int nbl = nblocks_for(d.n[0], 4);
+  const int per = (d.n[0] + nbl - 1) / nbl;
+  const int x0 = lb * per, x1 = min(d.n[0], x0 + per);
+  const double alpha = d.st->alpha_n;
+  const auto T = glb(d.cores), X = glb(d.X);
+  for (int f = threadIdx.x; f < NE; f += blockDim.x) {
+    const int a = f / R2, bb = f % R2;
+    double acc = 0.0;
+    for (int x = x0; x < x1; ++x) {
+      const long long off = d.coff[0] + (long long)x * RR;
+      const double va = (a < R) ? -alpha * X[off + a] : T[off + a - R];
+      const double vb = (bb < R) ? -alpha * X[off + bb] : T[off + bb - R];
+      acc += va * vb;
+    }
+    glb(d.part)[GB1_OFF + (long long)lb * NE + f] = acc;
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_rgram(const Dev *__restrict__ dt, int b) {
   const Dev &d = dt[blockIdx.y];
   const int nb = nblocks_for(d.n[b], 4);
-  if ((int)blockIdx.x >= nb || d.st->done) return;
+  const int m = d.m;
+  if (d.st->done) return;
+  if ((int)blockIdx.x >= nb) {
+    const int lb = (int)blockIdx.x - nb;
+    if (b == m - 1 && lb < nblocks_for(d.n[0], 4)) gram_first_cut(d, lb);
+    return;
+  }
   __shared__ double smem[SMEM];
-  const int R = d.R, R2 = 2 * R, NE = R2 * R2, m = d.m;
+  const int R = d.R, R2 = 2 * R, NE = R2 * R2;
   const int per = (d.n[b] + nb - 1) / nb;
   const int x0 = blockIdx.x * per, x1 = min(d.n[b], x0 + per);
   const double alpha = d.st->alpha_n;
@@ -411,6 +445,13 @@ __global__ void __launch_bounds__(1024) k_rgram_fin(const Dev *__restrict__ dt, 
     F[t] = (i >= 0 && col < rank) ? Fc[i * na + col] : 0.0;
   }
   if (threadIdx.x == 0) d.st->rank_f[b] = rank;
+  if (b == 1) {
+    // the first left cut: its Gram came from the first right-Gram launch
+    __threadfence_block();
+    __syncthreads();
+    reduce_partials(d.part + GB1_OFF, nblocks_for(d.n[0], 4), NE, smem, smem + 1024);
+    left_cut(d, 1, smem);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -482,11 +523,9 @@ __global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i
 
 // finish of a left-sweep cut (one block): S = F^T (B^T B) F, eigen-decomposition,
 // truncation to r_i: Tr_i and P_i
-__global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, int i) {
-  const Dev &d = dt[blockIdx.y];
-  const int nb = nblocks_for(d.n[i - 1], 4);
-  if (d.st->done) return;
-  __shared__ double smem[SMEM];
+// Truncation at cut i from G_B (in smem[0, NE)) and F_i (sm slot): S = F^T G_B F,
+// eigen-decomposition, Tr_i and P_i (one block).
+__device__ void left_cut(const Dev &d, int i, double *smem) {
   const int R = d.R, R2 = 2 * R, NE = R2 * R2;
 
   // last block: S = F^T GB F, eigen-decomposition, truncation to r_i
@@ -498,7 +537,6 @@ __global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, i
   double *Vs = smem + 5120;          // rank x rank (sort scratch)
   double *w = smem + 6144;           // 32
   double *cs = smem + 6176;          // 64
-  reduce_partials(d.part, nb, NE, GB, smem + 1024);
   const double *fs = sm_slot(d, i, S_F);
   for (int t = threadIdx.x; t < NE; t += blockDim.x) F[t] = fs[t];
   __syncthreads();
@@ -573,6 +611,15 @@ __global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, i
     for (int k = 0; k < R2; ++k) v += TrL[k * R + a] * GB[k * R2 + bcol];
     Pn[t] = v;
   }
+}
+
+__global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, int i) {
+  const Dev &d = dt[blockIdx.y];
+  const int nb = nblocks_for(d.n[i - 1], 4);
+  if (d.st->done) return;
+  __shared__ double smem[SMEM];
+  reduce_partials(d.part, nb, (2 * d.R) * (2 * d.R), smem, smem + 1024);
+  left_cut(d, i, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -828,11 +875,13 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
 hipError_t launch_retract(const Batch &bt, hipStream_t s) {
   const int m = bt.host[0].m, ns = bt.ns;
   for (int b = m - 1; b >= 1; --b) {
-    const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[b], 4); });
+    const int g = max_over(bt, [&](const Dev &d) {
+      return nblocks_for(d.n[b], 4) + (b == m - 1 ? nblocks_for(d.n[0], 4) : 0);
+    });
     hipLaunchKernelGGL(k_rgram, dim3(g, ns), dim3(1024), 0, s, bt.dt, b);
-    hipLaunchKernelGGL(k_rgram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, b);
+    hipLaunchKernelGGL(k_rgram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, b);   // b = 1 also truncates cut 1
   }
-  for (int i = 1; i <= m - 1; ++i) {
+  for (int i = 2; i <= m - 1; ++i) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[i - 1], 4); });
     hipLaunchKernelGGL(k_left, dim3(g, ns), dim3(1024), 0, s, bt.dt, i);
     hipLaunchKernelGGL(k_left_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, i);
