@@ -1,0 +1,83 @@
+"""Edge cases of the GPU path against the float64 reference: a single
+observation, rank-one TTs (smallest padding), a mode of size one, the largest
+rank at order 4, mostly unobserved slices on the any-order path, a start that
+already fits the data, and a zero iteration budget."""
+
+import numpy as np
+import pytest
+
+from oracle import prgd, tt
+from paper_2501_13385_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2501_13385_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def rel_dist(a, b):
+    return tt.tt_dist(a, b) / tt.tt_norm(b)
+
+
+CASES = {
+    "single_observation": ([3, 4, 5], [1, 1, 1, 1], 1),
+    "rank_one_order4": ([6, 5, 7, 4], [1, 1, 1, 1, 1], 300),
+    "unit_mode": ([1, 7, 6], [1, 1, 3, 1], 30),
+    "rank16_order4": ([6, 8, 8, 6], [1, 6, 16, 6, 1], 2000),
+    "sparse_slices_order4": ([30, 4, 5, 30], [1, 3, 3, 3, 1], 300),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_edge_case_iterates_match_reference(L, name):
+    shape, ranks, n_obs = CASES[name]
+    pb = wl.problem(shape, ranks, n_obs, 21, name=name, init_rel=0.1)
+    print("case", name, shape, ranks, n_obs, flush=True)
+    y = tt.tt_eval(pb.truth, pb.indices)
+    pol = prgd.Policy(step_rule="theory", c=0.5)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, step=0.5, stop_rule="none", max_iter=3)
+    ref = [c.copy() for c in pb.init]
+    try:
+        grads, ssq, rsq = s.sampled_pass()
+        r = prgd.residual(s.cores(), pb.indices, y)
+        assert abs(rsq - float(r @ r)) <= 1e-12 * max(float(r @ r), 1e-300)
+        for it in range(3):
+            s.iterate(1)
+            got = s.cores()
+            ref, _ = prgd.prgd_step(ref, pb.indices, y, pol, pb.ranks)
+            if ref is None:        # the reference reached an exact fit
+                break
+            assert rel_dist(got, ref) <= 1e-10, it
+    finally:
+        s.close()
+
+
+def test_start_that_fits_stops_before_the_first_step(L):
+    pb = wl.named("c1")
+    y = tt.tt_eval(pb.truth, pb.indices)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.truth, stop_rule="residual", tol=1e-12, max_iter=50)
+    try:
+        rep = s.run()
+        got = s.cores()
+    finally:
+        s.close()
+    assert rep["status"] == 0 and rep["iterations"] == 0
+    assert rel_dist(got, pb.truth) <= 1e-13
+
+
+def test_zero_iteration_budget(L):
+    pb = wl.named("c2_small")
+    y = tt.tt_eval(pb.truth, pb.indices)
+    for rule, want in (("none", 0), ("residual", 1)):
+        s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, stop_rule=rule, tol=1e-14, max_iter=0)
+        try:
+            rep = s.run()
+            got = s.cores()
+        finally:
+            s.close()
+        assert rep["iterations"] == 0 and rep["status"] == want, (rule, rep)
+        assert rel_dist(got, pb.init) <= 1e-13
