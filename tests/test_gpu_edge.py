@@ -81,3 +81,60 @@ def test_zero_iteration_budget(L):
             s.close()
         assert rep["iterations"] == 0 and rep["status"] == want, (rule, rep)
         assert rel_dist(got, pb.init) <= 1e-13
+
+
+def test_resume_from_saved_cores_continues_the_run(L):
+    """The state of PRGD is T_l alone: K iterations, then a new solve started from the
+    saved cores for K more, equals 2K iterations in one run."""
+    pb = wl.named("c2_small")
+    y = tt.tt_eval(pb.truth, pb.indices) + pb.noise_std * pb.noise
+    kw = dict(step=0.8, stop_rule="none")
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, max_iter=8, **kw)
+    s.iterate(8)
+    full = s.cores()
+    s.close()
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, max_iter=4, **kw)
+    s.iterate(4)
+    half = s.cores()
+    s.close()
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, half, max_iter=4, **kw)
+    s.iterate(4)
+    resumed = s.cores()
+    s.close()
+    assert rel_dist(resumed, full) <= 1e-10
+
+
+def test_repeated_runs_agree(L):
+    pb = wl.named("c1")
+    y = tt.tt_eval(pb.truth, pb.indices)
+    outs = []
+    for _ in range(2):
+        s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, step=1.001, stop_rule="none", max_iter=20)
+        s.iterate(20)
+        outs.append(s.cores())
+        s.close()
+    assert rel_dist(outs[0], outs[1]) <= 1e-13
+
+
+def test_rank_deficient_start_is_a_breakdown(L):
+    pb = wl.named("c2_small")
+    y = tt.tt_eval(pb.truth, pb.indices)
+    init = [c.copy() for c in pb.init]
+    init[1][:, :, 1:] = 0.0          # bond 2 drops to rank 1 < r_2
+    with pytest.raises(L.PrgdError) as e:
+        L.Solver(pb.shape, pb.ranks, pb.indices, y, init)
+    assert e.value.status == L.EBREAKDOWN
+
+
+def test_iteration_budget_reached_keeps_valid_cores(L):
+    pb = wl.named("c1")
+    y = tt.tt_eval(pb.truth, pb.indices)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, step=1.001, stop_rule="residual", tol=1e-14,
+                 max_iter=3)
+    try:
+        rep = s.run()
+        got = s.cores()
+    finally:
+        s.close()
+    assert rep["status"] == L.NOT_CONVERGED and rep["iterations"] == 3
+    assert np.isfinite(tt.tt_norm(got)) and rel_dist(got, pb.truth) < rel_dist(pb.init, pb.truth)

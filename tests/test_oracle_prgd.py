@@ -298,3 +298,42 @@ def test_noiseless_c1_recovery_other_policies(metric, rule, c):
     res = prgd.prgd(pb.init, pb.indices, y, pol, truth=pb.truth)
     assert res.status == "converged"
     assert tt.tt_dist(res.cores, pb.truth) / tt.tt_norm(pb.truth) <= 1e-9
+
+
+def test_direction_is_the_riemannian_gradient_under_the_metric():
+    """Section 3.2.2: xi = P~_T W^{-1} G is the gradient of f in the metric W restricted to
+    the tangent space, so <xi, eta>_W = <G, eta> for every tangent eta (dense check with
+    W = x_i G_i^{1/(2m)} applied entrywise, random tangent vectors)."""
+    shape, ranks, truth, cores, idx, y = tiny_problem(13, (3, 4, 3), (1, 2, 2, 1))
+    m = len(shape)
+    r = prgd.residual(cores, idx, y)
+    d = prgd.tangent_direction(cores, idx, r)
+    xi = tt.tt_full(prgd.tangent_tt(d.base, d.comps))
+    w = np.ones(shape)
+    for i in range(m):
+        sh = [1] * m
+        sh[i] = shape[i]
+        w = w * (d.g[i] ** (1.0 / (2 * m))).reshape(sh)
+    g = dense_gradient(shape, idx, r)
+    jac = jacobian(cores)
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        eta = (jac @ rng.standard_normal(jac.shape[1])).reshape(shape)     # a tangent vector
+        lhs = float(np.sum(w * xi * eta))
+        rhs = float(np.sum(g * eta))
+        assert abs(lhs - rhs) <= 1e-11 * (abs(rhs) + np.linalg.norm(g) * np.linalg.norm(eta))
+
+
+def test_component_weighted_representation():
+    """Proposition 1: W^{1/2} T has the TT cores T_i x_2 G_i^{1/(4m)}."""
+    shape, ranks, truth, cores, idx, y = tiny_problem(14, (3, 4, 5), (1, 2, 2, 1))
+    m = len(shape)
+    rng = np.random.default_rng(4)
+    g = [1.0 + rng.random(n) for n in shape]
+    scaled = [prgd.scale_mode(cores[k], g[k] ** (1.0 / (4 * m))) for k in range(m)]
+    w = np.ones(shape)
+    for i in range(m):
+        sh = [1] * m
+        sh[i] = shape[i]
+        w = w * (g[i] ** (1.0 / (4 * m))).reshape(sh)
+    np.testing.assert_allclose(tt.tt_full(scaled), w * tt.tt_full(cores), rtol=1e-13, atol=1e-15)
