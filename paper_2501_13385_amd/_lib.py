@@ -115,6 +115,7 @@ def load() -> C.CDLL:
         "prgd_iterate": (i32, [vp, i32]),
         "prgd_sync": (i32, [vp]),
         "prgd_iterate_profiled": (i32, [vp, i32, dp]),
+        "prgd_iterate_timed": (i32, [vp, i32, dp, dp]),
         "prgd_run": (i32, [vp, C.POINTER(prgd_report)]),
         "prgd_get_report": (i32, [vp, C.POINTER(prgd_report)]),
         "prgd_get_cores": (i32, [vp, dp, i64]),
@@ -140,7 +141,7 @@ def load() -> C.CDLL:
 
 
 def exported_symbols() -> List[str]:
-    return [n for n in ("prgd_cores_numel", "prgd_create", "prgd_iterate", "prgd_iterate_profiled",
+    return [n for n in ("prgd_cores_numel", "prgd_create", "prgd_iterate", "prgd_iterate_profiled", "prgd_iterate_timed",
                         "prgd_sync", "prgd_run",
                         "prgd_get_report", "prgd_get_cores", "prgd_get_history", "prgd_sampled_pass",
                         "prgd_eval", "prgd_destroy", "prgd_status_str", "prgd_last_error",
@@ -273,6 +274,14 @@ def prgd_iterate_profiled(h, iters: int) -> dict:
     return {PHASES[i]: float(buf[i]) for i in range(NPHASES)}
 
 
+def prgd_iterate_timed(h, iters: int):
+    """Run `iters` iterations; returns (main sampled kernel ms, whole run ms), device time."""
+    k1 = C.c_double(0.0)
+    tot = C.c_double(0.0)
+    _check(load().prgd_iterate_timed(h, int(iters), C.byref(k1), C.byref(tot)))
+    return float(k1.value), float(tot.value)
+
+
 def prgd_sync(h) -> None:
     _check(load().prgd_sync(h))
 
@@ -370,6 +379,9 @@ class Solver:
 
     def iterate_profiled(self, k: int) -> dict:
         return prgd_iterate_profiled(self.h, k)
+
+    def iterate_timed(self, k: int):
+        return prgd_iterate_timed(self.h, k)
 
     def run(self) -> dict:
         return prgd_run(self.h)

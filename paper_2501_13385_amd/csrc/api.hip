@@ -711,6 +711,43 @@ prgd_status prgd_iterate(prgd_solver s, int32_t iters) {
   return enqueue_iterations(s, iters);
 }
 
+prgd_status prgd_iterate_timed(prgd_solver s, int32_t iters, double *main_ms, double *total_ms) {
+  if (!s) return fail(PRGD_ESTATE, "null solver");
+  if (iters < 0 || !main_ms || !total_ms) return fail(PRGD_EINVAL, "iters < 0 or null output");
+  *main_ms = 0.0;
+  *total_ms = 0.0;
+  if (iters == 0) return PRGD_OK;
+  // ev[2 it] before iteration it, ev[2 it + 1] after its main sampled kernel,
+  // ev[2 iters] after the last iteration
+  std::vector<hipEvent_t> ev((size_t)2 * iters + 1);
+  for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
+  const Batch bt = s->batch();
+  hipError_t err = hipSuccess;
+  auto chk = [&](hipError_t x) { if (x != hipSuccess && err == hipSuccess) err = x; };
+  for (int it = 0; it < iters && err == hipSuccess; ++it) {
+    chk(hipEventRecord(ev[2 * it], s->stream));
+    chk(sampled_pass(s, 0, ev[2 * it + 1]));
+    chk(launch_dense_iteration(bt, s->stream, 0));
+    if (s->has_truth) chk(launch_truth_sweep(bt, s->stream, 0));
+  }
+  chk(hipEventRecord(ev[2 * iters], s->stream));
+  prgd_status rc = PRGD_OK;
+  if (err != hipSuccess) rc = fail(PRGD_EDEVICE, std::string("launch: ") + hipGetErrorString(err));
+  if (rc == PRGD_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = fail(PRGD_EDEVICE, "sync failed");
+  if (rc == PRGD_OK) {
+    for (int it = 0; it < iters; ++it) {
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, ev[2 * it], ev[2 * it + 1]);
+      *main_ms += ms;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[2 * iters]);
+    *total_ms = ms;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  return rc;
+}
+
 prgd_status prgd_iterate_profiled(prgd_solver s, int32_t iters, double *phase_ms) {
   if (!s) return fail(PRGD_ESTATE, "null solver");
   if (iters < 0 || !phase_ms) return fail(PRGD_EINVAL, "iters < 0 or null phase_ms");
@@ -742,7 +779,7 @@ prgd_status prgd_iterate_profiled(prgd_solver s, int32_t iters, double *phase_ms
     for (int it = 0; it < iters; ++it)
       for (int p = 0; p < NP; ++p) {
         float ms = 0.0f;
-        hipEventElapsedTime(&ms, ev[(size_t)it * (NP + 1) + p], ev[(size_t)it * (NP + 1) + p + 1]);
+        (void)hipEventElapsedTime(&ms, ev[(size_t)it * (NP + 1) + p], ev[(size_t)it * (NP + 1) + p + 1]);
         phase_ms[p] += ms;
       }
   for (auto &e : ev) hipEventDestroy(e);

@@ -13,180 +13,255 @@
 
 namespace prgd {
 
-// Pivoted Cholesky of a symmetric positive semidefinite n x n matrix A (ld n,
-// destroyed): F (ld n) gets columns 0..rank-1 with F F^T = A up to pivots
-// below n * 2.3e-16 * max diag.  Returns the rank.
-__device__ inline int block_pivoted_cholesky(double *A, int n, double *F) {
-  __shared__ int piv, rank, stop;
-  __shared__ double pvs, tol;
-  __shared__ unsigned used;
-  const int t = threadIdx.x, nt = blockDim.x;
-  for (int e = t; e < n * n; e += nt) F[e] = 0.0;
-  if (t < 64) {
-    double dm = 0.0;
-    for (int i = t; i < n; i += 64) dm = fmax(dm, A[i * n + i]);
-    dm = wave_max(dm);
-    if (t == 0) {
-      tol = (double)n * 2.3e-16 * dm;
-      rank = 0;
-      used = 0u;
-    }
-  }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    if (t < 64) {
-      const unsigned u = used;
-      double best = -1.0;
-      int bi = 64;
-      if (t < n && !((u >> t) & 1u)) {
-        best = A[t * n + t];
-        bi = t;
-      }
+// 1/x and 1/sqrt(x) for finite x > 0 (normal range): the hardware estimates,
+// good to about 23 bits, refined by `steps` Newton steps (each doubles the
+// number of correct bits, so two reach double precision).
+template <int steps>
+__device__ __forceinline__ double rcp_newton(double x) {
+  double y = __builtin_amdgcn_rcp(x);
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (t == 0) {
-        stop = (bi >= n || !(best > tol)) ? 1 : 0;
-        if (!stop) {
-          piv = bi;
-          pvs = sqrt(best);
-          used = u | (1u << bi);
-          rank = k + 1;
-        }
-      }
-    }
-    __syncthreads();
-    if (stop) break;
-    const int p = piv;
-    const double pv = pvs;
-    const unsigned u = used;
-    for (int i = t; i < n; i += nt) F[i * n + k] = (((u >> i) & 1u) && i != p) ? 0.0 : A[i * n + p] / pv;
-    __syncthreads();
-    for (int e = t; e < n * n; e += nt) {
-      const int i = e / n, j = e % n;
-      A[e] -= F[i * n + k] * F[j * n + k];
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  return rank;
+  for (int k = 0; k < steps; ++k) y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+template <int steps>
+__device__ __forceinline__ double rsq_newton(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+#pragma unroll
+  for (int k = 0; k < steps; ++k) y = fma(y, fma(-h * y, y, 0.5), y);
+  return y;
 }
 
-// Cyclic Jacobi for a symmetric n x n matrix A (ld n, destroyed), n <= 32.
-// Round-robin ordering: each round applies n/2 disjoint rotations; the
-// two-sided update J^T A J is done per 2 x 2 block (one thread per block), so a
-// round is one parameter phase and one update phase.  On exit w[0..n) holds
-// the eigenvalues in descending order and V (ld n) the eigenvectors as columns.
-// cs: 4 * 16 doubles; Vs: n n scratch.
-__device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, double *Vs, double *cs) {
-  __shared__ double sbuf[16];
-  __shared__ int goon;
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int ne = n + (n & 1);
-  const int np = ne / 2;
-  for (int e = t; e < n * n; e += nt) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+// Ordering of LDS accesses among the lanes of one wave.  A wave's LDS
+// operations are performed in issue order, so it suffices to keep the compiler
+// from moving memory operations across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// one DPP exchange of a 64-bit value (both halves moved with the same pattern)
+template <int ctrl>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long k) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)k, ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(k >> 32), ctrl, 0xF, 0xF, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// max of a 64-bit key over each group of 32 lanes (the two halves of the wave
+// reduce separately): DPP exchanges inside rows of 16 lanes, then one swap of
+// the rows.  Keys are compared as unsigned integers.
+__device__ __forceinline__ unsigned long long key_max32(unsigned long long k) {
+  unsigned long long o;
+  o = dpp_u64<0xB1>(k);   // quad_perm [1,0,3,2]: lane ^ 1
+  k = o > k ? o : k;
+  o = dpp_u64<0x4E>(k);   // quad_perm [2,3,0,1]: lane ^ 2
+  k = o > k ? o : k;
+  o = dpp_u64<0x141>(k);  // row_half_mirror: lane i <-> 7 - i within 8
+  k = o > k ? o : k;
+  o = dpp_u64<0x140>(k);  // row_mirror: lane i <-> 15 - i within 16
+  k = o > k ? o : k;
+  o = __shfl_xor(k, 16, 64);
+  return o > k ? o : k;
+}
+
+// Pivoted Cholesky of a symmetric positive semidefinite n x n matrix A (ld n,
+// n <= 32, read only): F (ld n) gets columns 0..rank-1 with F F^T = A up to
+// pivots below n * 2.3e-16 * max diag.  Returns the rank (in every thread).
+//
+// Run by the first wave alone, with no workgroup barrier per step: lane l
+// holds half of row l & 31 of the working matrix in registers (columns
+// 16 (l >> 5) .. + 15) and that row's diagonal entry.  The pivot (largest
+// remaining diagonal entry) is found with a key holding the entry's bits
+// (monotone for non-negative doubles) above 5 bits of 31 - row, so among
+// entries equal to 27 bits the smallest row wins; its exact value is then read
+// from the owning lane.
+__device__ inline int block_pivoted_cholesky(const double *A, int n, double *F) {
+  __shared__ double fcol[32];
+  __shared__ int rank_s;
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const int i = t & 31, h = t >> 5;
+    for (int e = t; e < n * n; e += 64) F[e] = 0.0;
+    double a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int j = 16 * h + c;
+      a[c] = (i < n && j < n) ? A[i * n + j] : 0.0;
+    }
+    double dg = i < n ? A[i * n + i] : 0.0;
+    double dm = dg;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+    const double tol = (double)n * 2.3e-16 * dm;
+    bool avail = i < n;  // row not yet a pivot
+    int rank = 0;
+    for (int k = 0; k < n; ++k) {
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(fmax(dg, 0.0));
+      const unsigned long long key = avail ? ((bits & ~31ull) | (unsigned long long)(31 - i)) : 0ull;
+      const unsigned long long kmax = key_max32(key);
+      const int p = 31 - (int)(__builtin_amdgcn_readfirstlane((unsigned)kmax) & 31u);
+      const double best = __shfl(dg, p, 64);
+      if (kmax == 0ull || !(best > tol)) break;
+      rank = k + 1;
+      const double rs = rsq_newton<2>(best);  // 1 / sqrt(pivot)
+      // this row's entry in column p, from the lane holding that column
+      const int cp = p & 15;
+      double colv = a[0];
+#pragma unroll
+      for (int c = 1; c < 16; ++c) colv = (c == cp) ? a[c] : colv;
+      const double x = __shfl(colv, i + 32 * (p >> 4), 64);
+      const double f = (i == p || avail) && i < n ? x * rs : 0.0;
+      if (i == p) avail = false;
+      dg = fma(-f, f, dg);
+      wave_lds_sync();  // every lane has read fcol of the last step
+      if (h == 0) {
+        fcol[i] = f;
+        if (i < n) F[i * n + k] = f;
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[c] = fma(-f, fcol[16 * h + c], a[c]);
+    }
+    if (t == 0) rank_s = rank;
+  }
   __syncthreads();
+  return rank_s;
+}
+
+// pair P of round rd in the round-robin ordering of m1 + 1 indices (m1 odd):
+// pair 0 is (m1, rd), pair P > 0 is (rd + P, rd - P) mod m1; returned p < q
+__device__ __forceinline__ void round_robin_pair(int rd, int P, int m1, int &p, int &q) {
+  if (P == 0) {
+    p = rd;
+    q = m1;
+    return;
+  }
+  int a = rd + P, b = rd - P + m1;
+  if (a >= m1) a -= m1;
+  if (b >= m1) b -= m1;
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+// Rotation (c, s) that zeroes the (p, q) entry of a symmetric matrix under
+// J^T A J, J = [[c, s], [-s, c]] on rows/columns (p, q): t = tan(theta) is the
+// smaller root of t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) / (2 a_pq).  The
+// angle only has to be accurate enough for fast convergence (an angle off by a
+// relative d leaves about d a_pq, removed in a later sweep), so t comes from
+// the hardware estimates of 1/x and 1/sqrt(x) as they are; c = 1/sqrt(1+t^2) is
+// refined to full precision so that c^2 + s^2 = 1 and the accumulated
+// eigenvectors stay orthonormal.  Entries below 2^-1000 are treated as zero.
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double &c, double &s) {
+  const bool rot = fabs(apq) > 0x1p-1000;
+  const double tau = (aqq - app) * (0.5 * __builtin_amdgcn_rcp(rot ? apq : 1.0));
+  const double at = fabs(tau);
+  const bool big = !(at < 1e150);
+  const double x = fma(big ? 1.0 : at, big ? 1.0 : at, 1.0);
+  const double tt0 = __builtin_amdgcn_rcp(big ? 2.0 * at : at + x * __builtin_amdgcn_rsq(x));
+  const double tt = tau >= 0.0 ? tt0 : -tt0;
+  const double cr = rsq_newton<2>(fma(tt, tt, 1.0));
+  c = rot ? cr : 1.0;
+  s = rot ? tt * cr : 0.0;
+}
+
+// Cyclic Jacobi for a symmetric n x n matrix A (ld n, n <= 32, destroyed),
+// for a block of at least 768 threads.  Round-robin ordering: each round
+// applies n/2 disjoint rotations.  Threads [0, NA) own one 2 x 2 block (P, Q)
+// of A each, threads from the next wave boundary one pair of V entries each;
+// every thread computes the rotations it needs itself from the previous state
+// and writes the next state into the other buffer, so a round costs one
+// barrier.  All operands are loaded unconditionally (indices clamped into the
+// matrix) so that a thread's loads issue together.
+// Sweeps stop once the off-diagonal Frobenius norm is at most 1e-15 of the
+// whole (a converged sweep leaves rounding residue near 3e-16 of it, so a
+// tighter bound would never be met), or once a sweep fails to shrink it (exact
+// rotations always do, so only rounding is left).  On exit w[0..n) holds the
+// eigenvalues in descending order and V (ld n) the eigenvectors as columns.
+// B: n n scratch (destroyed).
+__device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, double *B) {
+  __shared__ double sbuf[16];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int ne = n + (n & 1), np = ne / 2, m1 = ne - 1;
+  const int NA = np * np, NV = n * np;
+  const int v0 = (NA + 63) & ~63;  // first V thread (wave aligned)
+  for (int e = t; e < n * n; e += nt) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+  // this thread's item: block (r, Q) of A, or row r and pair Q of V
+  const bool isA = t < NA, isV = t >= v0 && t < v0 + NV;
+  const int e0 = isA ? t : (isV ? t - v0 : 0);
+  const int r = e0 / np, Q = e0 - r * np;
+  double *cur = A, *nxt = B;
+  __syncthreads();
+  double prev = 0.0;  // off-diagonal mass before the last sweep
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dia = 0.0;
     for (int e = t; e < n * n; e += nt) {
-      const double v = A[e];
+      const double v = cur[e];
       if (e / n == e % n) dia += v * v;
       else off += v * v;
     }
+    // block_sum hands every thread the same totals, so all take the same exit
     off = block_sum(off, sbuf);
     dia = block_sum(dia, sbuf);
-    if (t == 0) goon = (off > 1e-32 * (dia + off)) ? 1 : 0;
-    __syncthreads();
-    if (!goon) break;
-    for (int rd = 0; rd < ne - 1; ++rd) {
-      if (t < np) {
-        int p, q;
-        if (t == 0) {
-          p = ne - 1;
-          q = rd;
-        } else {
-          p = (rd + t) % (ne - 1);
-          q = (rd - t + ne - 1) % (ne - 1);
-        }
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = A[p * n + q];
-          if (apq != 0.0) {
-            const double tau = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
-            const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            s = tt * c;
-          }
-        }
-        cs[4 * t + 0] = c;
-        cs[4 * t + 1] = s;
-        cs[4 * t + 2] = (double)p;
-        cs[4 * t + 3] = (double)q;
-      }
-      __syncthreads();
-      // 2 x 2 block (P, Q) of A: rows {p_P, q_P}, columns {p_Q, q_Q}; then the
-      // rows of V (columns p, q of each pair)
-      for (int it = t; it < np * np + n * np; it += nt) {
-        if (it < np * np) {
-          const int P = it / np, Q = it % np;
-          const int i1 = (int)cs[4 * P + 2], i2 = (int)cs[4 * P + 3];
-          const int j1 = (int)cs[4 * Q + 2], j2 = (int)cs[4 * Q + 3];
-          const double cP = cs[4 * P], sP = cs[4 * P + 1], cQ = cs[4 * Q], sQ = cs[4 * Q + 1];
-          const bool r2 = i2 < n, c2 = j2 < n;
-          const double a11 = A[i1 * n + j1];
-          const double a12 = c2 ? A[i1 * n + j2] : 0.0;
-          const double a21 = r2 ? A[i2 * n + j1] : 0.0;
-          const double a22 = (r2 && c2) ? A[i2 * n + j2] : 0.0;
-          // M = A J_Q
+    if (!(off > 1e-30 * (dia + off)) || (sweep > 0 && off >= prev)) break;
+    prev = off;
+    for (int rd = 0; rd < m1; ++rd) {
+      if (isA || isV) {
+        int j1, j2;
+        round_robin_pair(rd, Q, m1, j1, j2);
+        const bool c2 = j2 < n;
+        const int k2 = c2 ? j2 : j1;
+        const double q11 = cur[j1 * n + j1], q22 = cur[k2 * n + k2], q12 = cur[j1 * n + k2];
+        double cQ, sQ;
+        jacobi_rotation(q11, q22, c2 ? q12 : 0.0, cQ, sQ);
+        if (isA) {
+          int i1, i2;
+          round_robin_pair(rd, r, m1, i1, i2);
+          const bool r2 = i2 < n;
+          const int l2 = r2 ? i2 : i1;
+          const double p11 = cur[i1 * n + i1], p22 = cur[l2 * n + l2], p12 = cur[i1 * n + l2];
+          double cP, sP;
+          jacobi_rotation(p11, p22, r2 ? p12 : 0.0, cP, sP);
+          const double x11 = cur[i1 * n + j1], x12 = cur[i1 * n + k2];
+          const double x21 = cur[l2 * n + j1], x22 = cur[l2 * n + k2];
+          const double a11 = x11, a12 = c2 ? x12 : 0.0, a21 = r2 ? x21 : 0.0, a22 = (r2 && c2) ? x22 : 0.0;
+          // M = A J_Q, then J_P^T M
           const double m11 = cQ * a11 - sQ * a12, m12 = sQ * a11 + cQ * a12;
           const double m21 = cQ * a21 - sQ * a22, m22 = sQ * a21 + cQ * a22;
-          // J_P^T M
-          A[i1 * n + j1] = cP * m11 - sP * m21;
-          if (c2) A[i1 * n + j2] = cP * m12 - sP * m22;
-          if (r2) A[i2 * n + j1] = sP * m11 + cP * m21;
-          if (r2 && c2) A[i2 * n + j2] = sP * m12 + cP * m22;
+          nxt[i1 * n + j1] = cP * m11 - sP * m21;
+          if (c2) nxt[i1 * n + j2] = cP * m12 - sP * m22;
+          if (r2) nxt[i2 * n + j1] = sP * m11 + cP * m21;
+          if (r2 && c2) nxt[i2 * n + j2] = sP * m12 + cP * m22;
         } else {
-          const int e = it - np * np;
-          const int i = e / np, Q = e % np;
-          const int p = (int)cs[4 * Q + 2], q = (int)cs[4 * Q + 3];
-          if (q < n) {
-            const double c = cs[4 * Q], s = cs[4 * Q + 1];
-            const double vp = V[i * n + p], vq = V[i * n + q];
-            V[i * n + p] = c * vp - s * vq;
-            V[i * n + q] = s * vp + c * vq;
+          const double vp = V[r * n + j1], vq = V[r * n + k2];
+          if (c2) {
+            V[r * n + j1] = cQ * vp - sQ * vq;
+            V[r * n + j2] = sQ * vp + cQ * vq;
           }
         }
       }
       __syncthreads();
+      double *x = cur;
+      cur = nxt;
+      nxt = x;
     }
   }
-  // sort descending (stable by index)
+  // sort descending (stable by index); nxt is free and takes the permuted V
   for (int i = t; i < n; i += nt) {
-    const double wi = A[i * n + i];
+    const double wi = cur[i * n + i];
     int rk = 0;
     for (int j = 0; j < n; ++j) {
-      const double wj = A[j * n + j];
+      const double wj = cur[j * n + j];
       if (wj > wi || (wj == wi && j < i)) ++rk;
     }
     w[rk] = wi;
-    for (int r = 0; r < n; ++r) Vs[r * n + rk] = V[r * n + i];
+    for (int rr = 0; rr < n; ++rr) nxt[rr * n + rk] = V[rr * n + i];
   }
   __syncthreads();
-  for (int e = t; e < n * n; e += nt) V[e] = Vs[e];
+  for (int e = t; e < n * n; e += nt) V[e] = nxt[e];
   __syncthreads();
 }
-
 
 // Inverses of two SPD matrices by Gauss-Jordan elimination on [A | I] (no
 // pivoting needed for SPD), the two eliminations advancing in lockstep.  The
