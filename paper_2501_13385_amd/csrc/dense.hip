@@ -534,7 +534,7 @@ __device__ void left_cut(const Dev &d, int i, double *smem) {
   double *T1 = smem + 2048;          // GB F (2R x rank)
   double *S = smem + 3072;           // rank x rank
   double *V = smem + 4096;           // rank x rank
-  double *Vs = smem + 5120;          // rank x rank (Jacobi scratch)
+  double *Vs = smem + 5120;          // Jacobi scratch (1024)
   double *w = smem + 6144;           // 32
   const double *fs = sm_slot(d, i, S_F);
   for (int t = threadIdx.x; t < NE; t += blockDim.x) F[t] = fs[t];
@@ -575,7 +575,7 @@ __device__ void left_cut(const Dev &d, int i, double *smem) {
     }
   }
   __syncthreads();
-  block_jacobi_eig(S, rk, V, w, Vs);
+  block_jacobi_eig(S, rk, V, w, T1, Vs);  // T1 is free once S is formed
   if (threadIdx.x == 0) {
     const double s0 = w[0];
     if (!(w[ri - 1] > 1e-28 * s0) || !isfinite(s0)) bad = 1;

@@ -166,78 +166,122 @@ __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double a
   s = rot ? tt * cr : 0.0;
 }
 
-// Cyclic Jacobi for a symmetric n x n matrix A (ld n, n <= 32, destroyed),
-// for a block of at least 768 threads.  Round-robin ordering: each round
-// applies n/2 disjoint rotations.  Threads [0, NA) own one 2 x 2 block (P, Q)
-// of A each, threads from the next wave boundary one pair of V entries each;
-// every thread computes the rotations it needs itself from the previous state
-// and writes the next state into the other buffer, so a round costs one
-// barrier.  All operands are loaded unconditionally (indices clamped into the
-// matrix) so that a thread's loads issue together.
+// one DPP exchange of a double (both halves moved with the same pattern)
+template <int ctrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+  return __builtin_bit_cast(double, (long long)dpp_u64<ctrl>((unsigned long long)__builtin_bit_cast(long long, v)));
+}
+
+// Sums of a and b over the block, the same value in every thread (fixed
+// order).  Every thread of the block must call it.  sb: 32 doubles.
+__device__ inline void block_sum2(double &a, double &b, double *sb) {
+  // rows of 16 lanes by DPP (the same total in every lane of a row)
+  a += dpp_f64<0xB1>(a);
+  b += dpp_f64<0xB1>(b);
+  a += dpp_f64<0x4E>(a);
+  b += dpp_f64<0x4E>(b);
+  a += dpp_f64<0x141>(a);
+  b += dpp_f64<0x141>(b);
+  a += dpp_f64<0x140>(a);
+  b += dpp_f64<0x140>(b);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  double sa = 0.0, sbv = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    sa += __shfl(a, 16 * r, 64);
+    sbv += __shfl(b, 16 * r, 64);
+  }
+  if (lane == 0) {
+    sb[w] = sa;
+    sb[16 + w] = sbv;
+  }
+  __syncthreads();
+  a = 0.0;
+  b = 0.0;
+  for (int k = 0; k < nw; ++k) {
+    a += sb[k];
+    b += sb[16 + k];
+  }
+}
+
+// Cyclic Jacobi for a symmetric n x n matrix A (ld n, n <= 32), for a block of
+// at least 256 threads.  The matrix and V are held padded to ne = n + (n & 1)
+// (a zero row and column, on which every rotation is exactly the identity),
+// so that no index needs a bound check.  Round-robin ordering: each round
+// applies ne/2 disjoint rotations.  Thread (P, Q), P, Q < ne/2, owns the 2 x 2
+// block (P, Q) of A and the 2 x 2 block of V with rows in pair P and columns
+// in pair Q; it computes the two rotations it needs itself from the previous
+// state and writes the next state of A into the other buffer, so a round
+// costs one barrier and at most four waves work (one per SIMD).  The
+// off-diagonal mass for the stopping rule is summed from the entries written
+// in a sweep's last round.
 // Sweeps stop once the off-diagonal Frobenius norm is at most 1e-15 of the
 // whole (a converged sweep leaves rounding residue near 3e-16 of it, so a
 // tighter bound would never be met), or once a sweep fails to shrink it (exact
 // rotations always do, so only rounding is left).  On exit w[0..n) holds the
 // eigenvalues in descending order and V (ld n) the eigenvectors as columns.
-// B: n n scratch (destroyed).
-__device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, double *B) {
-  __shared__ double sbuf[16];
+// A is read first and its area (1024 doubles) then reused as scratch; W1, W2:
+// scratch, 1024 doubles each.
+__device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, double *W1, double *W2) {
+  __shared__ double sb[32];
   const int t = threadIdx.x, nt = blockDim.x;
   const int ne = n + (n & 1), np = ne / 2, m1 = ne - 1;
-  const int NA = np * np, NV = n * np;
-  const int v0 = (NA + 63) & ~63;  // first V thread (wave aligned)
-  for (int e = t; e < n * n; e += nt) V[e] = (e / n == e % n) ? 1.0 : 0.0;
-  // this thread's item: block (r, Q) of A, or row r and pair Q of V
-  const bool isA = t < NA, isV = t >= v0 && t < v0 + NV;
-  const int e0 = isA ? t : (isV ? t - v0 : 0);
-  const int r = e0 / np, Q = e0 - r * np;
-  double *cur = A, *nxt = B;
+  double *cur = W1, *nxt = W2, *Vp = A;
+  double off = 0.0, dia = 0.0;
+  for (int e = t; e < ne * ne; e += nt) {
+    const int i = e / ne, j = e - i * ne;
+    const double v = (i < n && j < n) ? A[i * n + j] : 0.0;
+    cur[e] = v;
+    if (i == j) dia += v * v;
+    else off += v * v;
+  }
+  block_sum2(off, dia, sb);  // ends with a barrier: A has been read
+  for (int e = t; e < ne * ne; e += nt) Vp[e] = (e / ne == e % ne) ? 1.0 : 0.0;
+  const bool act = t < np * np;
+  const int P = act ? t / np : 0, Q = act ? t - P * np : 0;
   __syncthreads();
   double prev = 0.0;  // off-diagonal mass before the last sweep
   for (int sweep = 0; sweep < 40; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int e = t; e < n * n; e += nt) {
-      const double v = cur[e];
-      if (e / n == e % n) dia += v * v;
-      else off += v * v;
-    }
-    // block_sum hands every thread the same totals, so all take the same exit
-    off = block_sum(off, sbuf);
-    dia = block_sum(dia, sbuf);
     if (!(off > 1e-30 * (dia + off)) || (sweep > 0 && off >= prev)) break;
     prev = off;
+    off = 0.0;
+    dia = 0.0;
     for (int rd = 0; rd < m1; ++rd) {
-      if (isA || isV) {
-        int j1, j2;
+      if (act) {
+        int i1, i2, j1, j2;
+        round_robin_pair(rd, P, m1, i1, i2);
         round_robin_pair(rd, Q, m1, j1, j2);
-        const bool c2 = j2 < n;
-        const int k2 = c2 ? j2 : j1;
-        const double q11 = cur[j1 * n + j1], q22 = cur[k2 * n + k2], q12 = cur[j1 * n + k2];
-        double cQ, sQ;
-        jacobi_rotation(q11, q22, c2 ? q12 : 0.0, cQ, sQ);
-        if (isA) {
-          int i1, i2;
-          round_robin_pair(rd, r, m1, i1, i2);
-          const bool r2 = i2 < n;
-          const int l2 = r2 ? i2 : i1;
-          const double p11 = cur[i1 * n + i1], p22 = cur[l2 * n + l2], p12 = cur[i1 * n + l2];
-          double cP, sP;
-          jacobi_rotation(p11, p22, r2 ? p12 : 0.0, cP, sP);
-          const double x11 = cur[i1 * n + j1], x12 = cur[i1 * n + k2];
-          const double x21 = cur[l2 * n + j1], x22 = cur[l2 * n + k2];
-          const double a11 = x11, a12 = c2 ? x12 : 0.0, a21 = r2 ? x21 : 0.0, a22 = (r2 && c2) ? x22 : 0.0;
-          // M = A J_Q, then J_P^T M
-          const double m11 = cQ * a11 - sQ * a12, m12 = sQ * a11 + cQ * a12;
-          const double m21 = cQ * a21 - sQ * a22, m22 = sQ * a21 + cQ * a22;
-          nxt[i1 * n + j1] = cP * m11 - sP * m21;
-          if (c2) nxt[i1 * n + j2] = cP * m12 - sP * m22;
-          if (r2) nxt[i2 * n + j1] = sP * m11 + cP * m21;
-          if (r2 && c2) nxt[i2 * n + j2] = sP * m12 + cP * m22;
-        } else {
-          const double vp = V[r * n + j1], vq = V[r * n + k2];
-          if (c2) {
-            V[r * n + j1] = cQ * vp - sQ * vq;
-            V[r * n + j2] = sQ * vp + cQ * vq;
+        const int ri1 = __umul24(i1, ne), ri2 = __umul24(i2, ne), rj1 = __umul24(j1, ne), rj2 = __umul24(j2, ne);
+        const double p11 = cur[ri1 + i1], p22 = cur[ri2 + i2], p12 = cur[ri1 + i2];
+        const double q11 = cur[rj1 + j1], q22 = cur[rj2 + j2], q12 = cur[rj1 + j2];
+        const double a11 = cur[ri1 + j1], a12 = cur[ri1 + j2];
+        const double a21 = cur[ri2 + j1], a22 = cur[ri2 + j2];
+        const double v11 = Vp[ri1 + j1], v12 = Vp[ri1 + j2];
+        const double v21 = Vp[ri2 + j1], v22 = Vp[ri2 + j2];
+        double cP, sP, cQ, sQ;
+        jacobi_rotation(p11, p22, p12, cP, sP);
+        jacobi_rotation(q11, q22, q12, cQ, sQ);
+        // M = A J_Q, then J_P^T M
+        const double m11 = cQ * a11 - sQ * a12, m12 = sQ * a11 + cQ * a12;
+        const double m21 = cQ * a21 - sQ * a22, m22 = sQ * a21 + cQ * a22;
+        const double b11 = cP * m11 - sP * m21, b12 = cP * m12 - sP * m22;
+        const double b21 = sP * m11 + cP * m21, b22 = sP * m12 + cP * m22;
+        nxt[ri1 + j1] = b11;
+        nxt[ri1 + j2] = b12;
+        nxt[ri2 + j1] = b21;
+        nxt[ri2 + j2] = b22;
+        // V J_Q on rows i1, i2
+        Vp[ri1 + j1] = cQ * v11 - sQ * v12;
+        Vp[ri1 + j2] = sQ * v11 + cQ * v12;
+        Vp[ri2 + j1] = cQ * v21 - sQ * v22;
+        Vp[ri2 + j2] = sQ * v21 + cQ * v22;
+        if (rd == m1 - 1) {
+          const double s4 = b11 * b11 + b12 * b12 + b21 * b21 + b22 * b22;
+          if (P == Q) {  // b11, b22 on the diagonal
+            dia += b11 * b11 + b22 * b22;
+            off += b12 * b12 + b21 * b21;
+          } else {
+            off += s4;
           }
         }
       }
@@ -246,20 +290,19 @@ __device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, 
       cur = nxt;
       nxt = x;
     }
+    block_sum2(off, dia, sb);
   }
-  // sort descending (stable by index); nxt is free and takes the permuted V
+  // sort descending (stable by index)
   for (int i = t; i < n; i += nt) {
-    const double wi = cur[i * n + i];
+    const double wi = cur[i * ne + i];
     int rk = 0;
     for (int j = 0; j < n; ++j) {
-      const double wj = cur[j * n + j];
+      const double wj = cur[j * ne + j];
       if (wj > wi || (wj == wi && j < i)) ++rk;
     }
     w[rk] = wi;
-    for (int rr = 0; rr < n; ++rr) nxt[rr * n + rk] = V[rr * n + i];
+    for (int rr = 0; rr < n; ++rr) V[rr * n + rk] = Vp[rr * ne + i];
   }
-  __syncthreads();
-  for (int e = t; e < n * n; e += nt) V[e] = nxt[e];
   __syncthreads();
 }
 
