@@ -213,22 +213,29 @@ __global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, i
     return;
   }
   if (j == m - 1) {
-    // Psi_c = GL_{c+1}^{-1} Theta_c H_{c+1}^{-1}, c = 0..m-2
+    // Psi_c = GL_{c+1}^{-1} Theta_c H_{c+1}^{-1}, c = 0..m-2 (operands staged
+    // in LDS; the inverses were written above or by earlier launches)
+    double *gi = smem, *th = smem + 256, *hi = smem + 512, *t1 = smem + 768;
     for (int cc = 0; cc < m - 1; ++cc) {
-      const double *gi = sm_slot(d, cc + 1, S_GLI), *th = sm_slot(d, cc, S_TH), *hi = sm_slot(d, cc + 1, S_HI);
-      double *t1 = smem;
+      const auto ggi = glb(sm_slot(d, cc + 1, S_GLI)), gth = glb(sm_slot(d, cc, S_TH)), ghi = glb(sm_slot(d, cc + 1, S_HI));
       for (int t = threadIdx.x; t < RR; t += blockDim.x) {
-        const int a = t / R, b = t % R;
+        gi[t] = ggi[t];
+        th[t] = gth[t];
+        hi[t] = ghi[t];
+      }
+      __syncthreads();
+      for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+        const int a = t / R, b = t - a * R;
         double v = 0.0;
-        for (int k = 0; k < R; ++k) v += gi[a * R + k] * th[k * R + b];
+        for (int k = 0; k < R; ++k) v = fma(gi[a * R + k], th[k * R + b], v);
         t1[t] = v;
       }
       __syncthreads();
-      double *psi = sm_slot(d, cc, S_PSI);
+      auto psi = glb(sm_slot(d, cc, S_PSI));
       for (int t = threadIdx.x; t < RR; t += blockDim.x) {
-        const int a = t / R, b = t % R;
+        const int a = t / R, b = t - a * R;
         double v = 0.0;
-        for (int k = 0; k < R; ++k) v += t1[a * R + k] * hi[k * R + b];
+        for (int k = 0; k < R; ++k) v = fma(t1[a * R + k], hi[k * R + b], v);
         psi[t] = v;
       }
       __syncthreads();

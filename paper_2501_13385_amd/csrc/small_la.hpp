@@ -320,6 +320,10 @@ __device__ inline bool block_spd_inverse_pair(const double *A1, int lda1, int n1
   const int t = threadIdx.x, nt = blockDim.x;
   const int w1 = 2 * n1, w2 = 2 * n2, s1 = n1 * w1, s2 = n2 * w2, tot = s1 + s2;
   double *buf[2] = {scratch, scratch + tot};
+  // this thread's first entry (row i, column j of its matrix)
+  const bool first0 = t < s1;
+  const int w0 = first0 ? w1 : w2, nn0 = first0 ? n1 : n2, base0 = first0 ? 0 : s1;
+  const int i0 = (t - base0) / w0, j0 = (t - base0) - i0 * w0;
   for (int e = t; e < tot; e += nt) {
     double v;
     if (e < s1) {
@@ -339,22 +343,21 @@ __device__ inline bool block_spd_inverse_pair(const double *A1, int lda1, int n1
     const double *M = buf[cur];
     double *Mn = buf[cur ^ 1];
     for (int e = t; e < tot; e += nt) {
-      const bool first = e < s1;
-      const int w = first ? w1 : w2, n = first ? n1 : n2, base = first ? 0 : s1;
-      const int f = e - base, i = f / w, j = f % w;
-      if (k >= n) {
-        Mn[e] = M[e];
-        continue;
+      bool first = first0;
+      int w = w0, n = nn0, base = base0, i = i0, j = j0;
+      if (e != t) {
+        first = e < s1;
+        w = first ? w1 : w2;
+        n = first ? n1 : n2;
+        base = first ? 0 : s1;
+        i = (e - base) / w;
+        j = (e - base) - i * w;
       }
-      const double pk = M[base + k * w + k];
-      const double pj = M[base + k * w + j];
-      if (i == k) {
-        Mn[e] = pj / pk;
-      } else {
-        const double fi = M[base + i * w + k];
-        Mn[e] = M[e] - fi * (pj / pk);
-      }
-      if (j == k && i == k && (!(pk > 0.0) || !isfinite(pk))) bad = 1;
+      const int kk = k < n ? k : 0;  // keeps the loads in range when k >= n
+      const double pk = M[base + kk * w + kk], pj = M[base + kk * w + j], fi = M[base + i * w + kk], me = M[e];
+      const double q = pj * rcp_newton<2>(pk);
+      Mn[e] = k >= n ? me : (i == k ? q : fma(-fi, q, me));
+      if (k < n && j == k && i == k && (!(pk > 0.0) || !isfinite(pk))) bad = 1;
     }
     __syncthreads();
     cur ^= 1;
