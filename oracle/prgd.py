@@ -366,3 +366,57 @@ def spectral_init_dense(idx: np.ndarray, y: np.ndarray, shape: Sequence[int], ra
     x = np.zeros(shape)
     x[tuple(idx)] = y
     return tt.tt_svd_dense(x / sampling_ratio(idx.shape[1], shape), ranks)
+
+
+def spectral_init_sketch(idx: np.ndarray, y: np.ndarray, shape: Sequence[int], ranks: Sequence[int],
+                         gauss: Sequence[np.ndarray]) -> Cores:
+    """``T_0 ~ SVD^tt_r(P_Omega(y) / p)``: Algorithm 1 with every unfolding replaced by a sketch.
+
+    Z = P_Omega(y) / p with p = |Omega| / d* (the spectral initialisation the
+    convergence analysis assumes).  Algorithm 1 takes at split i the top r_i
+    left singular vectors of the projected unfolding
+    A_i = (T^{<=i-1} kron I_{n_i})^T Z^{<i>}, whose columns run over the later
+    modes.  Here A_i is multiplied on the right by a random test matrix Psi_i
+    whose row for the later indices (x_{i+1}, ..., x_m) is the elementwise
+    product of the rows Gamma_{i,k}[x_k, :] of independent standard-normal
+    matrices (one per later mode; E[Psi Psi^T] is a multiple of I), and the
+    core is the top r_i left singular vectors of the sketch Y_i = A_i Psi_i.
+    Y_i only needs the observed entries:
+    Y_i[(a, x), c] = sum over samples with x_i = x of
+    z_j ell_{i-1}(x^(j))[a] psi_i(x^(j))[c], with ell the interface of the
+    cores already built.  The last core is A_m itself.
+
+    ``gauss``: the matrices Gamma_{i,k} in split-major order (see
+    ``workloads.sketch_gaussians``).  Plain float64 loops over the samples
+    (``numpy.add.at``); singular vectors from ``numpy.linalg.svd``.
+    """
+    shape = [int(s) for s in shape]
+    m = len(shape)
+    idx = np.asarray(idx, dtype=np.int64)
+    n_obs = idx.shape[1]
+    z = np.asarray(y, dtype=np.float64) / sampling_ratio(n_obs, shape)
+    ell = np.ones((n_obs, 1))                     # ell_{i-1}(x^(j)), one row per sample
+    cores: Cores = []
+    g = 0
+    for i in range(m - 1):
+        r_prev, n_i, r_i = int(ranks[i]), shape[i], int(ranks[i + 1])
+        psi = None
+        for k in range(i + 1, m):
+            rows = np.asarray(gauss[g])[idx[k]]       # Gamma_{i,k}[x_k(j), :]
+            psi = rows if psi is None else psi * rows
+            g += 1
+        sketch = psi.shape[1]
+        Y = np.zeros((r_prev, n_i, sketch))
+        contrib = (z[:, None] * ell)[:, :, None] * psi[:, None, :]   # (N, r_prev, sketch)
+        np.add.at(Y, (slice(None), idx[i]), np.transpose(contrib, (1, 0, 2)))
+        u, sv, _ = np.linalg.svd(Y.reshape(r_prev * n_i, sketch), full_matrices=False)
+        if u.shape[1] < r_i or not sv[r_i - 1] > 1e-14 * sv[0]:
+            raise ValueError("sketch rank below the target rank")
+        core = u[:, :r_i].reshape(r_prev, n_i, r_i)
+        cores.append(core)
+        ell = np.einsum("ja,ajb->jb", ell, core[:, idx[i], :])
+    r_prev, n_m = int(ranks[m - 1]), shape[m - 1]
+    last = np.zeros((r_prev, n_m))
+    np.add.at(last, (slice(None), idx[m - 1]), (z[:, None] * ell).T)
+    cores.append(last.reshape(r_prev, n_m, 1))
+    return cores

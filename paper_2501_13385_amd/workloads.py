@@ -36,6 +36,7 @@ __all__ = [
     "named",
     "NAMED",
     "serving_mix",
+    "sketch_gaussians",
 ]
 
 
@@ -342,4 +343,20 @@ def random_mps(n_sites: int, bond: int, rng: np.random.Generator, local: int = 2
         re = rng.standard_normal((sl, local, sr))
         im = rng.standard_normal((sl, local, sr))
         out.append((re + 1j * im) / math.sqrt(2.0))
+    return out
+
+
+def sketch_gaussians(shape: Sequence[int], sketch: int, rng: np.random.Generator) -> List[np.ndarray]:
+    """Standard-normal test matrices for the sketched spectral initialisation.
+
+    For every split i = 0..m-2 (0-based) and every later mode k = i+1..m-1 one
+    ``(n_k, sketch)`` matrix, in that order (split-major).  Returned as a flat
+    list; ``numpy.concatenate([g.ravel() for g in ...])`` is the packed layout
+    the library takes.
+    """
+    m = len(shape)
+    out: List[np.ndarray] = []
+    for i in range(m - 1):
+        for k in range(i + 1, m):
+            out.append(rng.standard_normal((int(shape[k]), int(sketch))))
     return out

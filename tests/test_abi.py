@@ -99,3 +99,13 @@ def test_server_rejects_bad_arguments_before_device_work():
     assert lib.prgd_server_poll(None, 1, None, None, 0) == L.ESTATE
     assert lib.prgd_server_wait(None, 1, 0.0) == L.ESTATE
     assert lib.prgd_server_destroy(None) == L.ESTATE
+
+
+def test_iteration_calls_reject_a_null_solver():
+    lib = L.load()
+    buf = (ctypes.c_double * L.NPHASES)()
+    a, b = ctypes.c_double(1.0), ctypes.c_double(1.0)
+    assert lib.prgd_iterate(None, 1) == L.ESTATE
+    assert lib.prgd_iterate_profiled(None, 1, buf) == L.ESTATE
+    assert lib.prgd_iterate_timed(None, 1, ctypes.byref(a), ctypes.byref(b)) == L.ESTATE
+    assert lib.prgd_sync(None) == L.ESTATE

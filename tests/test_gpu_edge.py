@@ -138,3 +138,30 @@ def test_iteration_budget_reached_keeps_valid_cores(L):
         s.close()
     assert rep["status"] == L.NOT_CONVERGED and rep["iterations"] == 3
     assert np.isfinite(tt.tt_norm(got)) and rel_dist(got, pb.truth) < rel_dist(pb.init, pb.truth)
+
+
+def test_timed_and_profiled_iterations_match_plain_ones(L):
+    """prgd_iterate_timed and prgd_iterate_profiled run the same iterations as
+    prgd_iterate (bit for bit) and report non-negative device times."""
+    pb = wl.named("c2_small")
+    y = tt.tt_eval(pb.truth, pb.indices)
+    outs = {}
+    for mode in ("plain", "timed", "profiled"):
+        s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, step=0.9, stop_rule="none", max_iter=8)
+        try:
+            if mode == "plain":
+                s.iterate(6)
+                s.sync()
+            elif mode == "timed":
+                k1, total = s.iterate_timed(6)
+                assert 0.0 < k1 <= total
+            else:
+                ph = s.iterate_profiled(6)
+                assert len(ph) == L.NPHASES and all(v >= 0.0 for v in ph.values())
+            assert s.report()["iterations"] == 6
+            outs[mode] = s.cores()
+        finally:
+            s.close()
+    for mode in ("timed", "profiled"):
+        for a, b in zip(outs[mode], outs["plain"]):
+            assert np.array_equal(a, b), mode
