@@ -410,7 +410,9 @@ def spectral_init_sketch(idx: np.ndarray, y: np.ndarray, shape: Sequence[int], r
         contrib = (z[:, None] * ell)[:, :, None] * psi[:, None, :]   # (N, r_prev, sketch)
         np.add.at(Y, (slice(None), idx[i]), np.transpose(contrib, (1, 0, 2)))
         u, sv, _ = np.linalg.svd(Y.reshape(r_prev * n_i, sketch), full_matrices=False)
-        if u.shape[1] < r_i or not sv[r_i - 1] > 1e-14 * sv[0]:
+        # numerical rank: r_i-th singular value above 1e-7 of the largest (the
+        # resolution of a Gram-matrix eigen-decomposition in float64)
+        if u.shape[1] < r_i or not sv[r_i - 1] > 1e-7 * sv[0]:
             raise ValueError("sketch rank below the target rank")
         core = u[:, :r_i].reshape(r_prev, n_i, r_i)
         cores.append(core)
