@@ -209,6 +209,33 @@ prgd_status prgd_eval(int32_t m, const int32_t *n, const int32_t *r, const doubl
                       int64_t n_obs, const int32_t *indices, double *out, int32_t mem_device,
                       void *stream);
 
+/* Sketched spectral initialisation T_0 ~ SVD^tt_r(P_Omega(y) / p), p =
+   |Omega| / prod n_k: the starting point the convergence analysis assumes
+   (Theorem 1; the spectral choice is Algorithm 1 applied to the rescaled
+   sampled tensor).  Algorithm 1's projected unfolding A_i at split i
+   (i = 1..m-1) is replaced by the sketch Y_i = A_i Psi_i, where the row of
+   Psi_i for the later indices (x_{i+1}, ..., x_m) is the elementwise product
+   of the rows Gamma_{i,k}[x_k, :] of the caller's standard-normal test
+   matrices; core i is the top r_i left singular vectors of Y_i (so cores
+   1..m-1 are left-orthonormal) and core m is A_m.  For an exact TT-rank-r
+   tensor observed in full the result reproduces the tensor.
+     m, n[m], r[m+1]  order, mode sizes, TT ranks (r_0 = r_m = 1, r_k <= 16)
+     indices   host int32 SoA [m * n_obs], values host float64 [n_obs]
+     sketch    columns of every test matrix, max(r) <= sketch <= 32
+     gauss     host float64: for i = 1..m-1 and k = i+1..m, Gamma_{i,k}
+               (n_k x sketch, row-major) in that order
+     cores_out host float64, packed like prgd_eval's cores (prgd_cores_numel)
+     stream    hipStream_t or NULL; returns after cores_out is written.
+   Multi-indices are not required to be distinct (repeats add up).  Device
+   memory is allocated for the call and freed before it returns.
+   Errors: PRGD_EINVAL (arguments, index range, non-finite values),
+   PRGD_ENOTSUP (ranks above 16), PRGD_EBREAKDOWN (a sketch whose r_i-th
+   singular value is not above 1e-7 of its largest: too few samples for the
+   ranks), PRGD_EDEVICE. */
+prgd_status prgd_spectral_init(int32_t m, const int32_t *n, const int32_t *r, int64_t n_obs,
+                               const int32_t *indices, const double *values, int32_t sketch,
+                               const double *gauss, double *cores_out, void *stream);
+
 prgd_status prgd_destroy(prgd_solver s);
 
 /* ------------------------------------------------------------------------

@@ -122,6 +122,7 @@ def load() -> C.CDLL:
         "prgd_get_history": (i32, [vp, C.POINTER(prgd_iter_info), i32, i32p]),
         "prgd_sampled_pass": (i32, [vp, dp, dp, dp]),
         "prgd_eval": (i32, [i32, i32p, i32p, dp, i64, vp, vp, i32, vp]),
+        "prgd_spectral_init": (i32, [i32, i32p, i32p, i64, vp, vp, i32, vp, vp, vp]),
         "prgd_destroy": (i32, [vp]),
         "prgd_status_str": (C.c_char_p, [i32]),
         "prgd_last_error": (C.c_char_p, []),
@@ -144,7 +145,7 @@ def exported_symbols() -> List[str]:
     return [n for n in ("prgd_cores_numel", "prgd_create", "prgd_iterate", "prgd_iterate_profiled", "prgd_iterate_timed",
                         "prgd_sync", "prgd_run",
                         "prgd_get_report", "prgd_get_cores", "prgd_get_history", "prgd_sampled_pass",
-                        "prgd_eval", "prgd_destroy", "prgd_status_str", "prgd_last_error",
+                        "prgd_eval", "prgd_spectral_init", "prgd_destroy", "prgd_status_str", "prgd_last_error",
                         "prgd_server_create", "prgd_server_submit", "prgd_server_poll", "prgd_server_wait",
                         "prgd_server_stats", "prgd_server_destroy")]
 
@@ -336,6 +337,27 @@ def prgd_sampled_pass(h, shape, ranks):
                                     ssq.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rsq)))
     splits = np.cumsum(shape)[:-1]
     return unpack(grad, shape, ranks), list(np.split(ssq, splits)), float(rsq.value)
+
+
+def prgd_spectral_init(shape, ranks, indices, values, gauss, sketch, stream=None) -> List[np.ndarray]:
+    """Sketched spectral initialisation on the GPU; host numpy in, list of cores out.
+
+    ``gauss``: the standard-normal test matrices (see
+    ``workloads.sketch_gaussians``), a list of arrays or one packed array.
+    """
+    lib = load()
+    m = len(shape)
+    idx = np.ascontiguousarray(indices, dtype=np.int32)
+    val = np.ascontiguousarray(values, dtype=np.float64)
+    if isinstance(gauss, np.ndarray) and gauss.ndim == 1:
+        g = np.ascontiguousarray(gauss, dtype=np.float64)
+    else:
+        g = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in gauss]))
+    numel = sum(int(ranks[k]) * int(shape[k]) * int(ranks[k + 1]) for k in range(m))
+    out = np.empty(max(numel, 1), dtype=np.float64)
+    _check(lib.prgd_spectral_init(m, _i32arr(shape), _i32arr(ranks), int(idx.shape[1]), idx.ctypes.data, val.ctypes.data,
+                                  int(sketch), g.ctypes.data, out.ctypes.data, stream))
+    return unpack(out, shape, ranks)
 
 
 def prgd_eval(shape, ranks, cores, indices, out=None, stream=None):

@@ -109,3 +109,27 @@ def test_iteration_calls_reject_a_null_solver():
     assert lib.prgd_iterate_profiled(None, 1, buf) == L.ESTATE
     assert lib.prgd_iterate_timed(None, 1, ctypes.byref(a), ctypes.byref(b)) == L.ESTATE
     assert lib.prgd_sync(None) == L.ESTATE
+
+
+def test_spectral_init_rejects_bad_arguments_before_device_work():
+    shape, ranks = [4, 5, 6], [1, 2, 3, 1]
+    idx = np.array([[0, 1], [2, 3], [4, 5]], dtype=np.int32)
+    y = np.ones(2)
+    g = np.zeros(sum(shape[k] * 5 for i in range(2) for k in range(i + 1, 3)))
+    with pytest.raises(L.PrgdError) as e:
+        L.prgd_spectral_init(shape, ranks, idx, y, g, 2)          # sketch below max rank
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.PrgdError) as e:
+        L.prgd_spectral_init(shape, ranks, idx, y, g, 33)         # sketch above 32
+    assert e.value.status == L.EINVAL
+    bad = idx.copy()
+    bad[2, 1] = 6
+    with pytest.raises(L.PrgdError) as e:
+        L.prgd_spectral_init(shape, ranks, bad, y, g, 5)          # index out of range
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.PrgdError) as e:
+        L.prgd_spectral_init(shape, [1, 2, 17, 1], idx, y, g, 20)  # rank above 16
+    assert e.value.status == L.ENOTSUP
+    with pytest.raises(L.PrgdError) as e:
+        L.prgd_spectral_init(shape, ranks, idx, np.array([1.0, np.nan]), g, 5)
+    assert e.value.status == L.EINVAL

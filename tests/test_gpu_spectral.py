@@ -1,0 +1,97 @@
+"""Sketched spectral initialisation on the GPU against the reference
+(``oracle.prgd.spectral_init_sketch``) on the same test matrices, compared as
+tensors (cores may differ by signs of singular vectors): small cases of
+orders 2-4 and the n = 400 order-3 workload; exact recovery at full
+observation; the rank-deficient sketch error; and a solve started from the
+device initialisation."""
+
+import numpy as np
+import pytest
+
+from oracle import prgd, tt
+from paper_2501_13385_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2501_13385_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def rel(a, b):
+    return tt.tt_dist(a, b) / tt.tt_norm(b)
+
+
+CASES = {
+    "order2": ([40, 33], [1, 4, 1], 300, 7),
+    "order3": ([20, 18, 25], [1, 3, 4, 1], 2000, 8),
+    "order3_odd_sketch": ([17, 9, 13], [1, 3, 3, 1], 700, 5),
+    "order4": ([8, 7, 9, 6], [1, 2, 3, 2, 1], 1500, 6),
+    "order5_rank16": ([6, 5, 6, 5, 6], [1, 6, 16, 16, 6, 1], 5000, 16),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_matches_reference(L, name):
+    shape, ranks, n_obs, s = CASES[name]
+    print(f"spectral init case {name}: shape {shape} ranks {ranks} N {n_obs} sketch {s}", flush=True)
+    rng = wl.make_rng(21)
+    truth = wl.gaussian_cores(shape, ranks, rng)
+    idx = wl.sample_indices(shape, n_obs, rng)
+    y = tt.tt_eval(truth, idx) + 0.01 * rng.standard_normal(n_obs)
+    g = wl.sketch_gaussians(shape, s, rng)
+    ref = prgd.spectral_init_sketch(idx, y, shape, ranks, g)
+    got = L.prgd_spectral_init(shape, ranks, idx, y, g, s)
+    assert rel(got, ref) <= 1e-10
+    for c in got[:-1]:
+        u = c.reshape(-1, c.shape[2])
+        assert np.abs(u.T @ u - np.eye(u.shape[1])).max() <= 1e-12
+
+
+def test_exact_rank_tensor_in_full(L):
+    shape, ranks = [7, 6, 8], [1, 3, 2, 1]
+    rng = wl.make_rng(22)
+    truth = wl.gaussian_cores(shape, ranks, rng)
+    full = np.array(np.unravel_index(np.arange(int(np.prod(shape))), shape), dtype=np.int32)
+    y = tt.tt_eval(truth, full)
+    got = L.prgd_spectral_init(shape, ranks, full, y, wl.sketch_gaussians(shape, 5, rng), 5)
+    assert rel(got, truth) <= 1e-12
+
+
+def test_full_size_workload(L):
+    pb = wl.named("c2")
+    print(f"spectral init full size: shape {pb.shape} N {pb.n_obs}", flush=True)
+    rng = wl.make_rng(23)
+    y = tt.tt_eval(pb.truth, pb.indices) + pb.noise_std * pb.noise
+    g = wl.sketch_gaussians(pb.shape, 14, rng)
+    ref = prgd.spectral_init_sketch(pb.indices, y, pb.shape, pb.ranks, g)
+    got = L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, y, g, 14)
+    assert rel(got, ref) <= 1e-10
+
+
+def test_rank_deficient_sketch_is_reported(L):
+    shape, ranks = [6, 6, 6], [1, 3, 3, 1]
+    rng = wl.make_rng(24)
+    idx = wl.sample_indices(shape, 2, rng)
+    with pytest.raises(L.PrgdError) as e:
+        L.prgd_spectral_init(shape, ranks, idx, np.ones(2), wl.sketch_gaussians(shape, 5, rng), 5)
+    assert e.value.status == L.EBREAKDOWN
+
+
+def test_solve_from_device_initialisation(L):
+    pb = wl.named("c2_small")
+    rng = wl.make_rng(25)
+    y = tt.tt_eval(pb.truth, pb.indices)
+    init = L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, y, wl.sketch_gaussians(pb.shape, max(pb.ranks) + 4, rng),
+                                max(pb.ranks) + 4)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, init, step_policy="adaptive", stop_rule="change", tol=1e-12,
+                 max_iter=400)
+    try:
+        s.run()
+        got = s.cores()
+    finally:
+        s.close()
+    assert rel(got, pb.truth) <= 1e-6
