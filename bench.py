@@ -314,6 +314,16 @@ def main():
                          "iters_to_tol": m["iters_to_tol"], "rel_error_at_tol": m["rel_error_at_tol"],
                          "k1_ms_per_step": m["k1_ms_per_step"],
                          "phase_ms_per_step": m["phase_ms_per_step"], "dtype": "f32+f64"}
+    # sketched spectral initialisation of the same workload (host inputs, the
+    # call includes the host-to-device copies and the per-mode sorts)
+    vals = L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices) + pb.noise_std * pb.noise
+    sk = max(pb.ranks) + 4
+    gauss = np.concatenate([a.ravel() for a in wl.sketch_gaussians(pb.shape, sk, wl.make_rng(1))])
+    L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, vals, gauss, sk)     # warm-up
+    t0 = time.perf_counter()
+    L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, vals, gauss, sk)
+    line["spectral_init_s"] = time.perf_counter() - t0
+    line["spectral_init_sketch"] = sk
     if not args.no_serving:
         line["serving"] = serving_leg(L, args.serve_requests, args.serve_max_obs)
     if not args.no_cpu_baseline:

@@ -18,8 +18,9 @@
 //     r_k[c]) are fetched directly in the MFMA lane layout, so no transpose
 //     is needed; each wave's accumulator is added into a small per-workgroup
 //     segment table in LDS when the segment changes.
-// A second kernel sums the partials in a fixed order (deterministic) and
-// finishes the metric weights.
+// A second kernel sums the partials in a fixed order and finishes the metric
+// weights.  The LDS atomics inside a workgroup add in an order that varies from
+// run to run, so results repeat to rounding, not bit for bit.
 #include <algorithm>
 
 #include "prgd_internal.hpp"

@@ -142,7 +142,9 @@ def test_iteration_budget_reached_keeps_valid_cores(L):
 
 def test_timed_and_profiled_iterations_match_plain_ones(L):
     """prgd_iterate_timed and prgd_iterate_profiled run the same iterations as
-    prgd_iterate (bit for bit) and report non-negative device times."""
+    prgd_iterate and report non-negative device times.  (The order-3 pass
+    accumulates boundary gradients with LDS atomics, whose order varies from
+    run to run, so agreement is to rounding, as between two plain runs.)"""
     pb = wl.named("c2_small")
     y = tt.tt_eval(pb.truth, pb.indices)
     outs = {}
@@ -163,5 +165,4 @@ def test_timed_and_profiled_iterations_match_plain_ones(L):
         finally:
             s.close()
     for mode in ("timed", "profiled"):
-        for a, b in zip(outs[mode], outs["plain"]):
-            assert np.array_equal(a, b), mode
+        assert rel_dist(outs[mode], outs["plain"]) <= 1e-13, mode
