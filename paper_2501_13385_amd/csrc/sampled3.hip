@@ -167,7 +167,10 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
         flush();
         wv = v;
       }
-      const auto S = cores + co2 + (long long)v * RR;
+      // the middle slice is uniform across the wave: read it through the
+      // constant address space so that it lands in scalar registers
+      typedef __attribute__((address_space(4))) const F *cptr;
+      const cptr S = (cptr)((const F *)(cores + co2 + (long long)v * RR));
       F res = (F)0;
       if (me) {
         F l1[R], r3[R], u[R], l2[R];
