@@ -387,8 +387,9 @@ def spectral_init_sketch(idx: np.ndarray, y: np.ndarray, shape: Sequence[int], r
     cores already built.  The last core is A_m itself.
 
     ``gauss``: the matrices Gamma_{i,k} in split-major order (see
-    ``workloads.sketch_gaussians``).  Plain float64 loops over the samples
-    (``numpy.add.at``); singular vectors from ``numpy.linalg.svd``.
+    ``workloads.sketch_gaussians``).  Plain float64: the sums run mode value by
+    mode value over the matching samples; singular vectors from
+    ``numpy.linalg.svd``.
     """
     shape = [int(s) for s in shape]
     m = len(shape)
@@ -407,8 +408,10 @@ def spectral_init_sketch(idx: np.ndarray, y: np.ndarray, shape: Sequence[int], r
             g += 1
         sketch = psi.shape[1]
         Y = np.zeros((r_prev, n_i, sketch))
-        contrib = (z[:, None] * ell)[:, :, None] * psi[:, None, :]   # (N, r_prev, sketch)
-        np.add.at(Y, (slice(None), idx[i]), np.transpose(contrib, (1, 0, 2)))
+        zl = z[:, None] * ell
+        for x in range(n_i):                           # samples with x_i = x
+            sel = idx[i] == x
+            Y[:, x, :] = zl[sel].T @ psi[sel]
         u, sv, _ = np.linalg.svd(Y.reshape(r_prev * n_i, sketch), full_matrices=False)
         # numerical rank: r_i-th singular value above 1e-7 of the largest (the
         # resolution of a Gram-matrix eigen-decomposition in float64)
@@ -419,6 +422,8 @@ def spectral_init_sketch(idx: np.ndarray, y: np.ndarray, shape: Sequence[int], r
         ell = np.einsum("ja,ajb->jb", ell, core[:, idx[i], :])
     r_prev, n_m = int(ranks[m - 1]), shape[m - 1]
     last = np.zeros((r_prev, n_m))
-    np.add.at(last, (slice(None), idx[m - 1]), (z[:, None] * ell).T)
+    zl = z[:, None] * ell
+    for x in range(n_m):
+        last[:, x] = zl[idx[m - 1] == x].sum(axis=0)
     cores.append(last.reshape(r_prev, n_m, 1))
     return cores
