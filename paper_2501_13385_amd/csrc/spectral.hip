@@ -16,10 +16,12 @@
 // top r_i left singular vectors of Y_i, taken from the eigen-decomposition of
 // its Gram matrix (U = Y V_r D_r^{-1/2}); the last core is A_m itself.
 //
-// Work per split: Omega is grouped by x_i (stable radix sort), one workgroup
-// per value x accumulates its rows of Y_i in a fixed order (deterministic),
-// together with its share of the Gram matrix; one workgroup sums the shares,
-// runs the Jacobi eigen-solver and writes the core.
+// Work per split: Omega is grouped by x_i (stable radix sort); the samples of
+// each value x are cut into a fixed number of chunks whose workgroups
+// accumulate partial rows of Y_i in a fixed order, a second kernel adds the
+// chunks in order (deterministic) and forms each value's share of the Gram
+// matrix, and one workgroup sums the shares, runs the Jacobi eigen-solver and
+// writes the core.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -48,8 +50,10 @@ struct SketchArgs {
   int n[MAXM], r[MAXM + 1];
   long long goff[MAXM];        // offset of Gamma_{split,k} in gam (k > split)
   const double *gam;
+  int chunks;                  // workgroups per value of x_split
+  double *Ypart;               // [chunks][r_split * n_split][s] partial sketches
   double *Y;                   // rows (a * n_split + x), s columns
-  double *gpart;               // n_split blocks of s x s Gram shares
+  double *gpart;               // n_split blocks of s x s Gram shares (null: last core)
 };
 
 // first position in the sorted key column with key >= v
@@ -63,16 +67,19 @@ __device__ long long lower_bound_key(const int *key, long long N, int v) {
   return lo;
 }
 
+// Workgroup (x, ch): chunk ch of the samples with x_split = x, partial rows
+// (a, x) of Y_i into Ypart[ch].
 __global__ void __launch_bounds__(SK_NT) k_sketch(const SketchArgs A) {
-  __shared__ double zl[SK_B][SK_MAXR + 1], ps[SK_B][SK_MAXS + 1], yb[SK_MAXR][SK_MAXS + 1];
+  __shared__ double zl[SK_B][SK_MAXR + 1], ps[SK_B][SK_MAXS + 1];
   __shared__ long long seg[2];
-  const int x = blockIdx.x, t = threadIdx.x, i = A.split, s = A.s;
+  const int x = blockIdx.x, ch = blockIdx.y, t = threadIdx.x, i = A.split, s = A.s;
   const int rp = A.r[i];
   const long long N = A.N;
   const int *key = A.idx + (long long)i * N;
   if (t == 0) {
-    seg[0] = lower_bound_key(key, N, x);
-    seg[1] = lower_bound_key(key, N, x + 1);
+    const long long b0 = lower_bound_key(key, N, x), b1 = lower_bound_key(key, N, x + 1);
+    seg[0] = b0 + (b1 - b0) * ch / A.chunks;
+    seg[1] = b0 + (b1 - b0) * (ch + 1) / A.chunks;
   }
   __syncthreads();
   const long long lo = seg[0], hi = seg[1];
@@ -114,13 +121,25 @@ __global__ void __launch_bounds__(SK_NT) k_sketch(const SketchArgs A) {
       for (int b = 0; b < SK_B; ++b) acc = fma(zl[b][a], ps[b][c], acc);
     __syncthreads();
   }
-  if (act) {
+  if (act) A.Ypart[((long long)ch * rp * A.n[i] + (long long)a * A.n[i] + x) * s + c] = acc;
+}
+
+// Workgroup x: the rows (a, x) of Y_i as the sum of the chunks in order, and
+// (unless this is the last core) this value's share of Y_i^T Y_i.
+__global__ void __launch_bounds__(SK_NT) k_sketch_sum(const SketchArgs A) {
+  __shared__ double yb[SK_MAXR][SK_MAXS + 1];
+  const int x = blockIdx.x, t = threadIdx.x, i = A.split, s = A.s;
+  const int rp = A.r[i];
+  const int a = t / s, c = t - (t / s) * s;
+  if (a < rp) {
+    double acc = 0.0;
+    for (int ch = 0; ch < A.chunks; ++ch)
+      acc += A.Ypart[((long long)ch * rp * A.n[i] + (long long)a * A.n[i] + x) * s + c];
     A.Y[((long long)a * A.n[i] + x) * s + c] = acc;
     yb[a][c] = acc;
   }
   if (A.gpart == nullptr) return;
   __syncthreads();
-  // this value's share of Y^T Y
   for (int e = t; e < s * s; e += SK_NT) {
     const int c1 = e / s, c2 = e - (e / s) * s;
     double g = 0.0;
@@ -162,6 +181,9 @@ __global__ void __launch_bounds__(1024) k_sketch_core(const SketchArgs A, int *b
     core[e] = u / sqrt(w[col]);
   }
 }
+
+// workgroups per mode value: about 2048 workgroups per split in all, at most 64
+int sketch_chunks(int n_mode) { return std::max(1, std::min(64, (2048 + n_mode - 1) / n_mode)); }
 
 struct DevBuf {
   std::vector<void *> p;
@@ -220,13 +242,14 @@ extern "C" prgd_status prgd_spectral_init(int32_t m, const int32_t *n, const int
   A.m = m;
   A.N = n_obs;
   A.inv_p = numel_d / (double)n_obs;
-  long long numel = 0, rows_max = 0, nmax = 0;
+  long long numel = 0, rows_max = 0, nmax = 0, part_max = 0;
   for (int k = 0; k < m; ++k) {
     A.n[k] = n[k];
     A.coff[k] = numel;
     numel += (long long)r[k] * n[k] * r[k + 1];
     rows_max = std::max(rows_max, (long long)r[k] * n[k]);
     nmax = std::max(nmax, (long long)n[k]);
+    part_max = std::max(part_max, (long long)sketch_chunks(n[k]) * r[k] * n[k]);
   }
   A.coff[m] = numel;
   for (int k = 0; k <= m; ++k) A.r[k] = r[k];
@@ -243,7 +266,9 @@ extern "C" prgd_status prgd_spectral_init(int32_t m, const int32_t *n, const int
   SKCHECK(buf.get(&d_sval, (size_t)n_obs));
   SKCHECK(buf.get(&d_cores, (size_t)numel));
   SKCHECK(buf.get(&d_gam, (size_t)ngauss));
+  double *d_Yp = nullptr;
   SKCHECK(buf.get(&d_Y, (size_t)(rows_max * sketch)));
+  SKCHECK(buf.get(&d_Yp, (size_t)(part_max * sketch)));
   SKCHECK(buf.get(&d_gp, (size_t)(nmax * sketch * sketch)));
   SKCHECK(buf.get(&d_bad, 1));
   SKCHECK(hipMemcpyAsync(d_idx, indices, (size_t)m * n_obs * sizeof(int), hipMemcpyHostToDevice, st));
@@ -269,7 +294,11 @@ extern "C" prgd_status prgd_spectral_init(int32_t m, const int32_t *n, const int
       }
     A.Y = last ? d_cores + A.coff[m - 1] : d_Y;
     A.gpart = last ? nullptr : d_gp;
-    hipLaunchKernelGGL(k_sketch, dim3(n[i]), dim3(SK_NT), 0, st, A);
+    A.chunks = sketch_chunks(n[i]);
+    A.Ypart = d_Yp;
+    hipLaunchKernelGGL(k_sketch, dim3(n[i], A.chunks), dim3(SK_NT), 0, st, A);
+    SKCHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_sketch_sum, dim3(n[i]), dim3(SK_NT), 0, st, A);
     SKCHECK(hipGetLastError());
     if (!last) {
       hipLaunchKernelGGL(k_sketch_core, dim3(1), dim3(1024), 0, st, A, d_bad);
