@@ -919,6 +919,16 @@ prgd_status prgd_eval(int32_t m, const int32_t *n, const int32_t *r, const doubl
   double *dc = nullptr, *dout = nullptr;
   long long *dcoff = nullptr;
   int *didx = nullptr;
+  // device buffers freed on every exit, after the work queued on st has finished
+  struct Bufs {
+    hipStream_t st;
+    void **p[4];
+    ~Bufs() {
+      (void)hipStreamSynchronize(st);
+      for (void **q : p)
+        if (*q) (void)hipFree(*q);
+    }
+  } bufs{st, {(void **)&dc, (void **)&dout, (void **)&dcoff, (void **)&didx}};
   HIPCHECK(hipMalloc(&dc, packed.size() * sizeof(double)));
   HIPCHECK(hipMalloc(&dcoff, coff.size() * sizeof(long long)));
   HIPCHECK(hipMemcpy(dc, packed.data(), packed.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -935,10 +945,7 @@ prgd_status prgd_eval(int32_t m, const int32_t *n, const int32_t *r, const doubl
   HIPCHECK(launch_eval(m, R, n_obs, ip, dc, dcoff, op, st));
   HIPCHECK(hipStreamSynchronize(st));
   if (!mem_device) HIPCHECK(hipMemcpy(out, dout, (size_t)n_obs * sizeof(double), hipMemcpyDeviceToHost));
-  hipFree(dc);
-  hipFree(dcoff);
-  if (didx) hipFree(didx);
-  if (dout) hipFree(dout);
+
   return PRGD_OK;
 }
 

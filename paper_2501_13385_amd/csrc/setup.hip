@@ -75,6 +75,16 @@ hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *id
   int *keys_out = nullptr, *perm_in = nullptr, *perm_out = nullptr;
   void *temp = nullptr;
   size_t temp_bytes = 0;
+  // scratch freed on every exit, after the work queued on s has finished
+  struct Scratch {
+    hipStream_t s;
+    void **p[4];
+    ~Scratch() {
+      (void)hipStreamSynchronize(s);
+      for (void **q : p)
+        if (*q) (void)hipFree(*q);
+    }
+  } scratch{s, {(void **)&keys_out, (void **)&perm_in, (void **)&perm_out, &temp}};
   unsigned end_bit = 1;
   while (end_bit < 31 && (1u << end_bit) < (unsigned)n_mode) ++end_bit;
   if ((e = hipMalloc((void **)&keys_out, N * sizeof(int))) != hipSuccess) return e;
@@ -100,12 +110,7 @@ hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *id
                                 (const float *)values_in, perm_out, y32);
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-  hipFree(temp);
-  hipFree(keys_out);
-  hipFree(perm_in);
-  hipFree(perm_out);
-  return hipGetLastError();
+  return hipStreamSynchronize(s);
 }
 
 // copy each batch member's State to out[i] (thread i)

@@ -185,9 +185,13 @@ __global__ void __launch_bounds__(1024) k_sketch_core(const SketchArgs A, int *b
 // workgroups per mode value: about 2048 workgroups per split in all, at most 64
 int sketch_chunks(int n_mode) { return std::max(1, std::min(64, (2048 + n_mode - 1) / n_mode)); }
 
+// device buffers of one call, freed on every exit after the work queued on
+// the call's stream has finished
 struct DevBuf {
+  hipStream_t st = nullptr;
   std::vector<void *> p;
   ~DevBuf() {
+    (void)hipStreamSynchronize(st);
     for (void *q : p) (void)hipFree(q);
   }
   template <typename T>
@@ -258,6 +262,7 @@ extern "C" prgd_status prgd_spectral_init(int32_t m, const int32_t *n, const int
     for (int k = i + 1; k < m; ++k) ngauss += (long long)n[k] * sketch;
 
   DevBuf buf;
+  buf.st = st;
   int *d_idx = nullptr, *d_sidx = nullptr, *d_bad = nullptr;
   double *d_val = nullptr, *d_sval = nullptr, *d_cores = nullptr, *d_gam = nullptr, *d_Y = nullptr, *d_gp = nullptr;
   SKCHECK(buf.get(&d_idx, (size_t)m * n_obs));
