@@ -59,7 +59,19 @@ __host__ __device__ inline size_t modes_lds_bytes(int R, int prec, int nt) {
   return ((size_t)(nt / 64) * 2 * 64 * R + (size_t)KSEG * (R * R + 1)) * f;
 }
 
-template <typename F, int R, int NT>
+// Cores of every mode staged in LDS when they fit in this many bytes: the
+// interfaces gather a whole slice per sample and mode, which then comes from
+// LDS (broadcast when lanes share a slice) instead of the caches.
+constexpr size_t MODES_STAGE_MAX = 64 * 1024;
+
+// the staged copy or the global cores (keeping the global address space)
+template <bool STAGE, typename L, typename G>
+__device__ __forceinline__ auto pick_cores(L staged, G global) {
+  if constexpr (STAGE) return staged;
+  else return global;
+}
+
+template <typename F, int R, int NT, bool STAGE>
 __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int diag) {
   const Dev &d = dt[blockIdx.y];
   if ((int)blockIdx.x >= d.mt_wg || (!diag && d.st->done)) return;
@@ -78,9 +90,12 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
   F *P = lseg + KSEG * SEGW + (long long)w * 2 * 64 * R;   // [64][R]: R_j l_j
   F *Q = P + 64 * R;                                        // [64][R]: r_j
   for (int i = threadIdx.x; i < KSEG * SEGW; i += NT) lseg[i] = (F)0;
+  const auto gcores = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores));
+  F *lcores = lseg + KSEG * SEGW + (long long)NW * 2 * 64 * R;
+  if (STAGE)
+    for (long long i = threadIdx.x; i < d.coff[m]; i += NT) lcores[i] = gcores[i];
   __syncthreads();
-
-  const auto cores = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores));
+  const auto cores = pick_cores<STAGE>((const F *)lcores, gcores);
   const auto y = glb((const F *)q.y);
   const long long N = d.N;
   const auto idx = glb(q.idx);
@@ -263,8 +278,13 @@ static hipError_t launch_modes_t(const Batch &bt, int diag, hipStream_t st, hipE
     g = std::max(g, bt.host[i].mt_wg);
     go = std::max<long long>(go, bt.host[i].mt_out);
   }
-  const size_t lds = modes_lds_bytes(R, bt.host[0].prec, NT);
-  hipLaunchKernelGGL((k_modes<F, R, NT>), dim3(g, bt.ns), dim3(NT), lds, st, bt.dt, diag);
+  size_t lds = modes_lds_bytes(R, bt.host[0].prec, NT), core_bytes = 0;
+  for (int i = 0; i < bt.ns; ++i)
+    core_bytes = std::max(core_bytes, (size_t)bt.host[i].coff[bt.host[i].m] * sizeof(F));
+  if (core_bytes <= MODES_STAGE_MAX)
+    hipLaunchKernelGGL((k_modes<F, R, NT, true>), dim3(g, bt.ns), dim3(NT), lds + core_bytes, st, bt.dt, diag);
+  else
+    hipLaunchKernelGGL((k_modes<F, R, NT, false>), dim3(g, bt.ns), dim3(NT), lds, st, bt.dt, diag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (after_main && (e = hipEventRecord(after_main, st)) != hipSuccess) return e;
