@@ -111,6 +111,12 @@ typedef struct {
                                   -1 chooses the mode with the largest r_{k-1} r_k         */
   void *stream;                /* hipStream_t to run on; NULL: a stream owned by the solver */
   int32_t metric;              /* PRGD_METRIC_* (0 = PRGD)                                  */
+  int32_t mode_interfaces;     /* orders whose sampled pass runs mode by mode: 1 = one
+                                  pass forms every sample's left and right interfaces and
+                                  residual and the mode passes read them, -1 = every mode
+                                  pass re-evaluates them, 0 = choose (1 when |Omega| >=
+                                  65536 and the stored interfaces take at most 8 GiB).
+                                  Results agree to rounding either way.                     */
 } prgd_desc;
 
 /* One row of the per-iteration record kept on the device. */

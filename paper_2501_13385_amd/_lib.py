@@ -53,6 +53,7 @@ class prgd_desc(C.Structure):
         ("sort_mode", C.c_int32),
         ("stream", C.c_void_p),
         ("metric", C.c_int32),
+        ("mode_interfaces", C.c_int32),
     ]
 
 
@@ -197,7 +198,7 @@ def _ptr_of(a):
 
 def _make_desc(shape, ranks, indices, values, init_cores, *, truth_cores=None, precision="fp64",
                step_policy="theory", step=1.0, eps_fixed=0.0, stop_rule="residual", tol=1e-10,
-               max_iter=500, sort_mode=-1, stream=None, metric="data"):
+               max_iter=500, sort_mode=-1, stream=None, metric="data", mode_interfaces=0):
     """prgd_desc for the arguments, plus the objects that must outlive the call."""
     m = len(shape)
     keep = []
@@ -245,6 +246,7 @@ def _make_desc(shape, ranks, indices, values, init_cores, *, truth_cores=None, p
     d.sort_mode = int(sort_mode)
     d.stream = stream
     d.metric = METRIC[metric]
+    d.mode_interfaces = int(mode_interfaces)
     keep += [ns, rs]
     return d, keep
 

@@ -126,6 +126,15 @@ bool use_mode_passes(int m, const int *n, int R, int prec, long long N) {
 // workgroups of one mode's pass
 long long mode_pass_wgs(long long N) { return std::min<long long>(1024, std::max<long long>(1, (N + 2047) / 2048)); }
 
+// whether the mode passes read stored interfaces (option: 1 yes, -1 no, 0 when
+// Omega is large enough for the saved chain work to outweigh one more launch,
+// N >= 65536, and the records and position maps take at most 8 GiB)
+bool use_stored_interfaces(int option, int m, int R, int prec, long long N) {
+  if (option != 0) return option > 0;
+  const long long f = prec == PREC_MIXED ? 4 : 8;
+  return N >= 65536 && (long long)m * N * ((2LL * R + 1) * f + 4) <= (8LL << 30);
+}
+
 prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *vals, int64_t &numel) {
   const int m = ds->order;
   if (m < 2 || m > MAXM) return fail(m < 2 ? PRGD_EINVAL : PRGD_ENOTSUP, "order must be in [2, 32]");
@@ -149,6 +158,7 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
       ds->step_policy != PRGD_STEP_ADAPTIVE)
     return fail(PRGD_EINVAL, "step_policy");
   if (ds->metric != PRGD_METRIC_DATA && ds->metric != PRGD_METRIC_EUCLIDEAN) return fail(PRGD_EINVAL, "metric");
+  if (ds->mode_interfaces < -1 || ds->mode_interfaces > 1) return fail(PRGD_EINVAL, "mode_interfaces must be -1, 0 or 1");
   if (ds->step_policy == PRGD_STEP_CONST && ds->metric == PRGD_METRIC_DATA && !(ds->eps_fixed > 0.0))
     return fail(PRGD_EINVAL, "the constant step policy needs eps_fixed > 0");
   if (ds->stop_rule < PRGD_STOP_RESIDUAL || ds->stop_rule > PRGD_STOP_NONE) return fail(PRGD_EINVAL, "stop_rule");
@@ -287,6 +297,8 @@ int64_t solver_footprint(const prgd_desc *ds) {
         b += (int64_t)(m - 1) * (4 * m * N + f * N);      // sorted copies per mode
         for (int k = 0; k < m; ++k) b += nwg * (KSEG * segw * f + 4) + (int64_t)nv[k] * (segw * f + 8);
         b += 8 * nwg + (int64_t)m * (int64_t)sizeof(ModeTab) + 64 * 256 * 6 * m;
+        if (use_stored_interfaces(ds->mode_interfaces, m, R, ds->precision, N))
+          b += (int64_t)m * N * ((2 * R + 1) * f + 4) + 12 * N;   // records, position maps, permutations
       } else {
         sampled_plan(m, nv.data(), R, ds->precision, N, off, tot, nbs);
         b += (int64_t)nbs * tot * f;
@@ -445,6 +457,12 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     return cleanup(fail(PRGD_ENOTSUP, "order x rank too large for the sampled-pass interface stack"));
 
   const bool mixed = d.prec == PREC_MIXED;
+  // sampled-pass variant (decided here because the stored-interface form needs
+  // the permutation of the first grouping)
+  const bool use3_cand = m == 3 && sm == 1 && sampled3_lds_bytes(s->n[0], s->n[2], R, d.prec, 0) <= 163840;
+  const bool modes_cand = !use3_cand && use_mode_passes(m, s->n.data(), R, d.prec, N);
+  const bool want_iface = modes_cand && use_stored_interfaces(ds->mode_interfaces, m, R, d.prec, N);
+  int *perm0 = nullptr, *perm_k = nullptr, *inv_k = nullptr;
   // allocations
   int *idx_raw = nullptr, *idx_sorted = nullptr;
   void *val_raw = nullptr;
@@ -481,8 +499,11 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     idx_dev = idx_raw;
     val_dev = val_raw;
   }
+  if (want_iface && (!A(s->alloc(&perm0, N)) || !A(s->alloc(&perm_k, N)) || !A(s->alloc(&inv_k, N))))
+    return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
   {
-    hipError_t e = group_by_mode(m, N, sm, s->n[sm], idx_dev, val_dev, ds->values_fp64, idx_sorted, y64, y32, s->stream);
+    hipError_t e = group_by_mode(m, N, sm, s->n[sm], idx_dev, val_dev, ds->values_fp64, idx_sorted, y64, y32, s->stream,
+                                 perm0);
     if (e != hipSuccess) return cleanup(fail(PRGD_EDEVICE, std::string("grouping Omega: ") + hipGetErrorString(e)));
   }
 
@@ -594,10 +615,19 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   d.mp_rsq = nullptr;
   d.mt_wg = 0;
   d.mt_out = 0;
-  if (!d.use3 && use_mode_passes(m, s->n.data(), R, d.prec, N)) {
+  d.use_iface = 0;
+  d.rpos = nullptr;
+  d.ifl = nullptr;
+  d.ifr = nullptr;
+  if (!d.use3 && modes_cand) {
     const long long f = mixed ? 4 : 8;
     const long long segw = (long long)R * R + 1;
     std::vector<ModeTab> mt(m);
+    int *rpos = nullptr;
+    unsigned char *ifl = nullptr, *ifr = nullptr;
+    if (want_iface && (!A(s->alloc(&rpos, (long long)m * N)) || !A(s->alloc(&ifl, (long long)m * N * R * f)) ||
+                       !A(s->alloc(&ifr, (long long)m * N * (R + 1) * f))))
+      return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
     int wg0 = 0;
     long long out0 = 0;
     for (int k = 0; k < m; ++k) {
@@ -612,10 +642,16 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
         float *y3 = nullptr;
         if (!A(s->alloc(&ip, (long long)m * N)) || !(mixed ? A(s->alloc(&y3, N)) : A(s->alloc(&y6, N))))
           return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
-        hipError_t e = group_by_mode(m, N, k, nk, idx_dev, val_dev, ds->values_fp64, ip, y6, y3, s->stream);
+        hipError_t e = group_by_mode(m, N, k, nk, idx_dev, val_dev, ds->values_fp64, ip, y6, y3, s->stream,
+                                     want_iface ? perm_k : nullptr);
         if (e != hipSuccess) return cleanup(fail(PRGD_EDEVICE, std::string("grouping Omega: ") + hipGetErrorString(e)));
         t.idx = ip;
         t.y = mixed ? (const void *)y3 : (const void *)y6;
+      }
+      if (want_iface) {   // which sample of the grouping-mode copy sits at each position of this mode's copy
+        hipError_t e = compose_positions(N, k == sm ? perm0 : perm_k, perm0, inv_k, rpos + (long long)k * N, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // perm_k is reused by the next mode
+        if (e != hipSuccess) return cleanup(fail(PRGD_EDEVICE, std::string("position maps: ") + hipGetErrorString(e)));
       }
       long long nwg = mode_pass_wgs(N);
       t.chunk = (N + nwg - 1) / nwg;
@@ -666,7 +702,14 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     d.mt = dmt;
     d.mt_wg = wg0;
     d.mt_out = out0;
+    d.mt0_nwg = mt[0].nwg;
     d.use_modes = 1;
+    if (want_iface) {
+      d.use_iface = 1;
+      d.rpos = rpos;
+      d.ifl = ifl;
+      d.ifr = ifr;
+    }
   } else if (!d.use3) {
     long long tot = 0;
     int nbs = 1;
@@ -696,6 +739,11 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   if (idx_raw) {   // the unsorted copies are no longer needed (read_state synchronised)
     s->release(idx_raw);
     s->release(val_raw);
+  }
+  if (perm0) {     // nor the permutations behind the position maps
+    s->release(perm0);
+    s->release(perm_k);
+    s->release(inv_k);
   }
   *out = s;
   return PRGD_OK;

@@ -160,6 +160,15 @@ struct Dev {
   long long mt_out;            // outputs of all modes together (n_k (R*R + 1) each)
   const ModeTab *mt;           // device array [m]
   double *mp_rsq;              // [mt[0].nwg] partial ||R||^2
+  // stored interfaces for the mode passes: one pass over the grouping-mode
+  // copy writes, for every sample i of that copy and mode k, l_{k-1} into
+  // ifl[k][i] and (r_{k+1}, residual) into ifr[k][i]; mode k's pass finds the
+  // sample at its position p at i = rpos[k][p]
+  int use_iface;
+  int mt0_nwg;                 // workgroups of mode 0's pass (host copy of mt[0].nwg)
+  const int *rpos;             // [m][N]
+  void *ifl;                   // [m][N][R] in the working precision
+  void *ifr;                   // [m][N][R + 1] in the working precision
   S3 q3;
 };
 

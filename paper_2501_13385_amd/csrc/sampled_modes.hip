@@ -71,7 +71,81 @@ __device__ __forceinline__ auto pick_cores(L staged, G global) {
   else return global;
 }
 
-template <typename F, int R, int NT, bool STAGE>
+// Stored interfaces: one pass over the grouping-mode copy of Omega forms each
+// sample's prefix products l_k = T_1(x_1) ... T_k(x_k) (a left sweep, which also
+// gives T(x) and the residual) and suffix products r_k = T_k(x_k) ... T_m(x_m)
+// (a right sweep), and writes for every mode k l_{k-1} and (r_{k+1}, R_j) at
+// the sample's own position (coalesced).  Mode k's pass gathers them through
+// the position map instead of re-evaluating both chains (2m slice products
+// per sample instead of m (m - 1)).
+template <typename F, int R, bool STAGE>
+__global__ void __launch_bounds__(256) k_iface(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
+  const ModeTab &q0 = d.mt[0];
+  if ((int)blockIdx.x >= q0.nwg || (!diag && d.st->done)) return;
+  constexpr int RR = R * R;
+  const int m = d.m;
+  const long long N = d.N;
+  extern __shared__ unsigned char lds_raw[];
+  F *lcores = reinterpret_cast<F *>(lds_raw);
+  const auto gcores = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores));
+  if (STAGE)
+    for (long long i = threadIdx.x; i < d.coff[m]; i += blockDim.x) lcores[i] = gcores[i];
+  __syncthreads();
+  const auto cores = pick_cores<STAGE>((const F *)lcores, gcores);
+  const auto idx = glb(d.idx);
+  const auto y = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.y32 : (const void *)d.y64));
+  const auto ifl = glb((F *)d.ifl), ifr = glb((F *)d.ifr);
+  const long long j0 = (long long)blockIdx.x * q0.chunk, j1 = min(N, j0 + q0.chunk);
+  double rsq = 0.0;
+  for (long long j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    F v[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) v[a] = a == 0 ? (F)1 : (F)0;
+    for (int k = 0; k < m; ++k) {            // left sweep: record l_{k-1}, then v <- v T_k(x_k)
+      const long long rec = ((long long)k * N + j) * R;
+#pragma unroll
+      for (int a = 0; a < R; ++a) ifl[rec + a] = v[a];
+      const auto sl = cores + d.coff[k] + (long long)idx[(long long)k * N + j] * RR;
+      F nv[R];
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        F t = (F)0;
+#pragma unroll
+        for (int a = 0; a < R; ++a) t = fma(v[a], sl[a * R + b], t);
+        nv[b] = t;
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a) v[a] = nv[a];
+    }
+    const F res = v[0] - y[j];
+    rsq += (double)res * (double)res;
+#pragma unroll
+    for (int a = 0; a < R; ++a) v[a] = a == 0 ? (F)1 : (F)0;
+    for (int k = m - 1; k >= 0; --k) {       // right sweep: record r_{k+1} and R_j, then v <- T_k(x_k) v
+      const long long rec = ((long long)k * N + j) * (R + 1);
+#pragma unroll
+      for (int a = 0; a < R; ++a) ifr[rec + a] = v[a];
+      ifr[rec + R] = res;
+      const auto sl = cores + d.coff[k] + (long long)idx[(long long)k * N + j] * RR;
+      F nv[R];
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        F t = (F)0;
+#pragma unroll
+        for (int b = 0; b < R; ++b) t = fma(sl[a * R + b], v[b], t);
+        nv[a] = t;
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a) v[a] = nv[a];
+    }
+  }
+  __shared__ double sbuf[16];
+  const double bs = block_sum(rsq, sbuf);
+  if (threadIdx.x == 0) glb(d.mp_rsq)[blockIdx.x] = bs;
+}
+
+template <typename F, int R, int NT, bool STAGE, bool IFACE>
 __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int diag) {
   const Dev &d = dt[blockIdx.y];
   if ((int)blockIdx.x >= d.mt_wg || (!diag && d.st->done)) return;
@@ -140,7 +214,18 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
     const int xk = act ? idx[(long long)k * N + j] : -1;
     // interfaces of this sample
     F lv[R], rv[R];
-    if (k == 0) {
+    F rpre = (F)0;   // stored residual
+    if (IFACE) {
+      const long long i = act ? glb(d.rpos)[(long long)k * N + j] : 0;
+      const auto lrec = glb((const F *)d.ifl) + ((long long)k * N + i) * R;
+      const auto rrec = glb((const F *)d.ifr) + ((long long)k * N + i) * (R + 1);
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        lv[a] = act ? lrec[a] : (F)0;
+        rv[a] = act ? rrec[a] : (F)0;
+      }
+      rpre = act ? rrec[R] : (F)0;
+    } else if (k == 0) {
 #pragma unroll
       for (int a = 0; a < R; ++a) lv[a] = (a == 0) ? (F)1 : (F)0;
     } else {
@@ -163,7 +248,8 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
         for (int b = 0; b < R; ++b) lv[b] = nl[b];
       }
     }
-    if (k == m - 1) {
+    if (IFACE) {
+    } else if (k == m - 1) {
 #pragma unroll
       for (int a = 0; a < R; ++a) rv[a] = (a == 0) ? (F)1 : (F)0;
     } else {
@@ -186,7 +272,7 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
         for (int a = 0; a < R; ++a) rv[a] = nr[a];
       }
     }
-    const F yv = act ? y[j] : (F)0;
+    const F yv = (!IFACE && act) ? y[j] : (F)0;
     unsigned long long pending = __ballot(act);
     while (pending) {
       const int first = __ffsll((long long)pending) - 1;
@@ -200,15 +286,19 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
       const auto S = cores + cok + (long long)v * RR;
       F res = (F)0;
       if (me) {
-        F t = (F)0;
+        if (IFACE) {
+          res = rpre;
+        } else {
+          F t = (F)0;
 #pragma unroll
-        for (int a = 0; a < R; ++a) {
-          F u = (F)0;
+          for (int a = 0; a < R; ++a) {
+            F u = (F)0;
 #pragma unroll
-          for (int b = 0; b < R; ++b) u = fma(S[a * R + b], rv[b], u);
-          t = fma(lv[a], u, t);
+            for (int b = 0; b < R; ++b) u = fma(S[a * R + b], rv[b], u);
+            t = fma(lv[a], u, t);
+          }
+          res = t - yv;
         }
-        res = t - yv;
         const F r2 = res * res;
         rsq += (double)r2;
         ws2 += r2;
@@ -238,7 +328,7 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
   const double bs = block_sum(rsq, sbuf);   // ends with a barrier: the table is complete
   auto ps = glb((F *)q.part_seg) + (long long)wg * KSEG * SEGW;
   for (int i = threadIdx.x; i < KSEG * SEGW; i += NT) ps[i] = lseg[i];
-  if (k == 0 && threadIdx.x == 0) glb(d.mp_rsq)[wg] = bs;
+  if (!IFACE && k == 0 && threadIdx.x == 0) glb(d.mp_rsq)[wg] = bs;   // else written by k_iface
 }
 
 // Sum the segment tables of every mode in a fixed order into the padded
@@ -279,12 +369,27 @@ static hipError_t launch_modes_t(const Batch &bt, int diag, hipStream_t st, hipE
     go = std::max<long long>(go, bt.host[i].mt_out);
   }
   size_t lds = modes_lds_bytes(R, bt.host[0].prec, NT), core_bytes = 0;
-  for (int i = 0; i < bt.ns; ++i)
+  int g0 = 1;
+  for (int i = 0; i < bt.ns; ++i) {
     core_bytes = std::max(core_bytes, (size_t)bt.host[i].coff[bt.host[i].m] * sizeof(F));
-  if (core_bytes <= MODES_STAGE_MAX)
-    hipLaunchKernelGGL((k_modes<F, R, NT, true>), dim3(g, bt.ns), dim3(NT), lds + core_bytes, st, bt.dt, diag);
-  else
-    hipLaunchKernelGGL((k_modes<F, R, NT, false>), dim3(g, bt.ns), dim3(NT), lds, st, bt.dt, diag);
+    g0 = std::max(g0, bt.host[i].mt0_nwg);
+  }
+  const bool stage = core_bytes <= MODES_STAGE_MAX;
+  if (bt.host[0].use_iface) {   // the whole batch shares the variant
+    if (stage) {
+      hipLaunchKernelGGL((k_iface<F, R, true>), dim3(g0, bt.ns), dim3(256), core_bytes, st, bt.dt, diag);
+      if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+      hipLaunchKernelGGL((k_modes<F, R, NT, true, true>), dim3(g, bt.ns), dim3(NT), lds + core_bytes, st, bt.dt, diag);
+    } else {
+      hipLaunchKernelGGL((k_iface<F, R, false>), dim3(g0, bt.ns), dim3(256), 0, st, bt.dt, diag);
+      if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+      hipLaunchKernelGGL((k_modes<F, R, NT, false, true>), dim3(g, bt.ns), dim3(NT), lds, st, bt.dt, diag);
+    }
+  } else if (stage) {
+    hipLaunchKernelGGL((k_modes<F, R, NT, true, false>), dim3(g, bt.ns), dim3(NT), lds + core_bytes, st, bt.dt, diag);
+  } else {
+    hipLaunchKernelGGL((k_modes<F, R, NT, false, false>), dim3(g, bt.ns), dim3(NT), lds, st, bt.dt, diag);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (after_main && (e = hipEventRecord(after_main, st)) != hipSuccess) return e;

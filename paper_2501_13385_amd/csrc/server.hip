@@ -231,7 +231,7 @@ void prgd_server_s::admit() {
       q->vals.shrink_to_fit();
     }
     const Dev &d = s->d;
-    const int variant = d.use3 ? 1 : (d.use_modes ? 2 : 0);    // sampled-pass kernel family
+    const int variant = d.use3 ? 1 : (d.use_modes ? (d.use_iface ? 3 : 2) : 0);    // sampled-pass kernel family
     const GroupKey key{d.m, d.R, d.prec, variant, d.use3 ? d.q3.stage : 0};
     auto it = groups.find(key);
     if (it == groups.end()) {

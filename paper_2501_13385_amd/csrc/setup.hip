@@ -70,7 +70,7 @@ hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream
 // idx_in: [m][N] device, values_in: [N] device (float or double).
 // Outputs idx_out [m][N], y64/y32 (whichever is non-null) in sorted order.
 hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *idx_in, const void *values_in,
-                         int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s) {
+                         int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s, int *perm) {
   hipError_t e;
   int *keys_out = nullptr, *perm_in = nullptr, *perm_out = nullptr;
   void *temp = nullptr;
@@ -109,8 +109,27 @@ hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *id
     if (y32) hipLaunchKernelGGL((k_gather_val<float, float>), dim3(grid_for(N)), dim3(256), 0, s, N,
                                 (const float *)values_in, perm_out, y32);
   }
+  if (perm && (e = hipMemcpyAsync(perm, perm_out, N * sizeof(int), hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
   if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipStreamSynchronize(s);
+}
+
+__global__ void k_invert_perm(long long N, const int *__restrict__ perm, int *__restrict__ pos) {
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (long long)gridDim.x * blockDim.x)
+    pos[perm[p]] = (int)p;
+}
+
+__global__ void k_compose_pos(long long N, const int *__restrict__ perm0, const int *__restrict__ pos,
+                              int *__restrict__ out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x)
+    out[i] = pos[perm0[i]];
+}
+
+hipError_t compose_positions(long long N, const int *perm_a, const int *perm_b, int *scratch, int *out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_invert_perm, dim3(grid_for(N)), dim3(256), 0, s, N, perm_b, scratch);
+  hipLaunchKernelGGL(k_compose_pos, dim3(grid_for(N)), dim3(256), 0, s, N, perm_a, scratch, out);
+  return hipGetLastError();
 }
 
 // copy each batch member's State to out[i] (thread i)

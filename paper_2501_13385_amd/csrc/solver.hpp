@@ -21,8 +21,16 @@ hipError_t launch_project(const Batch &bt, hipStream_t s);
 hipError_t launch_retract(const Batch &bt, hipStream_t s);
 hipError_t launch_output(const Batch &bt, hipStream_t s, int init);
 hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode);
+// Stable grouping of Omega by one mode; perm (if not null) receives, for each
+// grouped position, the position of that sample in the input.
 hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *idx_in, const void *values_in,
-                         int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s);
+                         int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s,
+                         int *perm = nullptr);
+// pos[perm_b[p]] = p for p < N (inverse permutation of perm_b), then
+// out[i] = pos[perm_a[i]]: for the sample at position i under perm_a, its
+// position under perm_b
+hipError_t compose_positions(long long N, const int *perm_a, const int *perm_b, int *scratch, int *out,
+                             hipStream_t s);
 hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t s);
 hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream_t s);

@@ -133,3 +133,12 @@ def test_spectral_init_rejects_bad_arguments_before_device_work():
     with pytest.raises(L.PrgdError) as e:
         L.prgd_spectral_init(shape, ranks, idx, np.array([1.0, np.nan]), g, 5)
     assert e.value.status == L.EINVAL
+
+
+def test_create_rejects_a_bad_mode_interfaces_option():
+    shape, ranks = [4, 5, 6, 3], [1, 2, 2, 2, 1]
+    idx = np.array([[0, 1], [2, 3], [4, 5], [1, 2]], dtype=np.int32)
+    init = [np.ones((ranks[k], shape[k], ranks[k + 1])) for k in range(4)]
+    with pytest.raises(L.PrgdError) as e:
+        L.Solver(shape, ranks, idx, np.ones(2), init, mode_interfaces=2)
+    assert e.value.status == L.EINVAL

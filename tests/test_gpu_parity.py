@@ -256,3 +256,56 @@ def test_other_policies_match_reference_each_iteration(L, name, metric, rule, c,
         s.close()
     for h, a in zip(hist, alphas):
         assert abs(h["alpha"] - a) <= 1e-9 * abs(a), (h, a)
+
+
+@pytest.mark.parametrize("mi", [-1, 1])
+@pytest.mark.parametrize("name", ["c1", "ragged", "order6"])
+def test_mode_pass_forms_match_reference(L, name, mi):
+    """Orders above 3 run the sampled pass mode by mode; both forms (interfaces
+    re-evaluated in every mode's pass, or formed once and stored) match the
+    reference: the sampled pass to 1e-12 and five iterates to 1e-10."""
+    pb = make_case(name)
+    say("case", name, "mode_interfaces", mi)
+    y = observed(pb)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, stop_rule="none", max_iter=0, mode_interfaces=mi)
+    try:
+        cores = s.cores()
+        grads, ssq, rsq = s.sampled_pass()
+    finally:
+        s.close()
+    r = prgd.residual(cores, pb.indices, y)
+    ref_g = prgd.core_gradient(cores, pb.indices, r)
+    ref_s = prgd.slice_norms(pb.indices, r, pb.shape)
+    assert abs(rsq - float(r @ r)) <= 1e-12 * float(r @ r)
+    for k in range(pb.order):
+        assert np.abs(grads[k] - ref_g[k]).max() <= 1e-12 * np.abs(ref_g[k]).max(), k
+        np.testing.assert_allclose(ssq[k], ref_s[k], rtol=1e-12, atol=1e-14 * ref_s[k].max())
+    pol = prgd.Policy(step_rule="theory", c=0.8)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, step=0.8, stop_rule="none", max_iter=5, mode_interfaces=mi)
+    ref = [x.copy() for x in pb.init]
+    try:
+        for it in range(5):
+            s.iterate(1)
+            got = s.cores()
+            ref, _ = prgd.prgd_step(ref, pb.indices, y, pol, pb.ranks)
+            assert rel_dist(got, ref) <= 1e-10, (it, rel_dist(got, ref))
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("mi", [-1, 1])
+def test_mode_pass_forms_mixed(L, mi):
+    pb = make_case("c1")
+    y = observed(pb)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, precision="mixed", stop_rule="none", max_iter=0,
+                 mode_interfaces=mi)
+    try:
+        cores = s.cores()
+        grads, ssq, rsq = s.sampled_pass()
+    finally:
+        s.close()
+    r = prgd.residual(cores, pb.indices, y)
+    ref_g = prgd.core_gradient(cores, pb.indices, r)
+    assert abs(rsq - float(r @ r)) <= 1e-4 * float(r @ r)
+    for k in range(pb.order):
+        assert np.linalg.norm(grads[k] - ref_g[k]) <= 1e-4 * np.linalg.norm(ref_g[k]), k
