@@ -60,3 +60,39 @@ def test_full_size_mixed_sampled_pass(L, name):
     assert abs(rsq - float(r @ r)) <= 1e-4 * float(r @ r)
     for k in range(pb.order):
         assert np.linalg.norm(grads[k] - ref_g[k]) <= 1e-4 * np.linalg.norm(ref_g[k]), k
+
+
+def test_largest_size_sampled_pass_on_sampled_slices(L):
+    """2^25 observations of a 2048 x 64 x 2048 tensor at rank 8: the boundary
+    accumulators are too large for the grouped order-3 kernel, so this runs
+    the mode passes (without stored interfaces: they would exceed 8 GiB).
+    ||R||^2 is checked in full; gradient slices and slice sums one slice at a
+    time (the reference on that slice's samples only), three slices per mode."""
+    import time
+    rng = wl.make_rng(31)
+    shape, ranks = [2048, 64, 2048], [1, 8, 8, 1]
+    n_obs = 1 << 25
+    t0 = time.time()
+    truth = wl.gaussian_cores(shape, ranks, rng)
+    init = wl.perturb_cores(truth, 0.1, rng)
+    idx = wl.sample_indices(shape, n_obs, rng)
+    y = L.prgd_eval(shape, ranks, truth, idx)
+    print(f"largest case: shape {shape} ranks {ranks} N {n_obs}, inputs in {time.time() - t0:.1f} s", flush=True)
+    s = L.Solver(shape, ranks, idx, y, init, stop_rule="none", max_iter=0)
+    try:
+        cores = s.cores()
+        grads, ssq, rsq = s.sampled_pass()
+    finally:
+        s.close()
+    print(f"device pass done at {time.time() - t0:.1f} s", flush=True)
+    r = prgd.residual(cores, idx, y)
+    assert abs(rsq - float(r @ r)) <= 1e-12 * float(r @ r)
+    for k in range(3):
+        for x in rng.choice(shape[k], size=3, replace=False):
+            sel = np.nonzero(idx[k] == x)[0]
+            ref_g = prgd.core_gradient(cores, idx[:, sel], r[sel])[k][:, x, :]
+            scale = max(np.abs(ref_g).max(), 1e-300)
+            assert np.abs(grads[k][:, x, :] - ref_g).max() <= 1e-12 * scale, (k, x)
+            ref_s = float(r[sel] @ r[sel])
+            assert abs(ssq[k][x] - ref_s) <= 1e-12 * ref_s, (k, x)
+    print(f"checked at {time.time() - t0:.1f} s", flush=True)
