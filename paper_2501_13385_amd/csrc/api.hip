@@ -181,31 +181,55 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
     const double v = ds->values_fp64 ? ((const double *)vals)[j] : (double)((const float *)vals)[j];
     if (!std::isfinite(v)) return fail(PRGD_EINVAL, "non-finite observed value at sample " + std::to_string(j));
   }
-  // distinct multi-indices
+  // distinct multi-indices: a 64-bit key per sample (the linear index when
+  // it fits, else that index modulo 2^64, verified on equal keys), keys
+  // sorted by an LSD radix sort with 11-bit digits (2048 buckets stay in cache)
   double dstar = 1;
   for (int k = 0; k < m; ++k) dstar *= n[k];
-  bool dup = false;
-  if (dstar < 9.0e18) {
-    std::vector<uint64_t> key(N);
-    for (long long j = 0; j < N; ++j) {
-      uint64_t v = 0;
-      for (int k = 0; k < m; ++k) v = v * (uint64_t)n[k] + (uint64_t)idx[(long long)k * N + j];
-      key[j] = v;
-    }
-    std::sort(key.begin(), key.end());
-    for (long long j = 1; j < N && !dup; ++j) dup = key[j] == key[j - 1];
-  } else {
-    std::vector<int> ord(N);
-    std::iota(ord.begin(), ord.end(), 0);
-    auto less = [&](int a, int b) {
-      for (int k = 0; k < m; ++k) {
-        const int va = idx[(long long)k * N + a], vb = idx[(long long)k * N + b];
-        if (va != vb) return va < vb;
+  const bool exact = dstar < 9.0e18;
+  std::vector<uint64_t> key(N), key2(N);
+  std::vector<int> ord(N), ord2(N);
+  for (long long j = 0; j < N; ++j) {
+    uint64_t v = 0;
+    for (int k = 0; k < m; ++k) v = v * (uint64_t)n[k] + (uint64_t)idx[(long long)k * N + j];
+    key[j] = v;
+    ord[j] = (int)j;
+  }
+  {
+    constexpr int BITS = 11, B = 1 << BITS;
+    std::vector<long long> cnt(B + 1);
+    for (int sh = 0; sh < 64; sh += BITS) {
+      std::fill(cnt.begin(), cnt.end(), 0);
+      for (long long j = 0; j < N; ++j) ++cnt[((key[j] >> sh) & (B - 1)) + 1];
+      if (cnt[((key[0] >> sh) & (B - 1)) + 1] == N) continue;   // one digit value: nothing moves
+      for (int d = 0; d < B; ++d) cnt[d + 1] += cnt[d];
+      for (long long j = 0; j < N; ++j) {
+        const long long p = cnt[(key[j] >> sh) & (B - 1)]++;
+        key2[p] = key[j];
+        ord2[p] = ord[j];
       }
-      return false;
-    };
-    std::sort(ord.begin(), ord.end(), less);
-    for (long long j = 1; j < N && !dup; ++j) dup = !less(ord[j - 1], ord[j]) && !less(ord[j], ord[j - 1]);
+      key.swap(key2);
+      ord.swap(ord2);
+    }
+  }
+  auto same = [&](int a, int b) {
+    for (int k = 0; k < m; ++k)
+      if (idx[(long long)k * N + a] != idx[(long long)k * N + b]) return false;
+    return true;
+  };
+  bool dup = false;
+  for (long long j = 1; j < N && !dup; ++j) {
+    if (key[j] != key[j - 1]) continue;
+    if (exact) {
+      dup = true;
+      break;
+    }
+    // equal keys of distinct multi-indices are possible here: compare the run
+    long long e = j;
+    while (e + 1 < N && key[e + 1] == key[j - 1]) ++e;
+    for (long long a2 = j - 1; a2 <= e && !dup; ++a2)
+      for (long long b2 = a2 + 1; b2 <= e && !dup; ++b2) dup = same(ord[a2], ord[b2]);
+    j = e;
   }
   if (dup) return fail(PRGD_EDUPLICATE, "Omega contains a repeated multi-index");
   return PRGD_OK;

@@ -142,3 +142,21 @@ def test_create_rejects_a_bad_mode_interfaces_option():
     with pytest.raises(L.PrgdError) as e:
         L.Solver(shape, ranks, idx, np.ones(2), init, mode_interfaces=2)
     assert e.value.status == L.EINVAL
+
+
+def test_duplicate_check_beyond_64_bit_linear_indices():
+    """Five modes of 2^16: linear indices need 80 bits, so the 64-bit keys of
+    (0,0,0,0,0) and (1,0,0,0,0) collide; distinct multi-indices with equal keys
+    must pass the duplicate check and a true repeat must not."""
+    shape, ranks = [1 << 16] * 5, [1, 1, 1, 1, 1, 1]
+    init = [np.ones((1, 1 << 16, 1)) for _ in range(5)]
+    colliding = np.array([[0, 1, 0], [0, 0, 1], [0, 0, 0], [0, 0, 0], [0, 0, 0]], dtype=np.int32)
+    try:
+        h = L.prgd_create(shape, ranks, colliding, np.ones(3), init)
+        L.prgd_destroy(h)
+    except L.PrgdError as e:       # no device here: later steps may fail, but not as duplicates
+        assert e.status != L.EDUPLICATE
+    repeated = np.array([[0, 1, 1], [0, 0, 0], [0, 0, 0], [0, 0, 0], [0, 0, 0]], dtype=np.int32)
+    with pytest.raises(L.PrgdError) as ei:
+        L.prgd_create(shape, ranks, repeated, np.ones(3), init)
+    assert ei.value.status == L.EDUPLICATE
