@@ -9,6 +9,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/prgd.h"
@@ -135,6 +136,79 @@ bool use_stored_interfaces(int option, int m, int R, int prec, long long N) {
   return N >= 65536 && (long long)m * N * ((2LL * R + 1) * f + 4) <= (8LL << 30);
 }
 
+// true if two samples of Omega (SoA idx, m x N) share their multi-index
+bool has_repeated_multi_index(int m, const int32_t *n, long long N, const int32_t *idx, bool exact) {
+  constexpr int NB = 256;
+  const int nth = (int)std::max<long long>(1, std::min<long long>(8, N / 65536));
+  std::vector<uint64_t> key(N);
+  auto bucket = [](uint64_t v) { return (int)((v * 0x9E3779B97F4A7C15ull) >> 56); };
+  std::vector<std::vector<long long>> cnt(nth, std::vector<long long>(NB, 0));
+  auto chunk = [&](int t, long long &lo, long long &hi) {
+    lo = N * t / nth;
+    hi = N * (t + 1) / nth;
+  };
+  auto run = [&](auto fn) {
+    std::vector<std::thread> th;
+    for (int t = 1; t < nth; ++t) th.emplace_back(fn, t);
+    fn(0);
+    for (auto &x : th) x.join();
+  };
+  run([&](int t) {
+    long long lo, hi;
+    chunk(t, lo, hi);
+    for (long long j = lo; j < hi; ++j) {
+      uint64_t v = 0;
+      for (int k = 0; k < m; ++k) v = v * (uint64_t)n[k] + (uint64_t)idx[(long long)k * N + j];
+      key[j] = v;
+      ++cnt[t][bucket(v)];
+    }
+  });
+  std::vector<long long> start(NB + 1, 0);
+  std::vector<std::vector<long long>> off(nth, std::vector<long long>(NB, 0));
+  for (int b = 0; b < NB; ++b) {
+    long long p = start[b];
+    for (int t = 0; t < nth; ++t) {
+      off[t][b] = p;
+      p += cnt[t][b];
+    }
+    start[b + 1] = p;
+  }
+  std::vector<std::pair<uint64_t, int>> item(N);
+  run([&](int t) {
+    long long lo, hi;
+    chunk(t, lo, hi);
+    for (long long j = lo; j < hi; ++j) item[off[t][bucket(key[j])]++] = {key[j], (int)j};
+  });
+  auto same = [&](int a, int b) {
+    for (int k = 0; k < m; ++k)
+      if (idx[(long long)k * N + a] != idx[(long long)k * N + b]) return false;
+    return true;
+  };
+  std::vector<char> found(nth, 0);
+  run([&](int t) {
+    for (int b = t; b < NB && !found[t]; b += nth) {
+      auto first = item.begin() + start[b], last = item.begin() + start[b + 1];
+      std::sort(first, last);
+      for (auto it = first + (first != last ? 1 : 0); it < last && !found[t]; ++it) {
+        if (it->first != (it - 1)->first) continue;
+        if (exact) {
+          found[t] = 1;
+          break;
+        }
+        // equal keys of distinct multi-indices are possible: compare the run
+        auto e = it;
+        while (e + 1 < last && (e + 1)->first == it->first) ++e;
+        for (auto a = it - 1; a <= e && !found[t]; ++a)
+          for (auto c = a + 1; c <= e && !found[t]; ++c) found[t] = same(a->second, c->second);
+        it = e;
+      }
+    }
+  });
+  for (int t = 0; t < nth; ++t)
+    if (found[t]) return true;
+  return false;
+}
+
 prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *vals, int64_t &numel) {
   const int m = ds->order;
   if (m < 2 || m > MAXM) return fail(m < 2 ? PRGD_EINVAL : PRGD_ENOTSUP, "order must be in [2, 32]");
@@ -181,56 +255,14 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
     const double v = ds->values_fp64 ? ((const double *)vals)[j] : (double)((const float *)vals)[j];
     if (!std::isfinite(v)) return fail(PRGD_EINVAL, "non-finite observed value at sample " + std::to_string(j));
   }
-  // distinct multi-indices: a 64-bit key per sample (the linear index when
-  // it fits, else that index modulo 2^64, verified on equal keys), keys
-  // sorted by an LSD radix sort with 11-bit digits (2048 buckets stay in cache)
+  // distinct multi-indices: a 64-bit key per sample (the linear index when it
+  // fits, else that index modulo 2^64, verified on equal keys), spread over
+  // 256 buckets by a multiplicative hash, each bucket sorted and scanned;
+  // keys, bucketing and the per-bucket work run on up to 8 threads
   double dstar = 1;
   for (int k = 0; k < m; ++k) dstar *= n[k];
   const bool exact = dstar < 9.0e18;
-  std::vector<uint64_t> key(N), key2(N);
-  std::vector<int> ord(N), ord2(N);
-  for (long long j = 0; j < N; ++j) {
-    uint64_t v = 0;
-    for (int k = 0; k < m; ++k) v = v * (uint64_t)n[k] + (uint64_t)idx[(long long)k * N + j];
-    key[j] = v;
-    ord[j] = (int)j;
-  }
-  {
-    constexpr int BITS = 11, B = 1 << BITS;
-    std::vector<long long> cnt(B + 1);
-    for (int sh = 0; sh < 64; sh += BITS) {
-      std::fill(cnt.begin(), cnt.end(), 0);
-      for (long long j = 0; j < N; ++j) ++cnt[((key[j] >> sh) & (B - 1)) + 1];
-      if (cnt[((key[0] >> sh) & (B - 1)) + 1] == N) continue;   // one digit value: nothing moves
-      for (int d = 0; d < B; ++d) cnt[d + 1] += cnt[d];
-      for (long long j = 0; j < N; ++j) {
-        const long long p = cnt[(key[j] >> sh) & (B - 1)]++;
-        key2[p] = key[j];
-        ord2[p] = ord[j];
-      }
-      key.swap(key2);
-      ord.swap(ord2);
-    }
-  }
-  auto same = [&](int a, int b) {
-    for (int k = 0; k < m; ++k)
-      if (idx[(long long)k * N + a] != idx[(long long)k * N + b]) return false;
-    return true;
-  };
-  bool dup = false;
-  for (long long j = 1; j < N && !dup; ++j) {
-    if (key[j] != key[j - 1]) continue;
-    if (exact) {
-      dup = true;
-      break;
-    }
-    // equal keys of distinct multi-indices are possible here: compare the run
-    long long e = j;
-    while (e + 1 < N && key[e + 1] == key[j - 1]) ++e;
-    for (long long a2 = j - 1; a2 <= e && !dup; ++a2)
-      for (long long b2 = a2 + 1; b2 <= e && !dup; ++b2) dup = same(ord[a2], ord[b2]);
-    j = e;
-  }
+  const bool dup = has_repeated_multi_index(m, n, N, idx, exact);
   if (dup) return fail(PRGD_EDUPLICATE, "Omega contains a repeated multi-index");
   return PRGD_OK;
 }
