@@ -114,9 +114,10 @@ typedef struct {
   int32_t mode_interfaces;     /* orders whose sampled pass runs mode by mode: 1 = one
                                   pass forms every sample's left and right interfaces and
                                   residual and the mode passes read them, -1 = every mode
-                                  pass re-evaluates them, 0 = choose (1 when |Omega| >=
-                                  65536 and the stored interfaces take at most 8 GiB).
-                                  Results agree to rounding either way.                     */
+                                  pass re-evaluates them, 0 = choose (1 for orders >= 6
+                                  and ranks <= 8 with |Omega| >= 65536 when the stored
+                                  interfaces take at most 8 GiB).  Results agree to
+                                  rounding either way.                                      */
 } prgd_desc;
 
 /* One row of the per-iteration record kept on the device. */

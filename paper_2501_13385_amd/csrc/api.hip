@@ -128,12 +128,14 @@ bool use_mode_passes(int m, const int *n, int R, int prec, long long N) {
 long long mode_pass_wgs(long long N) { return std::min<long long>(1024, std::max<long long>(1, (N + 2047) / 2048)); }
 
 // whether the mode passes read stored interfaces (option: 1 yes, -1 no, 0 when
-// Omega is large enough for the saved chain work to outweigh one more launch,
-// N >= 65536, and the records and position maps take at most 8 GiB)
+// the order is at least 6 and the padded rank at most 8, so that 2m slice
+// products instead of m (m - 1) outweigh writing and gathering the records,
+// Omega is large enough to amortise one more launch, N >= 65536, and the
+// records and position maps take at most 8 GiB)
 bool use_stored_interfaces(int option, int m, int R, int prec, long long N) {
   if (option != 0) return option > 0;
   const long long f = prec == PREC_MIXED ? 4 : 8;
-  return N >= 65536 && (long long)m * N * ((2LL * R + 1) * f + 4) <= (8LL << 30);
+  return m >= 6 && R <= 8 && N >= 65536 && (long long)m * N * ((2LL * R + 1) * f + 4) <= (8LL << 30);
 }
 
 // true if two samples of Omega (SoA idx, m x N) share their multi-index
