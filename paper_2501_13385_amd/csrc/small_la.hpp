@@ -130,40 +130,40 @@ __device__ inline int block_pivoted_cholesky(const double *A, int n, double *F) 
   return rank_s;
 }
 
-// pair P of round rd in the round-robin ordering of m1 + 1 indices (m1 odd):
-// pair 0 is (m1, rd), pair P > 0 is (rd + P, rd - P) mod m1; returned p < q
-__device__ __forceinline__ void round_robin_pair(int rd, int P, int m1, int &p, int &q) {
-  if (P == 0) {
-    p = rd;
-    q = m1;
-    return;
-  }
-  int a = rd + P, b = rd - P + m1;
-  if (a >= m1) a -= m1;
-  if (b >= m1) b -= m1;
-  p = a < b ? a : b;
-  q = a < b ? b : a;
+// Slot of the round-robin ordering that the element in slot s moves to after
+// a round (np pairs, pair P = slots (2P, 2P+1)).  Slots 2k form the top row
+// and 2k+1 the bottom row of the usual tournament table; slot 0 stays, the
+// other elements move one place around the table (top row to the right,
+// bottom row to the left).  Every two of the 2 np elements share a pair in
+// exactly one of 2 np - 1 consecutive rounds, after which all are back in
+// their starting slots.
+__device__ __forceinline__ int tournament_next(int s, int np) {
+  if (np == 1 || s == 0) return s;
+  const int k = s >> 1;
+  if ((s & 1) == 0) return k == np - 1 ? s + 1 : s + 2;
+  return k == 0 ? 2 : s - 2;
 }
 
 // Rotation (c, s) that zeroes the (p, q) entry of a symmetric matrix under
 // J^T A J, J = [[c, s], [-s, c]] on rows/columns (p, q): t = tan(theta) is the
-// smaller root of t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) / (2 a_pq).  The
-// angle only has to be accurate enough for fast convergence (an angle off by a
-// relative d leaves about d a_pq, removed in a later sweep), so t comes from
-// the hardware estimates of 1/x and 1/sqrt(x) as they are; c = 1/sqrt(1+t^2) is
-// refined to full precision so that c^2 + s^2 = 1 and the accumulated
-// eigenvectors stay orthonormal.  Entries below 2^-1000 are treated as zero.
+// root of smaller magnitude of t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) /
+// (2 a_pq), written as t = sign(d) 2 a_pq / (|d| + sqrt(d^2 + 4 a_pq^2)) with
+// d = a_qq - a_pp.  The angle only has to be accurate enough for fast
+// convergence (an angle off by a relative delta leaves about delta a_pq for a
+// later sweep), so t comes from the hardware estimates of 1/x and 1/sqrt(x) as
+// they are; c = 1/sqrt(1+t^2) is refined to full precision so that
+// c^2 + s^2 = 1 to rounding and the accumulated eigenvectors stay orthonormal.
+// Entries |a_pq| <= 1e-150 are treated as zero, and so are pairs whose
+// diagonal difference reaches 1e150 (the squares stay in range).
 __device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double &c, double &s) {
-  const bool rot = fabs(apq) > 0x1p-1000;
-  const double tau = (aqq - app) * (0.5 * __builtin_amdgcn_rcp(rot ? apq : 1.0));
-  const double at = fabs(tau);
-  const bool big = !(at < 1e150);
-  const double x = fma(big ? 1.0 : at, big ? 1.0 : at, 1.0);
-  const double tt0 = __builtin_amdgcn_rcp(big ? 2.0 * at : at + x * __builtin_amdgcn_rsq(x));
-  const double tt = tau >= 0.0 ? tt0 : -tt0;
-  const double cr = rsq_newton<2>(fma(tt, tt, 1.0));
+  const double d = aqq - app, ad = fabs(d), e2 = apq + apq;
+  const bool rot = fabs(apq) > 1e-150 && ad < 1e150;
+  const double r2 = fma(d, d, e2 * e2);
+  const double t0 = e2 * __builtin_amdgcn_rcp(fma(r2, __builtin_amdgcn_rsq(r2), ad));
+  const double t = d < 0.0 ? -t0 : t0;
+  const double cr = rsq_newton<2>(fma(t, t, 1.0));
   c = rot ? cr : 1.0;
-  s = rot ? tt * cr : 0.0;
+  s = rot ? t * cr : 0.0;
 }
 
 // one DPP exchange of a double (both halves moved with the same pattern)
@@ -205,28 +205,31 @@ __device__ inline void block_sum2(double &a, double &b, double *sb) {
 }
 
 // Cyclic Jacobi for a symmetric n x n matrix A (ld n, n <= 32), for a block of
-// at least 256 threads.  The matrix and V are held padded to ne = n + (n & 1)
-// (a zero row and column, on which every rotation is exactly the identity),
-// so that no index needs a bound check.  Round-robin ordering: each round
-// applies ne/2 disjoint rotations.  Thread (P, Q), P, Q < ne/2, owns the 2 x 2
-// block (P, Q) of A and the 2 x 2 block of V with rows in pair P and columns
-// in pair Q; it computes the two rotations it needs itself from the previous
-// state and writes the next state of A into the other buffer, so a round
-// costs one barrier and at most four waves work (one per SIMD).  The
-// off-diagonal mass for the stopping rule is summed from the entries written
-// in a sweep's last round.
-// Sweeps stop once the off-diagonal Frobenius norm is at most 1e-15 of the
-// whole (a converged sweep leaves rounding residue near 3e-16 of it, so a
+// at least 256 threads.  The matrix and the eigenvector matrix are held padded
+// to ne = n + (n & 1) (a zero row and column, on which every rotation is
+// exactly the identity) with ld ne.  Pairs sit in fixed slots (2P, 2P+1), and
+// the round-robin ordering moves the data instead: each round writes the
+// rotated matrix into the other buffer with rows and columns already moved to
+// their next slots (and V's columns likewise), so every thread reads and
+// writes the same addresses in every round and no index is computed inside
+// the loop; after a sweep of ne - 1 rounds all slots are back in place.
+// Thread (P, Q), P, Q < ne/2, owns the 2 x 2 block (P, Q) of A and the 2 x 2
+// block of V with rows 2P, 2P+1 and columns in pair Q; it computes the two
+// rotations it needs itself from the previous state, so a round costs one
+// barrier and at most four waves work (one per SIMD).  The off-diagonal mass
+// for the stopping rule is summed from the entries written in a sweep's last
+// round.  Sweeps stop once the off-diagonal Frobenius norm is at most 1e-15 of
+// the whole (a converged sweep leaves rounding residue near 3e-16 of it, so a
 // tighter bound would never be met), or once a sweep fails to shrink it (exact
 // rotations always do, so only rounding is left).  On exit w[0..n) holds the
 // eigenvalues in descending order and V (ld n) the eigenvectors as columns.
-// A is read first and its area (1024 doubles) then reused as scratch; W1, W2:
+// A is read first and its area (1024 doubles) then reused, as is V's; W1, W2:
 // scratch, 1024 doubles each.
 __device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, double *W1, double *W2) {
   __shared__ double sb[32];
   const int t = threadIdx.x, nt = blockDim.x;
   const int ne = n + (n & 1), np = ne / 2, m1 = ne - 1;
-  double *cur = W1, *nxt = W2, *Vp = A;
+  double *cur = W1, *nxt = W2, *vc = A;
   double off = 0.0, dia = 0.0;
   for (int e = t; e < ne * ne; e += nt) {
     const int i = e / ne, j = e - i * ne;
@@ -236,63 +239,81 @@ __device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, 
     else off += v * v;
   }
   block_sum2(off, dia, sb);  // ends with a barrier: A has been read
-  for (int e = t; e < ne * ne; e += nt) Vp[e] = (e / ne == e % ne) ? 1.0 : 0.0;
+  for (int e = t; e < ne * ne; e += nt) vc[e] = (e / ne == e % ne) ? 1.0 : 0.0;
   const bool act = t < np * np;
   const int P = act ? t / np : 0, Q = act ? t - P * np : 0;
+  // this thread's fixed addresses: the reads at rows/columns 2P, 2P+1 and
+  // 2Q, 2Q+1, the writes at the slots those rows and columns move to
+  const int r1 = 2 * P * ne, r2 = r1 + ne, c1 = 2 * Q, c2 = c1 + 1;
+  const int p1 = 2 * P * (ne + 1), q1 = 2 * Q * (ne + 1);
+  const int nr1 = tournament_next(2 * P, np) * ne, nr2 = tournament_next(2 * P + 1, np) * ne;
+  const int nc1 = tournament_next(c1, np), nc2 = tournament_next(c2, np);
   __syncthreads();
+  // one round from buffers (src, vsrc) into (dst, vdst); instantiated once per
+  // direction so that every address is a fixed offset from a fixed buffer
+  auto one_round = [&](const double *src, double *dst, const double *vsrc, double *vdst, bool last) {
+    if (act) {
+      const double p11 = src[p1], p12 = src[p1 + 1], p22 = src[p1 + ne + 1];
+      const double q11 = src[q1], q12 = src[q1 + 1], q22 = src[q1 + ne + 1];
+      const double a11 = src[r1 + c1], a12 = src[r1 + c2];
+      const double a21 = src[r2 + c1], a22 = src[r2 + c2];
+      const double v11 = vsrc[r1 + c1], v12 = vsrc[r1 + c2];
+      const double v21 = vsrc[r2 + c1], v22 = vsrc[r2 + c2];
+      double cP, sP, cQ, sQ;
+      jacobi_rotation(p11, p22, p12, cP, sP);
+      jacobi_rotation(q11, q22, q12, cQ, sQ);
+      // M = A J_Q, then J_P^T M
+      const double m11 = cQ * a11 - sQ * a12, m12 = sQ * a11 + cQ * a12;
+      const double m21 = cQ * a21 - sQ * a22, m22 = sQ * a21 + cQ * a22;
+      const double b11 = cP * m11 - sP * m21, b12 = cP * m12 - sP * m22;
+      const double b21 = sP * m11 + cP * m21, b22 = sP * m12 + cP * m22;
+      dst[nr1 + nc1] = b11;
+      dst[nr1 + nc2] = b12;
+      dst[nr2 + nc1] = b21;
+      dst[nr2 + nc2] = b22;
+      // V J_Q on rows 2P, 2P+1 (V's rows stay; its columns move with A's)
+      vdst[r1 + nc1] = cQ * v11 - sQ * v12;
+      vdst[r1 + nc2] = sQ * v11 + cQ * v12;
+      vdst[r2 + nc1] = cQ * v21 - sQ * v22;
+      vdst[r2 + nc2] = sQ * v21 + cQ * v22;
+      if (last) {
+        if (P == Q) {  // b11, b22 on the diagonal
+          dia += b11 * b11 + b22 * b22;
+          off += b12 * b12 + b21 * b21;
+        } else {
+          off += b11 * b11 + b12 * b12 + b21 * b21 + b22 * b22;
+        }
+      }
+    }
+    __syncthreads();
+  };
   double prev = 0.0;  // off-diagonal mass before the last sweep
+  bool flip = false;  // data in (W2, V) rather than (W1, A)
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (!(off > 1e-30 * (dia + off)) || (sweep > 0 && off >= prev)) break;
     prev = off;
     off = 0.0;
     dia = 0.0;
     for (int rd = 0; rd < m1; ++rd) {
-      if (act) {
-        int i1, i2, j1, j2;
-        round_robin_pair(rd, P, m1, i1, i2);
-        round_robin_pair(rd, Q, m1, j1, j2);
-        const int ri1 = __umul24(i1, ne), ri2 = __umul24(i2, ne), rj1 = __umul24(j1, ne), rj2 = __umul24(j2, ne);
-        const double p11 = cur[ri1 + i1], p22 = cur[ri2 + i2], p12 = cur[ri1 + i2];
-        const double q11 = cur[rj1 + j1], q22 = cur[rj2 + j2], q12 = cur[rj1 + j2];
-        const double a11 = cur[ri1 + j1], a12 = cur[ri1 + j2];
-        const double a21 = cur[ri2 + j1], a22 = cur[ri2 + j2];
-        const double v11 = Vp[ri1 + j1], v12 = Vp[ri1 + j2];
-        const double v21 = Vp[ri2 + j1], v22 = Vp[ri2 + j2];
-        double cP, sP, cQ, sQ;
-        jacobi_rotation(p11, p22, p12, cP, sP);
-        jacobi_rotation(q11, q22, q12, cQ, sQ);
-        // M = A J_Q, then J_P^T M
-        const double m11 = cQ * a11 - sQ * a12, m12 = sQ * a11 + cQ * a12;
-        const double m21 = cQ * a21 - sQ * a22, m22 = sQ * a21 + cQ * a22;
-        const double b11 = cP * m11 - sP * m21, b12 = cP * m12 - sP * m22;
-        const double b21 = sP * m11 + cP * m21, b22 = sP * m12 + cP * m22;
-        nxt[ri1 + j1] = b11;
-        nxt[ri1 + j2] = b12;
-        nxt[ri2 + j1] = b21;
-        nxt[ri2 + j2] = b22;
-        // V J_Q on rows i1, i2
-        Vp[ri1 + j1] = cQ * v11 - sQ * v12;
-        Vp[ri1 + j2] = sQ * v11 + cQ * v12;
-        Vp[ri2 + j1] = cQ * v21 - sQ * v22;
-        Vp[ri2 + j2] = sQ * v21 + cQ * v22;
-        if (rd == m1 - 1) {
-          const double s4 = b11 * b11 + b12 * b12 + b21 * b21 + b22 * b22;
-          if (P == Q) {  // b11, b22 on the diagonal
-            dia += b11 * b11 + b22 * b22;
-            off += b12 * b12 + b21 * b21;
-          } else {
-            off += s4;
-          }
-        }
-      }
-      __syncthreads();
-      double *x = cur;
-      cur = nxt;
-      nxt = x;
+      const bool last = rd == m1 - 1;
+      if (flip) one_round(W2, W1, V, A, last);
+      else one_round(W1, W2, A, V, last);
+      flip = !flip;
     }
     block_sum2(off, dia, sb);
   }
-  // sort descending (stable by index)
+  cur = flip ? W2 : W1;
+  nxt = flip ? W1 : W2;
+  vc = flip ? V : A;
+  // the eigenvectors now sit in vc, in slot order (= original order); if that
+  // is V's own area, move them out of the way first
+  if (vc == V) {
+    for (int e = t; e < ne * ne; e += nt) nxt[e] = vc[e];
+    __syncthreads();
+    vc = nxt;
+  }
+  // sort descending (stable by index): ranks first, then every entry of V
+  __shared__ int rank_of[32];
   for (int i = t; i < n; i += nt) {
     const double wi = cur[i * ne + i];
     int rk = 0;
@@ -301,7 +322,12 @@ __device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, 
       if (wj > wi || (wj == wi && j < i)) ++rk;
     }
     w[rk] = wi;
-    for (int rr = 0; rr < n; ++rr) V[rr * n + rk] = Vp[rr * ne + i];
+    rank_of[i] = rk;
+  }
+  __syncthreads();
+  for (int e = t; e < n * n; e += nt) {
+    const int rr = e / n, i = e - rr * n;
+    V[rr * n + rank_of[i]] = vc[rr * ne + i];
   }
   __syncthreads();
 }
