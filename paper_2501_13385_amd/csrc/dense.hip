@@ -324,7 +324,24 @@ __device__ inline void build_block(const Dev &d, int c, const double *sT, const 
 // partial buffer) and the finish of the last right-Gram step uses them.
 constexpr long long GB1_OFF = 1LL << 19;
 
-__device__ void left_cut(const Dev &d, int i, double *smem);
+// The 2R x 2R Gram partials are symmetric: producers write the upper triangle
+// only (row-major, n (n + 1) / 2 entries), which halves what the one-block
+// finishers read back.
+__device__ __forceinline__ int sym_index(int a, int b, int n) { return (a * (2 * n - a + 1)) / 2 + (b - a); }
+
+// total of nb packed symmetric partials, unpacked into full[n * n] (LDS);
+// packed: LDS of n (n + 1) / 2 doubles, scratch: blockDim.x doubles
+__device__ __forceinline__ void reduce_sym_partials(const double *part, int nb, int n, double *full, double *packed,
+                                                    double *scratch) {
+  reduce_partials(part, nb, n * (n + 1) / 2, packed, scratch);
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int a = t / n, b = t - a * n;
+    full[t] = packed[a <= b ? sym_index(a, b, n) : sym_index(b, a, n)];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void left_cut(const Dev &d, int i, double *smem);
 
 __device__ void gram_first_cut(const Dev &d, int lb) {
   const int R = d.R, R2 = 2 * R, NE = R2 * R2, RR = R * R;
@@ -333,8 +350,10 @@ __device__ void gram_first_cut(const Dev &d, int lb) {
   const int x0 = lb * per, x1 = min(d.n[0], x0 + per);
   const double alpha = d.st->alpha_n;
   const auto T = glb(d.cores), X = glb(d.X);
+  const int NP = R2 * (R2 + 1) / 2;
   for (int f = threadIdx.x; f < NE; f += blockDim.x) {
     const int a = f / R2, bb = f % R2;
+    if (a > bb) continue;
     double acc = 0.0;
     for (int x = x0; x < x1; ++x) {
       const long long off = d.coff[0] + (long long)x * RR;
@@ -342,7 +361,7 @@ __device__ void gram_first_cut(const Dev &d, int lb) {
       const double vb = (bb < R) ? -alpha * X[off + bb] : T[off + bb - R];
       acc += va * vb;
     }
-    glb(d.part)[GB1_OFF + (long long)lb * NE + f] = acc;
+    glb(d.part)[GB1_OFF + (long long)lb * NP + sym_index(a, bb, R2)] = acc;
   }
 }
 
@@ -408,11 +427,13 @@ __global__ void __launch_bounds__(1024) k_rgram(const Dev *__restrict__ dt, int 
     for (int t = q.tl; t < NE; t += q.TPG, ++u) red[q.g * NE + t] = acc[u];
   }
   __syncthreads();
-  auto mypart = glb(d.part) + (long long)blockIdx.x * NE;
+  auto mypart = glb(d.part) + (long long)blockIdx.x * (R2 * (R2 + 1) / 2);
   for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+    const int a = t / R2, bb = t - a * R2;
+    if (a > bb) continue;
     double v = 0.0;
     for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
-    mypart[t] = v;
+    mypart[sym_index(a, bb, R2)] = v;
   }
 }
 
@@ -425,14 +446,8 @@ __global__ void __launch_bounds__(1024) k_rgram_fin(const Dev *__restrict__ dt, 
   const int R = d.R, R2 = 2 * R, NE = R2 * R2;
 
   double *GR = sm_slot(d, b, S_GR);
-  {
-    double *tot = smem + 4096;
-    reduce_partials(d.part, nb, NE, tot, smem);
-    for (int t = threadIdx.x; t < NE; t += blockDim.x) GR[t] = tot[t];
-    __syncthreads();
-    for (int t = threadIdx.x; t < NE; t += blockDim.x) smem[3072 + t] = tot[t];
-  }
-  __syncthreads();
+  reduce_sym_partials(d.part, nb, R2, smem + 3072, smem + 5120, smem);
+  for (int t = threadIdx.x; t < NE; t += blockDim.x) GR[t] = smem[3072 + t];
   // compress to the active indices [0, r_b) U [R, R + r_b)
   const int rb = d.r[b], na = 2 * rb;
   double *A = smem, *Fc = smem + 1024;
@@ -456,7 +471,7 @@ __global__ void __launch_bounds__(1024) k_rgram_fin(const Dev *__restrict__ dt, 
     // the first left cut: its Gram came from the first right-Gram launch
     __threadfence_block();
     __syncthreads();
-    reduce_partials(d.part + GB1_OFF, nblocks_for(d.n[0], 4), NE, smem, smem + 1024);
+    reduce_sym_partials(d.part + GB1_OFF, nblocks_for(d.n[0], 4), R2, smem, smem + 5120, smem + 1024);
     left_cut(d, 1, smem);
   }
 }
@@ -520,11 +535,13 @@ __global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i
     for (int t = q.tl; t < NE; t += q.TPG, ++u) red[q.g * NE + t] = acc[u];
   }
   __syncthreads();
-  auto mypart = glb(d.part) + (long long)blockIdx.x * NE;
+  auto mypart = glb(d.part) + (long long)blockIdx.x * (R2 * (R2 + 1) / 2);
   for (int t = threadIdx.x; t < NE; t += blockDim.x) {
+    const int a = t / R2, bb = t - a * R2;
+    if (a > bb) continue;
     double v = 0.0;
     for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
-    mypart[t] = v;
+    mypart[sym_index(a, bb, R2)] = v;
   }
 }
 
@@ -532,7 +549,7 @@ __global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i
 // truncation to r_i: Tr_i and P_i
 // Truncation at cut i from G_B (in smem[0, NE)) and F_i (sm slot): S = F^T G_B F,
 // eigen-decomposition, Tr_i and P_i (one block).
-__device__ void left_cut(const Dev &d, int i, double *smem) {
+__device__ __forceinline__ void left_cut(const Dev &d, int i, double *smem) {
   const int R = d.R, R2 = 2 * R, NE = R2 * R2;
 
   // last block: S = F^T GB F, eigen-decomposition, truncation to r_i
@@ -624,7 +641,7 @@ __global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, i
   const int nb = nblocks_for(d.n[i - 1], 4);
   if (d.st->done) return;
   __shared__ double smem[SMEM];
-  reduce_partials(d.part, nb, (2 * d.R) * (2 * d.R), smem, smem + 1024);
+  reduce_sym_partials(d.part, nb, 2 * d.R, smem, smem + 5120, smem + 1024);
   left_cut(d, i, smem);
 }
 
