@@ -170,13 +170,17 @@ prgd_status prgd_iterate(prgd_solver s, int32_t iters);
 prgd_status prgd_iterate_profiled(prgd_solver s, int32_t iters, double *phase_ms);
 
 /* Runs `iters` iterations exactly as prgd_iterate does, timed on the device
-   with two HIP events per iteration instead of seven: *main_ms receives the
-   summed device milliseconds of the sampled pass's main kernel (the interval
-   of phase 0 of prgd_iterate_profiled), *total_ms the device milliseconds from
-   the start of the first iteration to the end of the last.  Waits for the
-   solver's stream.  Both outputs are host pointers and required.
-   Errors: PRGD_EINVAL (iters < 0 or a null output), PRGD_EDEVICE. */
-prgd_status prgd_iterate_timed(prgd_solver s, int32_t iters, double *main_ms, double *total_ms);
+   with HIP events: the sampled pass's main kernel of every iteration `it` with
+   it % stride == 0 is bracketed by two events (the interval of phase 0 of
+   prgd_iterate_profiled), and *main_ms receives the mean of those intervals
+   in milliseconds per bracketed launch; *total_ms receives the device
+   milliseconds from the start of the first iteration to the end of the last.
+   Each recorded event idles the device for a few microseconds between
+   kernels, so a stride above 1 keeps that cost out of most iterations.
+   Waits for the solver's stream.  Both outputs are host pointers and
+   required.  Errors: PRGD_EINVAL (iters < 0, stride < 1 or a null output),
+   PRGD_EDEVICE. */
+prgd_status prgd_iterate_timed(prgd_solver s, int32_t iters, int32_t stride, double *main_ms, double *total_ms);
 
 /* Wait for the solver's stream. */
 prgd_status prgd_sync(prgd_solver s);

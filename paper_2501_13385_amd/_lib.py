@@ -116,7 +116,7 @@ def load() -> C.CDLL:
         "prgd_iterate": (i32, [vp, i32]),
         "prgd_sync": (i32, [vp]),
         "prgd_iterate_profiled": (i32, [vp, i32, dp]),
-        "prgd_iterate_timed": (i32, [vp, i32, dp, dp]),
+        "prgd_iterate_timed": (i32, [vp, i32, i32, dp, dp]),
         "prgd_run": (i32, [vp, C.POINTER(prgd_report)]),
         "prgd_get_report": (i32, [vp, C.POINTER(prgd_report)]),
         "prgd_get_cores": (i32, [vp, dp, i64]),
@@ -277,11 +277,12 @@ def prgd_iterate_profiled(h, iters: int) -> dict:
     return {PHASES[i]: float(buf[i]) for i in range(NPHASES)}
 
 
-def prgd_iterate_timed(h, iters: int):
-    """Run `iters` iterations; returns (main sampled kernel ms, whole run ms), device time."""
+def prgd_iterate_timed(h, iters: int, stride: int = 1):
+    """Run `iters` iterations; returns (mean ms of the main sampled kernel over
+    the iterations it % stride == 0, whole run ms), device time."""
     k1 = C.c_double(0.0)
     tot = C.c_double(0.0)
-    _check(load().prgd_iterate_timed(h, int(iters), C.byref(k1), C.byref(tot)))
+    _check(load().prgd_iterate_timed(h, int(iters), int(stride), C.byref(k1), C.byref(tot)))
     return float(k1.value), float(tot.value)
 
 
@@ -404,8 +405,8 @@ class Solver:
     def iterate_profiled(self, k: int) -> dict:
         return prgd_iterate_profiled(self.h, k)
 
-    def iterate_timed(self, k: int):
-        return prgd_iterate_timed(self.h, k)
+    def iterate_timed(self, k: int, stride: int = 1):
+        return prgd_iterate_timed(self.h, k, stride)
 
     def run(self) -> dict:
         return prgd_run(self.h)

@@ -817,37 +817,41 @@ prgd_status prgd_iterate(prgd_solver s, int32_t iters) {
   return enqueue_iterations(s, iters);
 }
 
-prgd_status prgd_iterate_timed(prgd_solver s, int32_t iters, double *main_ms, double *total_ms) {
+prgd_status prgd_iterate_timed(prgd_solver s, int32_t iters, int32_t stride, double *main_ms, double *total_ms) {
   if (!s) return fail(PRGD_ESTATE, "null solver");
-  if (iters < 0 || !main_ms || !total_ms) return fail(PRGD_EINVAL, "iters < 0 or null output");
+  if (iters < 0 || stride < 1 || !main_ms || !total_ms) return fail(PRGD_EINVAL, "iters < 0, stride < 1 or null output");
   *main_ms = 0.0;
   *total_ms = 0.0;
   if (iters == 0) return PRGD_OK;
-  // ev[2 it] before iteration it, ev[2 it + 1] after its main sampled kernel,
-  // ev[2 iters] after the last iteration
-  std::vector<hipEvent_t> ev((size_t)2 * iters + 1);
+  // for the k-th bracketed iteration: ev[2 k] before it, ev[2 k + 1] after its
+  // main sampled kernel; ev.back() after the last iteration
+  const int nbr = (iters + stride - 1) / stride;
+  std::vector<hipEvent_t> ev((size_t)2 * nbr + 1);
   for (auto &e : ev) HIPCHECK(hipEventCreate(&e));
   const Batch bt = s->batch();
   hipError_t err = hipSuccess;
   auto chk = [&](hipError_t x) { if (x != hipSuccess && err == hipSuccess) err = x; };
   for (int it = 0; it < iters && err == hipSuccess; ++it) {
-    chk(hipEventRecord(ev[2 * it], s->stream));
-    chk(sampled_pass(s, 0, ev[2 * it + 1]));
+    const bool br = it % stride == 0;
+    const int k = it / stride;
+    if (br) chk(hipEventRecord(ev[2 * k], s->stream));
+    chk(sampled_pass(s, 0, br ? ev[2 * k + 1] : nullptr));
     chk(launch_dense_iteration(bt, s->stream, 0));
     if (s->has_truth) chk(launch_truth_sweep(bt, s->stream, 0));
   }
-  chk(hipEventRecord(ev[2 * iters], s->stream));
+  chk(hipEventRecord(ev.back(), s->stream));
   prgd_status rc = PRGD_OK;
   if (err != hipSuccess) rc = fail(PRGD_EDEVICE, std::string("launch: ") + hipGetErrorString(err));
   if (rc == PRGD_OK && hipStreamSynchronize(s->stream) != hipSuccess) rc = fail(PRGD_EDEVICE, "sync failed");
   if (rc == PRGD_OK) {
-    for (int it = 0; it < iters; ++it) {
+    for (int k = 0; k < nbr; ++k) {
       float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, ev[2 * it], ev[2 * it + 1]);
+      (void)hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
       *main_ms += ms;
     }
+    *main_ms /= nbr;
     float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, ev[0], ev[2 * iters]);
+    (void)hipEventElapsedTime(&ms, ev[0], ev.back());
     *total_ms = ms;
   }
   for (auto &e : ev) (void)hipEventDestroy(e);

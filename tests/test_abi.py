@@ -107,7 +107,7 @@ def test_iteration_calls_reject_a_null_solver():
     a, b = ctypes.c_double(1.0), ctypes.c_double(1.0)
     assert lib.prgd_iterate(None, 1) == L.ESTATE
     assert lib.prgd_iterate_profiled(None, 1, buf) == L.ESTATE
-    assert lib.prgd_iterate_timed(None, 1, ctypes.byref(a), ctypes.byref(b)) == L.ESTATE
+    assert lib.prgd_iterate_timed(None, 1, 1, ctypes.byref(a), ctypes.byref(b)) == L.ESTATE
     assert lib.prgd_sync(None) == L.ESTATE
 
 

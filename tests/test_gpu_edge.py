@@ -148,15 +148,20 @@ def test_timed_and_profiled_iterations_match_plain_ones(L):
     pb = wl.named("c2_small")
     y = tt.tt_eval(pb.truth, pb.indices)
     outs = {}
-    for mode in ("plain", "timed", "profiled"):
+    for mode in ("plain", "timed", "timed3", "profiled"):
         s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, step=0.9, stop_rule="none", max_iter=8)
         try:
             if mode == "plain":
                 s.iterate(6)
                 s.sync()
-            elif mode == "timed":
-                k1, total = s.iterate_timed(6)
-                assert 0.0 < k1 <= total
+            elif mode in ("timed", "timed3"):
+                stride = 1 if mode == "timed" else 3
+                if mode == "timed3":
+                    with pytest.raises(L.PrgdError):
+                        s.iterate_timed(2, 0)     # stride < 1: rejected before any launch
+                k1, total = s.iterate_timed(6, stride)   # mean per bracketed launch
+                bracketed = -(-6 // stride)
+                assert 0.0 < k1 and bracketed * k1 <= total
             else:
                 ph = s.iterate_profiled(6)
                 assert len(ph) == L.NPHASES and all(v >= 0.0 for v in ph.values())
@@ -164,5 +169,5 @@ def test_timed_and_profiled_iterations_match_plain_ones(L):
             outs[mode] = s.cores()
         finally:
             s.close()
-    for mode in ("timed", "profiled"):
+    for mode in ("timed", "timed3", "profiled"):
         assert rel_dist(outs[mode], outs["plain"]) <= 1e-13, mode
