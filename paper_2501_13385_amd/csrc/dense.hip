@@ -162,7 +162,9 @@ __global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j
     red[(q.g * 2 + 1) * RR + e] = acct;
   }
   __syncthreads();
-  auto mypart = glb(d.part) + (long long)blockIdx.x * 2 * RR;
+  // left blocks: GL and Theta (2 RR each); right blocks: H only (RR each,
+  // after the left blocks' partials)
+  auto mypart = glb(d.part) + (left ? (long long)lb * 2 * RR : (long long)nbL * 2 * RR + (long long)lb * RR);
   for (int t = threadIdx.x; t < RR; t += blockDim.x) {
     double a0 = 0.0, a1 = 0.0;
     for (int g = 0; g < q.G; ++g) {
@@ -170,7 +172,7 @@ __global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j
       a1 += red[(g * 2 + 1) * RR + t];
     }
     mypart[t] = a0;
-    mypart[RR + t] = a1;
+    if (left) mypart[RR + t] = a1;
   }
 }
 
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, i
       THc[t] = tot[RR + t];
     }
     __syncthreads();
-    reduce_partials(d.part + (long long)nbL * 2 * RR, nbT - nbL, 2 * RR, tot, smem);
+    reduce_partials(d.part + (long long)nbL * 2 * RR, nbT - nbL, RR, tot, smem);
     for (int t = threadIdx.x; t < RR; t += blockDim.x) Hb[t] = tot[t];
   }
   __threadfence_block();

@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(256) k_sampled_priv_reduce(const Dev *__restri
 // finish of the sampled pass (one block): total ||R||^2 from the per-block
 // partials, then the weights and the residual stopping test
 template <typename F>
-__global__ void __launch_bounds__(256) k_sampled_fin(const Dev *__restrict__ dt, int diag) {
+__global__ void __launch_bounds__(1024) k_sampled_fin(const Dev *__restrict__ dt, int diag) {
   const Dev &d = dt[blockIdx.y];
   if (!diag && d.st->done) return;
   const double *rsq_part = d.use3 ? d.q3.part_rsq : (d.use_modes ? d.mp_rsq : d.part);
@@ -202,9 +202,9 @@ __global__ void __launch_bounds__(256) k_sampled_fin(const Dev *__restrict__ dt,
 
 hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s) {
   if (bt.host[0].prec == PREC_MIXED)
-    hipLaunchKernelGGL(k_sampled_fin<float>, dim3(1, bt.ns), dim3(256), 0, s, bt.dt, diag);
+    hipLaunchKernelGGL(k_sampled_fin<float>, dim3(1, bt.ns), dim3(1024), 0, s, bt.dt, diag);
   else
-    hipLaunchKernelGGL(k_sampled_fin<double>, dim3(1, bt.ns), dim3(256), 0, s, bt.dt, diag);
+    hipLaunchKernelGGL(k_sampled_fin<double>, dim3(1, bt.ns), dim3(1024), 0, s, bt.dt, diag);
   return hipGetLastError();
 }
 
