@@ -23,10 +23,20 @@ __device__ void sampled_finish_total(const Dev &d, F *sacc, double rs, int diag)
   }
   const int m = d.m;
   const int stot = d.soff[m];
+  // the first KC slice sums of each thread stay in registers for the weights
+  constexpr int KC = 4;
+  double sv[KC];
   double emax = 0.0;
-  for (int i = threadIdx.x; i < stot; i += blockDim.x) emax = fmax(emax, (double)sacc[i]);
+#pragma unroll
+  for (int u = 0; u < KC; ++u) {
+    const int i = threadIdx.x + u * blockDim.x;
+    sv[u] = i < stot ? (double)sacc[i] : 0.0;
+    emax = fmax(emax, sv[u]);
+  }
+  for (int i = threadIdx.x + KC * blockDim.x; i < stot; i += blockDim.x) emax = fmax(emax, (double)sacc[i]);
   emax = block_max(emax, sbuf);
   __shared__ int go;
+  __shared__ double eps_sh;
   if (threadIdx.x == 0) {
     go = 0;
     st->res_sq = rs;
@@ -56,6 +66,7 @@ __device__ void sampled_finish_total(const Dev &d, F *sacc, double rs, int diag)
     } else {
       const double epsn = (d.metric == METRIC_EUCLIDEAN) ? 1.0 : (d.eps_fixed > 0.0 ? d.eps_fixed : emax);
       st->eps_n = epsn;
+      eps_sh = epsn;
       st->alpha_n = (d.step_policy == STEP_THEORY) ? d.step / d.p
                     : (d.step_policy == STEP_CONST) ? d.step / sqrt(epsn) : 0.0;
       rec.eps = epsn;
@@ -67,10 +78,18 @@ __device__ void sampled_finish_total(const Dev &d, F *sacc, double rs, int diag)
   }
   __syncthreads();
   if (go) {
-    const double inv = 1.0 / st->eps_n;
+    const double inv = 1.0 / eps_sh;
     const double ex = 1.0 / (2.0 * m);
     const bool euclid = d.metric == METRIC_EUCLIDEAN;
-    for (int i = threadIdx.x; i < stot; i += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < KC; ++u) {
+      const int i = threadIdx.x + u * blockDim.x;
+      if (i < stot) {
+        d.omega[i] = euclid ? 1.0 : pow(1.0 + sv[u] * inv, ex);
+        sacc[i] = (F)0;
+      }
+    }
+    for (int i = threadIdx.x + KC * blockDim.x; i < stot; i += blockDim.x) {
       d.omega[i] = euclid ? 1.0 : pow(1.0 + (double)sacc[i] * inv, ex);
       sacc[i] = (F)0;
     }
