@@ -345,7 +345,10 @@ __device__ inline bool block_spd_inverse_pair(const double *A1, int lda1, int n1
   __shared__ int bad;
   const int t = threadIdx.x, nt = blockDim.x;
   const int w1 = 2 * n1, w2 = 2 * n2, s1 = n1 * w1, s2 = n2 * w2, tot = s1 + s2;
-  double *buf[2] = {scratch, scratch + tot};
+  // the two buffers are picked with a select of LDS addresses (an array of
+  // pointers indexed at run time would hide the address space and turn every
+  // access into a flat one)
+  double *const buf0 = scratch, *const buf1 = scratch + tot;
   // this thread's first entry (row i, column j of its matrix)
   const bool first0 = t < s1;
   const int w0 = first0 ? w1 : w2, nn0 = first0 ? n1 : n2, base0 = first0 ? 0 : s1;
@@ -359,15 +362,15 @@ __device__ inline bool block_spd_inverse_pair(const double *A1, int lda1, int n1
       const int f = e - s1, i = f / w2, j = f % w2;
       v = (j < n2) ? A2[i * lda2 + j] : (j - n2 == i ? 1.0 : 0.0);
     }
-    buf[0][e] = v;
+    buf0[e] = v;
   }
   if (t == 0) bad = 0;
   __syncthreads();
   const int nmax = n1 > n2 ? n1 : n2;
   int cur = 0;
   for (int k = 0; k < nmax; ++k) {
-    const double *M = buf[cur];
-    double *Mn = buf[cur ^ 1];
+    const double *M = cur ? buf1 : buf0;
+    double *Mn = cur ? buf0 : buf1;
     for (int e = t; e < tot; e += nt) {
       bool first = first0;
       int w = w0, n = nn0, base = base0, i = i0, j = j0;
@@ -388,7 +391,7 @@ __device__ inline bool block_spd_inverse_pair(const double *A1, int lda1, int n1
     __syncthreads();
     cur ^= 1;
   }
-  const double *M = buf[cur];
+  const double *M = cur ? buf1 : buf0;
   for (int e = t; e < 2 * R * R; e += nt) {
     const bool first = e < R * R;
     const int f = first ? e : e - R * R, i = f / R, j = f % R;
