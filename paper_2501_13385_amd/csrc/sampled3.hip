@@ -16,12 +16,15 @@
 //   * dT_2(x2) = sum over the segment of R l r^T is a rank-K update that the
 //     matrix cores accumulate: 16x16x4 MFMAs whose A/B operands (R_k l_k[c],
 //     r_k[c]) are fetched directly in the MFMA lane layout, so no transpose
-//     is needed; each wave's accumulator is added into a small per-workgroup
-//     segment table in LDS when the segment changes.
+//     is needed, and whose samples come from the lane's own row of 16 (a DPP
+//     broadcast instead of a cross-row shuffle through LDS); each wave's
+//     accumulator is added into a small per-workgroup segment table in LDS
+//     when the segment changes.
 // A second kernel sums the partials in a fixed order and finishes the metric
 // weights.  The LDS atomics inside a workgroup add in an order that varies from
 // run to run, so results repeat to rounding, not bit for bit.
 #include <algorithm>
+#include <utility>
 
 #include "prgd_internal.hpp"
 #include "block_ops.hpp"
@@ -53,8 +56,42 @@ struct Mma<float> {
   __device__ static int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
-__device__ inline double ld_shfl(double v, int src) { return __shfl(v, src, 64); }
-__device__ inline float ld_shfl(float v, int src) { return __shfl(v, src, 64); }
+// value of lane 16 (l / 16) + N in lane l: DPP row_newbcast, which copies lane
+// N of each row of 16 lanes to the whole row without going through LDS
+template <int N>
+__device__ __forceinline__ int row_bcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false);
+}
+template <int N>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(row_bcast<N>(__float_as_int(v)));
+}
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = row_bcast<N>((int)b), hi = row_bcast<N>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// dT_2(v) += sum_k res_k l1_k r3_k^T over the 64 lanes of a wave as 16 MFMA
+// steps: in step S row r of the wave (the MFMA's k index) holds the sample of
+// lane 16 r + S, so the operands come from the lane's own row
+template <typename M, typename F, int R, int... S>
+__device__ __forceinline__ void segment_mfma(typename M::acc_t &acc, F res, int x1, int x3, const F *T1,
+                                             const F *T3, int c, std::integer_sequence<int, S...>) {
+  (
+      [&] {
+        const F rk = row_bcast<S>(res);
+        const int x1k = row_bcast<S>(x1), x3k = row_bcast<S>(x3);
+        F av = (F)0, bv = (F)0;
+        if (c < R) {
+          av = rk * T1[x1k * R + c];
+          bv = T3[x3k * R + c];
+        }
+        acc = M::step(av, bv, acc);
+      }(),
+      ...);
+}
 
 template <typename F, int R, int NT, bool STAGE>
 __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int diag) {
@@ -206,19 +243,7 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
         atomicAdd(&ls3[x3], (double)r2);
       }
       // dT_2(v) += sum_k res_k l1_k r3_k^T over this wave's 64 lanes (zero for others)
-#pragma unroll
-      for (int st = 0; st < 16; ++st) {
-        const int k = 4 * st + (lane >> 4);
-        const F rk = ld_shfl(res, k);
-        const int x1k = __shfl(x1, k, 64);
-        const int x3k = __shfl(x3, k, 64);
-        F av = (F)0, bv = (F)0;
-        if (c < R) {
-          av = rk * T1[x1k * R + c];
-          bv = T3[x3k * R + c];
-        }
-        acc = M::step(av, bv, acc);
-      }
+      segment_mfma<M, F, R>(acc, res, x1, x3, T1, T3, c, std::make_integer_sequence<int, 16>{});
     }
   }
   flush();
