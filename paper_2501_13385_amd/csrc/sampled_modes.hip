@@ -56,7 +56,7 @@ __device__ inline void mp_wave_sync() {
 // segment table
 __host__ __device__ inline size_t modes_lds_bytes(int R, int prec, int nt) {
   const size_t f = prec == PREC_MIXED ? 4 : 8;
-  return ((size_t)(nt / 64) * 2 * 64 * R + (size_t)KSEG * (R * R + 1)) * f;
+  return ((size_t)(nt / 64) * 2 * 64 * (R + 1) + (size_t)KSEG * (R * R + 1)) * f;
 }
 
 // Cores of every mode staged in LDS when they fit in this many bytes: the
@@ -161,11 +161,14 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
   extern __shared__ unsigned char lds_raw[];
   F *lseg = reinterpret_cast<F *>(lds_raw);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  F *P = lseg + KSEG * SEGW + (long long)w * 2 * 64 * R;   // [64][R]: R_j l_j
-  F *Q = P + 64 * R;                                        // [64][R]: r_j
+  // [64][R + 1]: R_j l_j and r_j, rows padded to an odd length so that the
+  // lanes' row-wise stores spread over the banks
+  constexpr int RP = R + 1;
+  F *P = lseg + KSEG * SEGW + (long long)w * 2 * 64 * RP;
+  F *Q = P + 64 * RP;
   for (int i = threadIdx.x; i < KSEG * SEGW; i += NT) lseg[i] = (F)0;
   const auto gcores = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores));
-  F *lcores = lseg + KSEG * SEGW + (long long)NW * 2 * 64 * R;
+  F *lcores = lseg + KSEG * SEGW + (long long)NW * 2 * 64 * RP;
   if (STAGE)
     for (long long i = threadIdx.x; i < d.coff[m]; i += NT) lcores[i] = gcores[i];
   __syncthreads();
@@ -306,8 +309,8 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
       // stage R_j l_j and r_j of this wave's lanes (zero for other segments)
 #pragma unroll
       for (int a = 0; a < R; ++a) {
-        P[lane * R + a] = res * lv[a];
-        Q[lane * R + a] = me ? rv[a] : (F)0;
+        P[lane * RP + a] = res * lv[a];
+        Q[lane * RP + a] = me ? rv[a] : (F)0;
       }
       mp_wave_sync();
 #pragma unroll
@@ -315,8 +318,8 @@ __global__ void __launch_bounds__(NT) k_modes(const Dev *__restrict__ dt, int di
         const int kk = 4 * st + (lane >> 4);
         F av = (F)0, bv = (F)0;
         if (c < R) {
-          av = P[kk * R + c];
-          bv = Q[kk * R + c];
+          av = P[kk * RP + c];
+          bv = Q[kk * RP + c];
         }
         acc = M::step(av, bv, acc);
       }
