@@ -49,9 +49,39 @@ __device__ __forceinline__ unsigned long long dpp_u64(unsigned long long k) {
   return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
+// value of lane l ^ 16 in lane l (the rows of 16 swapped pairwise), by
+// v_permlane16_swap instead of a trip through LDS; whole wave active
+__device__ __forceinline__ unsigned long long xor16_u64(unsigned long long k) {
+  const int lo = (int)(unsigned)k, hi = (int)(unsigned)(k >> 32);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  // a[0] holds rows (0, 0, 2, 2) and a[1] rows (1, 1, 3, 3) of the input
+  const bool odd = (threadIdx.x >> 4) & 1;
+  const unsigned l = (unsigned)(odd ? a[0] : a[1]), h = (unsigned)(odd ? b[0] : b[1]);
+  return ((unsigned long long)h << 32) | l;
+}
+
+// value of lane (l & 31) + 32 upper in lane l, by v_permlane32_swap; whole
+// wave active
+__device__ __forceinline__ double half_value(double v, bool upper) {
+  const long long b = __double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((int)b, (int)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((int)(b >> 32), (int)(b >> 32), false, false);
+  // [0] holds the lower half's values in both halves, [1] the upper half's
+  const unsigned l = (unsigned)(upper ? lo[1] : lo[0]), h = (unsigned)(upper ? hi[1] : hi[0]);
+  return __longlong_as_double((long long)(((unsigned long long)h << 32) | l));
+}
+
+// value of v in lane c (c wave-uniform)
+__device__ __forceinline__ double lane_value(double v, int c) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, c), hi = __builtin_amdgcn_readlane((int)(b >> 32), c);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // max of a 64-bit key over each group of 32 lanes (the two halves of the wave
 // reduce separately): DPP exchanges inside rows of 16 lanes, then one swap of
-// the rows.  Keys are compared as unsigned integers.
+// the rows.  Keys are compared as unsigned integers.  Whole wave active.
 __device__ __forceinline__ unsigned long long key_max32(unsigned long long k) {
   unsigned long long o;
   o = dpp_u64<0xB1>(k);   // quad_perm [1,0,3,2]: lane ^ 1
@@ -62,7 +92,7 @@ __device__ __forceinline__ unsigned long long key_max32(unsigned long long k) {
   k = o > k ? o : k;
   o = dpp_u64<0x140>(k);  // row_mirror: lane i <-> 15 - i within 16
   k = o > k ? o : k;
-  o = __shfl_xor(k, 16, 64);
+  o = xor16_u64(k);
   return o > k ? o : k;
 }
 
@@ -102,7 +132,7 @@ __device__ inline int block_pivoted_cholesky(const double *A, int n, double *F) 
       const unsigned long long key = avail ? ((bits & ~31ull) | (unsigned long long)(31 - i)) : 0ull;
       const unsigned long long kmax = key_max32(key);
       const int p = 31 - (int)(__builtin_amdgcn_readfirstlane((unsigned)kmax) & 31u);
-      const double best = __shfl(dg, p, 64);
+      const double best = lane_value(dg, p);
       if (kmax == 0ull || !(best > tol)) break;
       rank = k + 1;
       const double rs = rsq_newton<2>(best);  // 1 / sqrt(pivot)
@@ -111,7 +141,7 @@ __device__ inline int block_pivoted_cholesky(const double *A, int n, double *F) 
       double colv = a[0];
 #pragma unroll
       for (int c = 1; c < 16; ++c) colv = (c == cp) ? a[c] : colv;
-      const double x = __shfl(colv, i + 32 * (p >> 4), 64);
+      const double x = half_value(colv, p >= 16);
       const double f = (i == p || avail) && i < n ? x * rs : 0.0;
       if (i == p) avail = false;
       dg = fma(-f, f, dg);
