@@ -176,8 +176,7 @@ __global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j
   }
 }
 
-// finish of a Gram sweep step (one block): totals, inverses, and after the
-// last step the products Psi_c
+// finish of a Gram sweep step (one block): totals and inverses
 __global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, int j) {
   const Dev &d = dt[blockIdx.y];
   if (d.st->done) return;
@@ -214,35 +213,6 @@ __global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, i
     }
     return;
   }
-  if (j == m - 1) {
-    // Psi_c = GL_{c+1}^{-1} Theta_c H_{c+1}^{-1}, c = 0..m-2 (operands staged
-    // in LDS; the inverses were written above or by earlier launches)
-    double *gi = smem, *th = smem + 256, *hi = smem + 512, *t1 = smem + 768;
-    for (int cc = 0; cc < m - 1; ++cc) {
-      const auto ggi = glb(sm_slot(d, cc + 1, S_GLI)), gth = glb(sm_slot(d, cc, S_TH)), ghi = glb(sm_slot(d, cc + 1, S_HI));
-      for (int t = threadIdx.x; t < RR; t += blockDim.x) {
-        gi[t] = ggi[t];
-        th[t] = gth[t];
-        hi[t] = ghi[t];
-      }
-      __syncthreads();
-      for (int t = threadIdx.x; t < RR; t += blockDim.x) {
-        const int a = t / R, b = t - a * R;
-        double v = 0.0;
-        for (int k = 0; k < R; ++k) v = fma(gi[a * R + k], th[k * R + b], v);
-        t1[t] = v;
-      }
-      __syncthreads();
-      auto psi = glb(sm_slot(d, cc, S_PSI));
-      for (int t = threadIdx.x; t < RR; t += blockDim.x) {
-        const int a = t / R, b = t - a * R;
-        double v = 0.0;
-        for (int k = 0; k < R; ++k) v = fma(t1[a * R + k], hi[k * R + b], v);
-        psi[t] = v;
-      }
-      __syncthreads();
-    }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -256,11 +226,32 @@ __global__ void __launch_bounds__(1024) k_tangent(const Dev *__restrict__ dt) {
   block_core(d, c, x0, x1);
   const int R = d.R, RR = R * R, m = d.m;
   double *GI = smem, *HI = smem + RR, *PS = smem + 2 * RR;
-  const double *gi = sm_slot(d, c, S_GLI), *hi = sm_slot(d, c + 1, S_HI), *ps = sm_slot(d, c, S_PSI);
+  // Psi_c = GL_{c+1}^{-1} Theta_c H_{c+1}^{-1} (zero for the last core), formed
+  // by every block from the finished Grams; its operands sit where the slice
+  // buffers go afterwards
+  double *G1 = smem + 3 * RR, *TH = G1 + RR, *T1 = TH + RR;
+  const bool psi = c < m - 1;
+  const double *gi = sm_slot(d, c, S_GLI), *hi = sm_slot(d, c + 1, S_HI);
+  const double *g1 = sm_slot(d, psi ? c + 1 : c, S_GLI), *th = sm_slot(d, c, S_TH);
   for (int t = threadIdx.x; t < RR; t += blockDim.x) {
     GI[t] = gi[t];
     HI[t] = hi[t];
-    PS[t] = (c < m - 1) ? ps[t] : 0.0;
+    G1[t] = g1[t];
+    TH[t] = th[t];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    const int a = t / R, b = t - a * R;
+    double v = 0.0;
+    for (int k = 0; k < R; ++k) v = fma(G1[a * R + k], TH[k * R + b], v);
+    T1[t] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    const int a = t / R, b = t - a * R;
+    double v = 0.0;
+    for (int k = 0; k < R; ++k) v = fma(T1[a * R + k], HI[k * R + b], v);
+    PS[t] = psi ? v : 0.0;
   }
   const Grp q = make_grp(RR);
   double *sT = smem + 3 * RR + q.g * 3 * RR;
@@ -746,25 +737,26 @@ __global__ void __launch_bounds__(1024) k_output_fin(const Dev *__restrict__ dt,
   const Dev &d = dt[blockIdx.y];
   const int nb = d.blk_off[d.m];
   if (d.st->done) return;
-  __shared__ double sbuf[16];
+  __shared__ double sbuf[32];
+  State *st = d.st;
+  // the state this thread updates is read before the reduction, so that its
+  // latency overlaps the partial loads
+  const double old = st->tnorm_sq;
+  const int it = st->iter;
   double a0 = 0.0, a1 = 0.0;
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
     a0 += glb(d.part)[2 * k];
     a1 += glb(d.part)[2 * k + 1];
   }
-  a0 = block_sum(a0, sbuf);
-  a1 = block_sum(a1, sbuf);
+  block_sum2(a0, a1, sbuf);
   if (threadIdx.x == 0) {
-    State *st = d.st;
     if (init) {
       st->tnorm_sq = a0;
     } else {
-      const double old = st->tnorm_sq;
       const double diff = fmax(0.0, a0 - 2.0 * a1 + old);
       const double rc = sqrt(diff) / fmax(1.0, sqrt(old));
       st->rel_change = rc;
       st->tnorm_sq = a0;
-      const int it = st->iter;
       if (it < d.hist_cap) {
         d.hist[it].rel_change = rc;
         d.hist[it].flags |= 1;

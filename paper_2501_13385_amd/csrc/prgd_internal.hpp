@@ -30,7 +30,6 @@ enum Slot {
   S_H,        // weighted right Gram H_b = sum_x w T H_{b+1} T^T          (R x R)
   S_HI,       // inverse of H_b                                           (R x R)
   S_TH,       // Theta_b = sum_x T_b^T Y_b  (core b)                       (R x R)
-  S_PSI,      // Psi_b = GL_{b+1}^{-1} Theta_b H_{b+1}^{-1}  (core b)       (R x R)
   S_GR,       // right Gram of the block TT W^{>=b}                       (2R x 2R)
   S_F,        // factor F_b with F F^T = GR_b (columns 0..rankF-1)       (2R x 2R)
   S_P,        // P_b = T'^{<=b,T} W^{<=b}                                (R x 2R)
