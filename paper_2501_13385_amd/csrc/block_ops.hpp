@@ -45,6 +45,27 @@ __device__ inline double block_max(double v, double *sbuf) {
   return r;
 }
 
+// Sum of s and maximum of m over the block in one pass (one exchange through
+// LDS), the same values in every thread.  sbuf: 32 doubles.
+__device__ inline void block_sum_max(double &s, double &m, double *sbuf) {
+  s = wave_sum(s);
+  m = wave_max(m);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    sbuf[w] = s;
+    sbuf[16 + w] = m;
+  }
+  __syncthreads();
+  s = 0.0;
+  m = sbuf[16];
+  for (int i = 0; i < nw; ++i) {
+    s += sbuf[i];
+    m = fmax(m, sbuf[16 + i]);
+  }
+  __syncthreads();
+}
+
 // Sum nb partial vectors part[b * ne + e] (b < nb, e < ne) into out[e] (LDS),
 // deterministically.  Threads split the partials into groups with several
 // independent accumulators each, so many loads are in flight at once (the
@@ -83,6 +104,44 @@ __device__ inline void reduce_partials(const double *part_, int nb, int ne, doub
       for (; b < nb; ++b) a[0] += part[(long long)b * ne + e];
       out[e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
+  }
+  __syncthreads();
+}
+
+// Two independent sets of partials reduced in one pass (their loads in
+// flight together): nbA vectors of neA doubles at partA into outA and nbB of
+// neB at partB into outB (both LDS).  Deterministic; the same order within
+// each set as reduce_partials when neA + neB <= blockDim.x.  scratch: LDS of
+// at least blockDim.x doubles.  Ends with a barrier.
+__device__ inline void reduce_partials2(const double *partA, int nbA, int neA, double *outA, const double *partB,
+                                        int nbB, int neB, double *outB, double *scratch) {
+  const int ne = neA + neB;
+  if (ne > (int)blockDim.x) {   // too wide for one pass
+    reduce_partials(partA, nbA, neA, outA, scratch);
+    reduce_partials(partB, nbB, neB, outB, scratch);
+    return;
+  }
+  const int nt = blockDim.x, t = threadIdx.x;
+  const int G = nt / ne, g = t / ne, e = t % ne;
+  const bool inA = e < neA;
+  const auto part = glb(inA ? partA : partB);
+  const int nb = inA ? nbA : nbB, w = inA ? neA : neB, ee = inA ? e : e - neA;
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (g < G) {
+    int b = g;
+    for (; b + 7 * G < nb; b += 8 * G) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += part[(long long)(b + u * G) * w + ee];
+    }
+    for (; b < nb; b += G) a[0] += part[(long long)b * w + ee];
+    scratch[g * ne + e] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  }
+  __syncthreads();
+  for (int i = t; i < ne; i += nt) {
+    double v = 0.0;
+    for (int gg = 0; gg < G; ++gg) v += scratch[gg * ne + i];
+    if (i < neA) outA[i] = v;
+    else outB[i - neA] = v;
   }
   __syncthreads();
 }

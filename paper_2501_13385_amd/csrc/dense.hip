@@ -187,15 +187,13 @@ __global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, i
   // last block: totals, inverses
   double *GLj = sm_slot(d, j, S_GL), *THc = sm_slot(d, j - 1, S_TH), *Hb = sm_slot(d, m - j, S_H);
   {
-    double *tot = smem + 2048;           // [2 RR]
-    reduce_partials(d.part, nbL, 2 * RR, tot, smem);
+    double *tot = smem + 2048, *toth = tot + 2 * RR;   // [2 RR] GL and Theta, [RR] H
+    reduce_partials2(d.part, nbL, 2 * RR, tot, d.part + (long long)nbL * 2 * RR, nbT - nbL, RR, toth, smem);
     for (int t = threadIdx.x; t < RR; t += blockDim.x) {
       GLj[t] = tot[t];
       THc[t] = tot[RR + t];
+      Hb[t] = toth[t];
     }
-    __syncthreads();
-    reduce_partials(d.part + (long long)nbL * 2 * RR, nbT - nbL, RR, tot, smem);
-    for (int t = threadIdx.x; t < RR; t += blockDim.x) Hb[t] = tot[t];
   }
   __threadfence_block();
   __syncthreads();

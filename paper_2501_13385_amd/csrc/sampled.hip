@@ -194,10 +194,9 @@ __global__ void __launch_bounds__(1024) k_sampled_fin(const Dev *__restrict__ dt
   if (!diag && d.st->done) return;
   const double *rsq_part = d.use3 ? d.q3.part_rsq : (d.use_modes ? d.mp_rsq : d.part);
   const int nb = d.use3 ? d.q3.nwg : (d.use_modes ? d.mt[0].nwg : d.nb_sampled);
-  __shared__ double sbuf[16];
   double v = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) v += rsq_part[i];
-  sampled_finish_total<F>(d, (F *)d.s, block_sum(v, sbuf), diag);
+  sampled_finish_total<F>(d, (F *)d.s, v, diag);   // v: this thread's share of ||R||^2
 }
 
 hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s) {

@@ -15,14 +15,14 @@ namespace prgd {
 // alpha / eps^{1/2}; with the Euclidean metric eps plays no part (eps_n = 1).
 template <typename F>
 __device__ void sampled_finish_total(const Dev &d, F *sacc, double rs, int diag) {
-  __shared__ double sbuf[16];
+  __shared__ double sbuf[32];
   State *st = d.st;
-  if (diag) {
-    if (threadIdx.x == 0) st->res_sq = rs;
-    return;
-  }
+  // the state this block updates is read first, so that its latency overlaps
+  // the loads of the slice sums
+  const double y_sq = st->y_sq;
+  const int it = st->iter;
   const int m = d.m;
-  const int stot = d.soff[m];
+  const int stot = diag ? 0 : d.soff[m];
   // the first KC slice sums of each thread stay in registers for the weights
   constexpr int KC = 4;
   double sv[KC];
@@ -34,15 +34,18 @@ __device__ void sampled_finish_total(const Dev &d, F *sacc, double rs, int diag)
     emax = fmax(emax, sv[u]);
   }
   for (int i = threadIdx.x + KC * blockDim.x; i < stot; i += blockDim.x) emax = fmax(emax, (double)sacc[i]);
-  emax = block_max(emax, sbuf);
+  block_sum_max(rs, emax, sbuf);   // rs enters as this thread's share of ||R||^2
+  if (diag) {
+    if (threadIdx.x == 0) st->res_sq = rs;
+    return;
+  }
   __shared__ int go;
   __shared__ double eps_sh;
   if (threadIdx.x == 0) {
     go = 0;
     st->res_sq = rs;
-    const double rel = st->y_sq > 0.0 ? sqrt(rs / st->y_sq) : sqrt(rs);
+    const double rel = y_sq > 0.0 ? sqrt(rs / y_sq) : sqrt(rs);
     st->rel_res = rel;
-    const int it = st->iter;
     IterRecord rec;
     rec.iter = it;
     rec.flags = 0;
