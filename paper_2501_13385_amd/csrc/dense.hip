@@ -573,21 +573,15 @@ __device__ __forceinline__ void left_cut(const Dev &d, int i, double *smem) {
     T1[a * rk + bcol] = v;
   }
   __syncthreads();
+  // S is symmetric: each entry of the upper triangle is formed once and
+  // mirrored, so the matrix handed to Jacobi is exactly symmetric
   for (int t = threadIdx.x; t < rk * rk; t += blockDim.x) {
     const int a = t / rk, bcol = t % rk;
+    if (a > bcol) continue;
     double v = 0.0;
     for (int k = 0; k < R2; ++k) v += F[k * R2 + a] * T1[k * rk + bcol];
-    S[t] = v;
-  }
-  __syncthreads();
-  // symmetrise (rounding) before Jacobi
-  for (int t = threadIdx.x; t < rk * rk; t += blockDim.x) {
-    const int a = t / rk, bcol = t % rk;
-    if (a < bcol) {
-      const double v = 0.5 * (S[a * rk + bcol] + S[bcol * rk + a]);
-      S[a * rk + bcol] = v;
-      S[bcol * rk + a] = v;
-    }
+    S[a * rk + bcol] = v;
+    S[bcol * rk + a] = v;
   }
   __syncthreads();
   block_jacobi_eig(S, rk, V, w, T1, Vs);  // T1 is free once S is formed
