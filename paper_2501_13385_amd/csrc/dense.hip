@@ -113,9 +113,10 @@ __global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j
   double acc = 0.0, acct = 0.0;
   const int e = q.tl;                    // one output entry per thread (RR <= TPG)
   const int ea = e / R, eb = e % R;
-  __syncthreads();
-  for (int base = x0; base < x1; base += q.G) {
-    const int x = base + q.g;
+  // the first round's slices are fetched before the barrier, with their loads
+  // in flight together with those of the staged matrices above
+  {
+    const int x = x0 + q.g;
     const bool act = (q.g < q.G) && (x < x1);
     if (act) {
       const long long off = d.coff[c] + (long long)x * RR;
@@ -124,7 +125,21 @@ __global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j
         if (want_th) sY[t] = load_grad(d, off + t);
       }
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    if (base != x0) {
+      if (act) {
+        const long long off = d.coff[c] + (long long)x * RR;
+        for (int t = q.tl; t < RR; t += q.TPG) {
+          sT[t] = glb(d.cores)[off + t];
+          if (want_th) sY[t] = load_grad(d, off + t);
+        }
+      }
+      __syncthreads();
+    }
     if (act && e < RR) {
       if (left) {
         double v = 0.0;   // tmp = GLprev * T
@@ -379,9 +394,10 @@ __global__ void __launch_bounds__(1024) k_rgram(const Dev *__restrict__ dt, int 
   double *tmp = C + NE;
   double *sT = tmp + NE, *sX = sT + R * R;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  __syncthreads();
-  for (int base = x0; base < x1; base += q.G) {
-    const int x = base + q.g;
+  // the first round's slices are fetched before the barrier, with their loads
+  // in flight together with those of the staged matrices above
+  {
+    const int x = x0 + q.g;
     const bool act = (q.g < q.G) && (x < x1);
     const long long off = d.coff[b] + (long long)x * R * R;
     if (act)
@@ -389,7 +405,20 @@ __global__ void __launch_bounds__(1024) k_rgram(const Dev *__restrict__ dt, int 
         sT[t] = glb(d.cores)[off + t];
         sX[t] = glb(d.X)[off + t];
       }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    const long long off = d.coff[b] + (long long)x * R * R;
+    if (base != x0) {
+      if (act)
+        for (int t = q.tl; t < R * R; t += q.TPG) {
+          sT[t] = glb(d.cores)[off + t];
+          sX[t] = glb(d.X)[off + t];
+        }
+      __syncthreads();
+    }
     if (act) build_block(d, b, sT, sX, alpha, C, q.tl, q.TPG);
     __syncthreads();
     if (act)
@@ -487,9 +516,10 @@ __global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i
   double *B = C + NE;
   double *sT = B + R * R2, *sX = sT + R * R;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  __syncthreads();
-  for (int base = x0; base < x1; base += q.G) {
-    const int x = base + q.g;
+  // the first round's slices are fetched before the barrier, with their loads
+  // in flight together with those of the staged matrices above
+  {
+    const int x = x0 + q.g;
     const bool act = (q.g < q.G) && (x < x1);
     const long long off = d.coff[c] + (long long)x * R * R;
     if (act)
@@ -497,7 +527,20 @@ __global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i
         sT[t] = glb(d.cores)[off + t];
         sX[t] = glb(d.X)[off + t];
       }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    const long long off = d.coff[c] + (long long)x * R * R;
+    if (base != x0) {
+      if (act)
+        for (int t = q.tl; t < R * R; t += q.TPG) {
+          sT[t] = glb(d.cores)[off + t];
+          sX[t] = glb(d.X)[off + t];
+        }
+      __syncthreads();
+    }
     if (act) build_block(d, c, sT, sX, alpha, C, q.tl, q.TPG);
     __syncthreads();
     if (act)
@@ -658,9 +701,10 @@ __global__ void __launch_bounds__(1024) k_output(const Dev *__restrict__ dt, int
   double *PC = C + R2 * R2;
   double *sT = PC + R * R2, *sX = sT + RR, *out = sX + RR;
   double nn = 0.0, cr = 0.0;
-  __syncthreads();
-  for (int base = x0; base < x1; base += q.G) {
-    const int x = base + q.g;
+  // the first round's slices are fetched before the barrier, with their loads
+  // in flight together with those of the staged matrices above
+  {
+    const int x = x0 + q.g;
     const bool act = (q.g < q.G) && (x < x1);
     const long long off = d.coff[c] + (long long)x * RR;
     if (act)
@@ -668,7 +712,20 @@ __global__ void __launch_bounds__(1024) k_output(const Dev *__restrict__ dt, int
         sT[t] = glb(d.cores)[off + t];
         sX[t] = glb(d.X)[off + t];
       }
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int base = x0; base < x1; base += q.G) {
+    const int x = base + q.g;
+    const bool act = (q.g < q.G) && (x < x1);
+    const long long off = d.coff[c] + (long long)x * RR;
+    if (base != x0) {
+      if (act)
+        for (int t = q.tl; t < RR; t += q.TPG) {
+          sT[t] = glb(d.cores)[off + t];
+          sX[t] = glb(d.X)[off + t];
+        }
+      __syncthreads();
+    }
     if (act) build_block(d, c, sT, sX, alpha, C, q.tl, q.TPG);
     __syncthreads();
     if (act)
