@@ -288,18 +288,24 @@ __global__ void __launch_bounds__(256) k_sampled3_reduce(const Dev *__restrict__
   if ((int)blockIdx.x < nbB) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int o = blockIdx.x * 64 + lane;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    // sixteen independent loads in flight per lane: the partials come from
+    // every XCD, so the time is set by the number of dependent round trips
+    double a[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) a[u] = 0.0;
     if (o < L) {
       int b = w;
-      for (; b + 12 < q.nwg; b += 16) {
-        a0 += (double)pb[(long long)b * L + o];
-        a1 += (double)pb[(long long)(b + 4) * L + o];
-        a2 += (double)pb[(long long)(b + 8) * L + o];
-        a3 += (double)pb[(long long)(b + 12) * L + o];
+      for (; b + 60 < q.nwg; b += 64) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) a[u] += (double)pb[(long long)(b + 4 * u) * L + o];
       }
-      for (; b < q.nwg; b += 4) a0 += (double)pb[(long long)b * L + o];
+      for (; b < q.nwg; b += 4) a[0] += (double)pb[(long long)b * L + o];
     }
-    red[w][lane] = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int h = 8; h > 0; h >>= 1)
+#pragma unroll
+      for (int u = 0; u < h; ++u) a[u] += a[u + h];
+    red[w][lane] = a[0];
     __syncthreads();
     if (w == 0 && o < L) {
       const double acc = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
