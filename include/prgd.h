@@ -60,8 +60,12 @@ typedef int32_t prgd_status;
 /* precision */
 #define PRGD_PREC_FP64   0   /* every step in float64                                        */
 #define PRGD_PREC_MIXED  1   /* sampled pass (evaluation, residual, weights, gradient
-                                scatter) in float32 with float32 accumulation; Grams,
-                                factorisations, retraction and stopping test in float64     */
+                                scatter) in float32 arithmetic.  Its sums accumulate in
+                                float32, except in the order-3 grouped kernel, whose
+                                boundary-core gradients and slice sums accumulate in
+                                float64 (LDS), and ||R||^2, always summed in float64.
+                                Grams, factorisations, retraction, stopping test in
+                                float64                                                     */
 /* step policy (section 3.2.2 and Theorem 1) */
 #define PRGD_STEP_THEORY 0   /* alpha_l = step * eps_l^{1/2} / p, p = N / (n_1...n_m);
                                 Theorem 1 uses step = 1.001                                 */
@@ -143,15 +147,24 @@ typedef struct {
 /* Total length of the packed cores for shape n[m] and ranks r[m+1] (-1 if invalid). */
 int64_t prgd_cores_numel(int32_t m, const int32_t *n, const int32_t *r);
 
-/* Validate the problem on the host, copy it to the device, group Omega by
-   sort_mode, left-orthogonalise T_0 and prepare the iteration.  Validation
+/* Set up one completion problem (section 1: observed entries y_j of T* at the
+   multi-indices of Omega; TT cores of the ranks tt_ranks, section 2.1) for
+   Algorithm 2 started at T_0 = init_cores, which Algorithm 2 requires to lie on
+   the rank-r manifold.  Validate the problem on the host, copy it to the
+   device, group Omega by sort_mode, left-orthogonalise T_0 (Algorithm 1 applied
+   to T_0 at its own ranks) and prepare the iteration.  Validation
    (shapes, ranks, index ranges, duplicate multi-indices, finite values) runs
    before any GPU work.  On success *out owns all device memory of the solve. */
 prgd_status prgd_create(const prgd_desc *desc, prgd_solver *out);
 
-/* Enqueue exactly `iters` iterations (fewer if the stopping rule fires or
-   max_iter is reached: later iterations become no-ops on the device) without
-   synchronising.  Returns PRGD_OK once enqueued. */
+/* Enqueue exactly `iters` iterations of Algorithm 2 (one iteration: residual
+   G_l on Omega, metric weights of section 3.2.1, direction P~_T W^{-1} G_l by
+   Lemma 3, step of section 3.2.2, W_l = T_l - alpha_l xi, T_{l+1} =
+   TT-SVD_r(W_l) by Algorithm 1) without synchronising; fewer if the stopping
+   rule fires or max_iter is reached (later iterations become no-ops on the
+   device).  Returns PRGD_OK once enqueued, PRGD_ESTATE for a null handle,
+   PRGD_EINVAL for iters < 0, PRGD_EDEVICE on a launch failure.  A breakdown
+   found on the device is reported by prgd_get_report / prgd_run. */
 prgd_status prgd_iterate(prgd_solver s, int32_t iters);
 
 /* Number of phases reported by prgd_iterate_profiled. */
@@ -185,15 +198,21 @@ prgd_status prgd_iterate_timed(prgd_solver s, int32_t iters, int32_t stride, dou
 /* Wait for the solver's stream. */
 prgd_status prgd_sync(prgd_solver s);
 
-/* Iterate until the stopping rule holds or max_iter iterations, then fill
-   *report (may be NULL).  Returns PRGD_OK, PRGD_NOT_CONVERGED or an error. */
+/* Iterate Algorithm 2 until the stopping rule (stop_rule, tol: the rules of
+   section 5.1) holds or max_iter iterations, then fill *report (may be NULL).
+   Returns PRGD_OK, PRGD_NOT_CONVERGED (cores hold the last iterate) or an
+   error: PRGD_EBREAKDOWN (non-positive-definite Gram, non-finite residual,
+   or a truncation whose kept singular values span more than 1e6, the
+   resolution of the Gram-form retraction), PRGD_EDEVICE, PRGD_ESTATE. */
 prgd_status prgd_run(prgd_solver s, prgd_report *report);
 
 /* Current state without iterating (synchronises). */
 prgd_status prgd_get_report(prgd_solver s, prgd_report *report);
 
-/* Copy the current iterate, packed, into host memory out[cap].  Cores 1..m-1
-   are left-orthogonal after any completed iteration. */
+/* Copy the current iterate T_l (the output of Algorithm 2 once the run has
+   stopped), packed, into host memory out[cap]; cap >= prgd_cores_numel or
+   PRGD_EINVAL.  Cores 1..m-1 are left-orthogonal (Algorithm 1's output form)
+   after any completed iteration. */
 prgd_status prgd_get_cores(prgd_solver s, double *out, int64_t cap);
 
 /* Copy up to cap per-iteration records into out; *count receives the number

@@ -412,10 +412,14 @@ def spectral_init_sketch(idx: np.ndarray, y: np.ndarray, shape: Sequence[int], r
         for x in range(n_i):                           # samples with x_i = x
             sel = idx[i] == x
             Y[:, x, :] = zl[sel].T @ psi[sel]
-        u, sv, _ = np.linalg.svd(Y.reshape(r_prev * n_i, sketch), full_matrices=False)
-        # numerical rank: r_i-th singular value above 1e-7 of the largest (the
-        # resolution of a Gram-matrix eigen-decomposition in float64)
-        if u.shape[1] < r_i or not sv[r_i - 1] > 1e-7 * sv[0]:
+        ymat = Y.reshape(r_prev * n_i, sketch)
+        u, sv, _ = np.linalg.svd(ymat, full_matrices=False)
+        # Algorithm 1 keeps the top r_i left singular vectors; they are only
+        # defined when the sketch has r_i singular values that float64 can tell
+        # from zero.  Numerical rank in the usual sense: singular values above
+        # max(rows, cols) * eps * sigma_1 (rounding of an SVD in float64).
+        tol = max(ymat.shape) * np.finfo(np.float64).eps * (sv[0] if sv.size else 0.0)
+        if u.shape[1] < r_i or not sv[r_i - 1] > tol:
             raise ValueError("sketch rank below the target rank")
         core = u[:, :r_i].reshape(r_prev, n_i, r_i)
         cores.append(core)

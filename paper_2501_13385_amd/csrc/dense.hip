@@ -347,6 +347,17 @@ __device__ __forceinline__ void reduce_sym_partials(const double *part, int nb, 
   __syncthreads();
 }
 
+// Breakdown rule of the truncation at a cut.  The kept singular vectors come
+// from the eigen-decomposition of S = M^T M, M the unfolding being truncated,
+// so the eigenvalues carry rounding of about eps * w[0] and the new core
+// M Z_r Sigma_r^{-1} departs from orthonormality by about
+// eps * (sigma_1 / sigma_r)^2.  A kept singular value below 1e-6 of the
+// largest (eigenvalue ratio 1e-12, orthonormality defect up to ~2e-4) stops
+// the solve with PRGD_EBREAKDOWN rather than continuing on inaccurate cores.
+// An SVD of M itself (Algorithm 1 as written) resolves ratios down to ~1e-15;
+// this limit belongs to the Gram form only.
+constexpr double TRUNC_MIN_EIG_RATIO = 1e-12;
+
 __device__ __forceinline__ void left_cut(const Dev &d, int i, double *smem);
 
 __device__ void gram_first_cut(const Dev &d, int lb) {
@@ -630,7 +641,7 @@ __device__ __forceinline__ void left_cut(const Dev &d, int i, double *smem) {
   block_jacobi_eig(S, rk, V, w, T1, Vs);  // T1 is free once S is formed
   if (threadIdx.x == 0) {
     const double s0 = w[0];
-    if (!(w[ri - 1] > 1e-28 * s0) || !isfinite(s0)) bad = 1;
+    if (!(w[ri - 1] > TRUNC_MIN_EIG_RATIO * s0) || !isfinite(s0)) bad = 1;
   }
   __syncthreads();
   if (bad) {

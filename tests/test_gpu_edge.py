@@ -171,3 +171,61 @@ def test_timed_and_profiled_iterations_match_plain_ones(L):
             s.close()
     for mode in ("timed", "timed3", "profiled"):
         assert rel_dist(outs[mode], outs["plain"]) <= 1e-13, mode
+
+
+def _min_kept_ratio(cores, ranks):
+    """Smallest sigma_{r_k} / sigma_1 over the cuts k of the dense tensor."""
+    full = tt.tt_full(cores)
+    shape = full.shape
+    worst = 1.0
+    for k in range(1, len(shape)):
+        sv = np.linalg.svd(full.reshape(int(np.prod(shape[:k])), -1), compute_uv=False)
+        worst = min(worst, sv[ranks[k] - 1] / sv[0])
+    return worst
+
+
+def test_solver_rank_above_truth_rank_matches_or_reports_breakdown(L):
+    """Noiseless, fully observed truth of TT rank (1,2,2,1) solved on the
+    rank-(1,3,3,1) manifold: the third singular value of the iterates decays
+    towards zero (about 20x every three iterations).
+    While it is resolvable the device follows the reference (tensor difference
+    within 1e-10 plus the truncation's rounding, about 1e-15 sigma_1/sigma_3);
+    once sigma_3 / sigma_1 falls below the device's truncation limit (1e-6,
+    the Gram form's resolution) the device stops with PRGD_EBREAKDOWN, and it
+    must not stop while the ratio is still above 1e-5."""
+    shape, tranks, ranks = [8, 9, 7], [1, 2, 2, 1], [1, 3, 3, 1]
+    rng = wl.make_rng(50)
+    truth = wl.gaussian_cores(shape, tranks, rng)
+    extra = wl.gaussian_cores(shape, [1, 1, 1, 1], rng)
+    extra[0] = extra[0] * 0.05
+    init = tt.tt_add(truth, extra)
+    init = [c + 0.02 * rng.standard_normal(c.shape) for c in init]
+    idx = wl.sample_indices(shape, 504, rng)      # every entry: sigma_3 decays geometrically
+    y = tt.tt_eval(truth, idx)
+    pol = prgd.Policy(step_rule="theory", c=0.8)
+    s = L.Solver(shape, ranks, idx, y, init, step=0.8, stop_rule="none", max_iter=200)
+    ref = [c.copy() for c in init]
+    broke_at = None
+    ratios = []
+    try:
+        for it in range(200):
+            ratio_before = _min_kept_ratio(ref, ranks)
+            ref_next, _ = prgd.prgd_step(ref, idx, y, pol, ranks)
+            ratio_after = _min_kept_ratio(ref_next, ranks)
+            s.iterate(1)
+            rep = s.report()
+            if rep["status"] == L.EBREAKDOWN:
+                broke_at = (it, ratio_before, ratio_after)
+                assert min(ratio_before, ratio_after) < 1e-5, broke_at
+                break
+            got = s.cores()
+            d = rel_dist(got, ref_next)
+            ratios.append(ratio_after)
+            assert d <= 1e-10 + 1e-15 / max(ratio_after, 1e-300), (it, d, ratio_after)
+            ref = ref_next
+            if ratio_after < 1e-8:
+                break
+    finally:
+        s.close()
+    print("ratios", ratios[::10], "breakdown", broke_at, flush=True)
+    assert broke_at is not None, "sigma_3 / sigma_1 reached 1e-8 without a reported breakdown"

@@ -309,3 +309,37 @@ def test_mode_pass_forms_mixed(L, mi):
     assert abs(rsq - float(r @ r)) <= 1e-4 * float(r @ r)
     for k in range(pb.order):
         assert np.linalg.norm(grads[k] - ref_g[k]) <= 1e-4 * np.linalg.norm(ref_g[k]), k
+
+
+@pytest.mark.parametrize("name,c,iters", [("c1", 1.0, 12), ("c2_small", 0.8, 10), ("ragged", 0.8, 8)])
+def test_constant_step_with_fixed_eps_matches_reference(L, name, c, iters):
+    """The constant step of section 3.2.2 ("PRGD-const" of section 5.1): a fixed
+    alpha with a fixed eps in the metric G_{l,i} = eps I + diag(M_i M_i^T).  The
+    values are those the theory step would take at T_0 (eps_0, c sqrt(eps_0) / p)
+    and then stay fixed.  Every iterate within 1e-10 of the reference; the
+    recorded eps and alpha equal the fixed ones."""
+    pb = make_case(name)
+    say("case", name, "const")
+    y = observed(pb)
+    r0 = prgd.residual(pb.init, pb.indices, y)
+    eps0 = prgd.eps_vee(prgd.slice_norms(pb.indices, r0, pb.shape))
+    alpha = prgd.step_theory(c, eps0, prgd.sampling_ratio(pb.n_obs, pb.shape))
+    pol = prgd.Policy(step_rule="const", alpha=alpha, eps=eps0)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y, pb.init, step=alpha, step_policy="const", eps_fixed=eps0,
+                 stop_rule="none", max_iter=iters)
+    ref = [x.copy() for x in pb.init]
+    try:
+        for it in range(iters):
+            s.iterate(1)
+            got = s.cores()
+            ref, info = prgd.prgd_step(ref, pb.indices, y, pol, pb.ranks)
+            assert info["alpha"] == alpha and info["eps"] == eps0
+            d = rel_dist(got, ref)
+            assert d <= 1e-10, (it, d)
+        hist = s.history()
+    finally:
+        s.close()
+    assert len(hist) >= iters
+    for h in hist[:iters]:
+        assert abs(h["alpha"] - alpha) <= 1e-12 * alpha, h
+        assert abs(h["eps"] - eps0) <= 1e-12 * eps0, h

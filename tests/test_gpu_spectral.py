@@ -130,3 +130,39 @@ def test_order14_workload_properties(L):
         ell = np.einsum("ja,ajb->jb", ell, got[k][:, pb.indices[k, sel], :])
     want = (z[sel, None] * ell).sum(axis=0)
     assert np.allclose(got[-1][:, 1, 0], want, rtol=1e-9, atol=1e-9 * np.abs(want).max())
+
+
+def _two_scale_tensor(ratio, seed):
+    """Fully observed 6 x 5 x 7 tensor of TT rank (1, 2, 2, 1) whose second
+    component is `ratio` times smaller than the first."""
+    shape, ranks = [6, 5, 7], [1, 2, 2, 1]
+    rng = wl.make_rng(seed)
+    big = wl.gaussian_cores(shape, [1, 1, 1, 1], rng)
+    small = wl.gaussian_cores(shape, [1, 1, 1, 1], rng)
+    small[0] = small[0] * ratio
+    truth = tt.tt_add(big, small)
+    full = np.array(np.unravel_index(np.arange(int(np.prod(shape))), shape)).astype(np.int32)
+    return shape, ranks, truth, full, tt.tt_eval(truth, full), rng
+
+
+def test_moderately_small_singular_value_agrees_with_reference(L):
+    shape, ranks, truth, full, y, rng = _two_scale_tensor(1e-4, 28)
+    g = wl.sketch_gaussians(shape, 5, rng)
+    got = L.prgd_spectral_init(shape, ranks, full, y, g, 5)
+    ref = prgd.spectral_init_sketch(full, y, shape, ranks, g)
+    assert rel(got, ref) <= 1e-10
+    assert rel(got, truth) <= 1e-10
+
+
+def test_device_refuses_sketches_below_its_gram_resolution(L):
+    """Device limit, not a property of Algorithm 1: the device takes the singular
+    vectors of a sketch from its Gram matrix, whose eigenvalues resolve singular
+    value ratios only down to about 1e-7, so it reports PRGD_EBREAKDOWN there.
+    The reference (plain SVD) still returns the cores in that band."""
+    shape, ranks, truth, full, y, rng = _two_scale_tensor(1e-10, 29)
+    g = wl.sketch_gaussians(shape, 5, rng)
+    ref = prgd.spectral_init_sketch(full, y, shape, ranks, g)
+    assert rel(ref, truth) <= 1e-12
+    with pytest.raises(L.PrgdError) as e:
+        L.prgd_spectral_init(shape, ranks, full, y, g, 5)
+    assert e.value.status == L.EBREAKDOWN

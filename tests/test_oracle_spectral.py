@@ -101,3 +101,25 @@ def test_too_few_samples_is_reported():
     idx = wl.sample_indices(shape, 2, rng)       # sketch of rank <= 2 < r_1
     with pytest.raises(ValueError):
         prgd.spectral_init_sketch(idx, np.ones(2), shape, ranks, wl.sketch_gaussians(shape, 5, rng))
+
+
+def test_small_but_resolvable_singular_values_are_kept():
+    """Algorithm 1 keeps the top r singular vectors whatever their scale; only a
+    rank that float64 cannot resolve is refused.  A fully observed tensor whose
+    r-th sketch singular value is about 1e-10 of the largest (far below the
+    square root of machine precision, far above its rounding level) is still
+    reproduced."""
+    from oracle import tt as _tt
+    shape, ranks = [6, 5, 7], [1, 2, 2, 1]
+    rng = wl.make_rng(16)
+    big = wl.gaussian_cores(shape, [1, 1, 1, 1], rng)
+    small = wl.gaussian_cores(shape, [1, 1, 1, 1], rng)
+    small[0] = small[0] * 1e-10
+    truth = _tt.tt_add(big, small)                 # TT rank (1, 2, 2, 1), sigma_2 / sigma_1 ~ 1e-10
+    full = np.array(np.unravel_index(np.arange(int(np.prod(shape))), shape)).astype(np.int32)
+    y = _tt.tt_eval(truth, full)
+    got = prgd.spectral_init_sketch(full, y, shape, ranks, wl.sketch_gaussians(shape, 5, rng))
+    assert rel(got, truth) <= 1e-12
+    # the small component itself is recovered, not only the dominant one
+    diff = _tt.tt_add(got, big, -1.0)
+    assert _tt.tt_dist(diff, small) <= 1e-4 * _tt.tt_norm(small)
