@@ -1,23 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the PRGD hot path on one MI355X.
 
-Workload: order 3, n = 400 per mode, TT ranks (1,10,10,1), Gaussian-core
-ground truth with unit expected Frobenius norm, |Omega| = 640,000 (1%) drawn
-uniformly without replacement, additive Gaussian noise 1e-3 x RMS entry,
-int32 indices, float64 (plain) / float32 (mixed) values.  Synthetic and
-seeded; the starting point is the truth with every core perturbed by 10% of
-its RMS (a rank-preserving perturbation).
+Headline workload: order 14, n = 4 per mode, TT ranks min(8, 4^k, 4^{14-k})
+(an MPS-shaped tensor), Gaussian cores N(0, 1/r_k), |Omega| = 2,000,000
+distinct entries drawn uniformly, noiseless, float64.  Every iteration of a
+solve from its start to relative error 1e-6 against the ground truth is timed.
 
 A step is one full PRGD iteration on the device: sampled pass (evaluation,
 residual, slice sums, gradient scatter), metric-weighted Grams, tangent
-components, TT-SVD retraction, stopping-test reductions.  The observation
-set and cores are resident in HBM before the timed region.
+components, TT-SVD retraction, stopping-test reductions.  The observation set
+and cores are resident in HBM before the timed region.  The iteration count to
+tolerance l* comes from a first run with the truth cores; the timed run then
+performs exactly l* iterations (or --steps) without any truth tracking.
 
-The serving leg runs a stream of independent requests through the request
-server (orders {3,4,5,8}, n in [20,300], ranks {2,4,8,16}, sampling ratio in
-[0.5%, 10%], Gaussian-core truths, each solved to relative error 1e-6):
-closed-loop solves/s per precision, then Poisson arrivals at 0.7x the
-measured capacity for p50/p99 latency.
+Also measured: the same workload with the float32 sampled pass (mixed); the
+n = 400 order-3 noisy workload, the 256 x 256 x 128 smooth-core workload and the
+order-4 noiseless workload, each in both precisions; the sketched spectral
+initialisation; the request server on a stream of independent problems; and the
+float64 reference implementation on the host cores.
 
 Prints one JSON line.  --gpus above 1 is not supported (one-GPU build).
 """
@@ -25,8 +25,8 @@ Prints one JSON line.  --gpus above 1 is not supported (one-GPU build).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -38,15 +38,34 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-import hashlib  # noqa: E402
-
 METRIC = "|Ω|·iterations/s, time to 1e-6 rel. error; served solves/s + p99 latency"
-WORKLOAD = "c2"
-# MI355X peaks (published): HBM 8 TB/s; FP64 vector 78.6 TFLOP/s.  Non-packed FP32
-# vector issue has the same rate as FP64 (packed FP32 is disabled in this build):
-# 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.
+HEADLINE = "c4"
+# MI355X peaks (published): HBM 8 TB/s; FP64 vector and FP64 MFMA 78.6 TFLOP/s.
+# Non-packed FP32 vector issue has the same rate as FP64 (packed FP32 is disabled
+# in this build): 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s.
 PEAK_ALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
+
+# How each workload is solved.  start: "spectral" = the device's sketched
+# spectral initialisation of P_Omega(y)/p, "perturbed" = truth cores with 10%
+# RMS noise per core (the sketched initialisation does not reach the basin of
+# convergence on the order-14 and smooth-core workloads).  rule/tol: the
+# stopping rule that defines "to tolerance"; the noisy workload floors near
+# 3e-4 relative error, so its clock is relative change <= 1e-6.  The smooth-core
+# cube is ill-conditioned: the theory step diverges on it for every constant
+# tried (0.4 .. 1.001), the adaptive step converges.
+LEGS = {
+    "c4": dict(start="perturbed", rule="error", tol=1e-6, policy="theory", c=1.001, max_iter=500,
+               desc="order-14 TT completion, n=4, TT ranks min(8,4^k,4^(14-k)), |Omega|=2,000,000 "
+                    "(0.745%), noiseless, int32 indices"),
+    "c2": dict(start="spectral", rule="change", tol=1e-6, policy="theory", c=0.9, max_iter=500,
+               desc="order-3 TT completion, n=400, TT ranks (1,10,10,1), |Omega|=640,000 (1%), "
+                    "noise 1e-3 RMS, int32 indices"),
+    "c3": dict(start="perturbed", rule="error", tol=1e-6, policy="adaptive", c=1.0, max_iter=1500,
+               desc="256x256x128 smooth-core cube, TT ranks (1,16,16,1), 5% observed, noiseless"),
+    "c1": dict(start="spectral", rule="residual", tol=1e-10, policy="theory", c=1.001, max_iter=500,
+               desc="order-4 TT completion, n=10, TT ranks (1,2,2,2,1), 3,000 of 10^4 entries, noiseless"),
+}
 
 
 def log(*a):
@@ -67,61 +86,108 @@ def sampled_pass_bytes(shape, n_obs, val_bytes):
     return float(n_obs) * (4 * len(shape) + val_bytes)
 
 
-def gpu_leg(pb, L, precision, steps, warmup, timed_only=False):
-    vals = L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices) + pb.noise_std * pb.noise
+def observations(pb, L):
+    return L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices) + pb.noise_std * pb.noise
+
+
+def spectral_start(pb, L, vals):
+    from paper_2501_13385_amd import workloads as wl
+    sk = max(pb.ranks) + 4
+    gauss = np.concatenate([a.ravel() for a in wl.sketch_gaussians(pb.shape, sk, wl.make_rng(1))])
+    L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, vals, gauss, sk)     # warm-up
+    t0 = time.perf_counter()
+    init = L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, vals, gauss, sk)
+    return init, time.perf_counter() - t0, sk
+
+
+def solve_leg(pb, L, precision, steps, warmup, cfg, init, phases=True):
+    """l* with the truth cores, then exactly K = steps (default l*) timed iterations of a
+    fresh solve from the same start, without truth tracking."""
+    vals = observations(pb, L)
     vals = vals.astype(np.float64 if precision == "fp64" else np.float32)
-    step_c = pb.step
+    kw = dict(precision=precision, step_policy=cfg["policy"], step=cfg["c"])
     out = {}
-    t_setup = time.perf_counter()
-    prof_steps = max(1, min(steps, 20))
-    s = L.Solver(pb.shape, pb.ranks, pb.indices, vals, pb.init, precision=precision, step=step_c,
-                 stop_rule="none", max_iter=warmup + steps + prof_steps + 1)
-    out["setup_s"] = time.perf_counter() - t_setup
+    # 1. iterations to tolerance (the error rule needs the truth cores)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, vals, init, truth_cores=pb.truth, stop_rule=cfg["rule"],
+                 tol=cfg["tol"], max_iter=cfg["max_iter"], **kw)
     try:
-        s.iterate(warmup)
-        s.sync()
-        t0 = time.perf_counter()
-        # the main sampled kernel of every K1_STRIDE-th iteration is bracketed
-        # by events (each recorded event idles the device for a few us)
-        k1_ms, dev_ms = s.iterate_timed(steps, K1_STRIDE)  # waits for the stream
-        t1 = time.perf_counter()
-        # per-phase split from a short separate pass (seven events per
-        # iteration would slow the timed loop itself)
-        phases = s.iterate_profiled(prof_steps)
-        rep = s.report()
-    finally:
-        s.close()
-    if rep["iterations"] != warmup + steps + prof_steps:
-        raise RuntimeError(f"expected {warmup + steps + prof_steps} completed iterations, got {rep['iterations']}")
-    wall = t1 - t0
-    out["seconds"] = wall
-    out["device_seconds"] = dev_ms * 1e-3
-    out["ms_per_step"] = 1e3 * wall / steps
-    out["value"] = pb.n_obs * steps / wall
-    out["k1_ms_per_step"] = k1_ms
-    out["phase_ms_per_step"] = {k: v / prof_steps for k, v in phases.items()}
-    if timed_only:
-        return out
-    # time to tolerance (relative change <= 1e-6; the noise floor keeps the error
-    # against T* near 3e-4, so 1e-6 error is unreachable on this workload)
-    s = L.Solver(pb.shape, pb.ranks, pb.indices, vals, pb.init, precision=precision, step=step_c,
-                 stop_rule="change", tol=1e-6, max_iter=500)
-    try:
-        s.sync()
         r = s.run()
     finally:
         s.close()
-    out["time_to_tol_s"] = r["seconds"]
-    out["iters_to_tol"] = r["iterations"]
+    lstar = int(r["iterations"])
+    out["iters_to_tol"] = lstar
     out["converged"] = r["status"] == 0
-    s = L.Solver(pb.shape, pb.ranks, pb.indices, vals, pb.init, truth_cores=pb.truth, precision=precision,
-                 step=step_c, stop_rule="change", tol=1e-6, max_iter=500)
-    try:
-        r2 = s.run()
-    finally:
-        s.close()
-    out["rel_error_at_tol"] = r2["rel_error"]
+    out["rel_error_at_tol"] = r["rel_error"]
+    out["rel_residual_at_tol"] = r["rel_residual"]
+    K = steps if steps > 0 else max(1, lstar)
+    # 2. warm-up on a separate solve of the same problem
+    if warmup > 0:
+        s = L.Solver(pb.shape, pb.ranks, pb.indices, vals, init, stop_rule="none", max_iter=warmup, **kw)
+        try:
+            s.iterate(warmup)
+            s.sync()
+        finally:
+            s.close()
+
+    def timed(iters):
+        t_setup = time.perf_counter()
+        s = L.Solver(pb.shape, pb.ranks, pb.indices, vals, init, stop_rule="none", max_iter=iters, **kw)
+        setup = time.perf_counter() - t_setup
+        try:
+            s.sync()
+            t0 = time.perf_counter()
+            k1_ms, dev_ms = s.iterate_timed(iters, K1_STRIDE)   # waits for the stream
+            t1 = time.perf_counter()
+            rep = s.report()
+        finally:
+            s.close()
+        if rep["iterations"] != iters:
+            raise RuntimeError(f"expected {iters} completed iterations, got {rep['iterations']}")
+        return t1 - t0, k1_ms, dev_ms, setup
+
+    # 3. the timed window
+    wall, k1_ms, dev_ms, setup = timed(K)
+    out["steps"] = K
+    out["setup_s"] = setup
+    out["seconds"] = wall
+    out["ms_per_step"] = 1e3 * wall / K
+    out["device_ms_per_step"] = dev_ms / K
+    out["value"] = pb.n_obs * K / wall
+    out["k1_ms"] = k1_ms
+    out["k1_launches_timed"] = -(-K // K1_STRIDE)
+    out["time_to_tol_s"] = wall if K == lstar else timed(max(1, lstar))[0]
+    if phases:
+        # per-phase split from a short separate pass (seven events per iteration
+        # would slow the timed loop itself)
+        np_ = max(1, min(K, 20))
+        s = L.Solver(pb.shape, pb.ranks, pb.indices, vals, init, stop_rule="none", max_iter=np_, **kw)
+        try:
+            ph = s.iterate_profiled(np_)
+        finally:
+            s.close()
+        out["phase_ms_per_step"] = {k: v / np_ for k, v in ph.items()}
     return out
+
+
+def workload_legs(name, L, precisions, steps, warmup, phases=True):
+    from paper_2501_13385_amd import workloads as wl
+    cfg = LEGS[name]
+    pb = wl.named(name, seed=0)
+    log(f"workload {name}: shape {pb.shape} ranks {pb.ranks} |Omega| {pb.n_obs} start {cfg['start']}")
+    res = {"start": cfg["start"], "stop": f"{cfg['rule']} <= {cfg['tol']:g}", "step": f"{cfg['policy']} c={cfg['c']}"}
+    if cfg["start"] == "spectral":
+        init, t_init, sk = spectral_start(pb, L, observations(pb, L))
+        res["spectral_init_s"] = t_init
+        res["spectral_init_sketch"] = sk
+    else:
+        init = pb.init
+    for prec in precisions:
+        log(f"  {name} {prec}")
+        res[prec] = solve_leg(pb, L, prec, steps, warmup, cfg, init, phases=phases)
+        r = res[prec]
+        log(f"    l*={r['iters_to_tol']} time_to_tol={r['time_to_tol_s']:.4g}s {r['ms_per_step']:.4f} ms/step "
+            f"value={r['value']:.4g} k1={r['k1_ms']:.4g} ms err={r['rel_error_at_tol']:.3g}")
+    return pb, res
 
 
 def serving_leg(L, n_req, max_obs, seed=0, max_iter=150, precisions=("fp64", "mixed")):
@@ -199,58 +265,79 @@ def copy_calibration(reps=5):
     print(json.dumps({"copy_bytes": COPY_BYTES, "reps": reps}), flush=True)
 
 
-def kernel_source_hash():
-    with open(os.path.join(ROOT, "paper_2501_13385_amd", "csrc", "sampled3.hip"), "rb") as f:
+# The main sampled kernel of each workload and the source file it is built from;
+# HBM traffic recorded under profiles/ is tied to that file's contents.
+MAIN_KERNEL = {
+    "c4": ("k_chain", "sampled_chain.hip"),
+    "c2": ("k_sampled3", "sampled3.hip"),
+}
+
+
+def kernel_source_hash(workload=HEADLINE):
+    src = MAIN_KERNEL[workload][1]
+    with open(os.path.join(ROOT, "paper_2501_13385_amd", "csrc", src), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(precision):
-    """HBM bytes per launch of the order-3 sampled kernel from the committed PMC summary,
-    or None when the kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_sampled3_c2.json")
+def traffic_path(workload=HEADLINE):
+    return os.path.join(ROOT, "profiles", f"traffic_{MAIN_KERNEL[workload][0]}_{workload}.json")
+
+
+def measured_traffic(precision, workload=HEADLINE):
+    """HBM bytes per launch of the workload's main sampled kernel from the committed
+    PMC summary, or None when the kernel source changed since the counters were taken."""
     try:
-        with open(path) as f:
+        with open(traffic_path(workload)) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256_16") != kernel_source_hash():
+    if rec.get("source_sha256_16") != kernel_source_hash(workload):
         return None
     leg = rec.get(precision)
     return None if leg is None else leg.get("bytes_per_launch")
 
 
-def cpu_baseline(pb, iters):
-    """The reference implementation, as it stands, on the host cores (one BLAS thread)."""
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(pb, name, n_sample, threads):
+    """The reference implementation, as it stands, on the host cores: one PRGD
+    iteration of the workload restricted to its first n_sample observations."""
     from threadpoolctl import threadpool_limits
 
     from oracle import prgd, tt
 
-    y = tt.tt_eval(pb.truth, pb.indices) + pb.noise_std * pb.noise
-    pol = prgd.Policy(step_rule="theory", c=pb.step)
+    idx = np.ascontiguousarray(pb.indices[:, :n_sample])
+    y = tt.tt_eval(pb.truth, idx) + pb.noise_std * pb.noise[:n_sample]
+    pol = prgd.Policy(step_rule="theory", c=LEGS[name]["c"])
     cores = [c.copy() for c in pb.init]
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         t0 = time.perf_counter()
-        for _ in range(iters):
-            cores, _ = prgd.prgd_step(cores, pb.indices, y, pol, pb.ranks)
+        prgd.prgd_step(cores, idx, y, pol, pb.ranks)
         t1 = time.perf_counter()
-    return {"value": pb.n_obs * iters / (t1 - t0), "unit": "samples*iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{iters} PRGD iterations of the same workload (full |Omega| = {pb.n_obs}) from the same start, "
-                      f"float64 numpy, {t1 - t0:.1f} s"}
+    return {"value": n_sample / (t1 - t0), "unit": "samples*iterations/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 PRGD iteration of the {name} workload restricted to its first {n_sample} of "
+                      f"{pb.n_obs} observations (same start), float64 numpy, {t1 - t0:.1f} s"}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=0, help="timed iterations (0: the iterations to tolerance)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workloads", default="c4,c2,c3,c1", help="comma list; the first is the headline")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000, help="observations in the CPU baseline's sample")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-max-obs", type=int, default=1 << 19)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--profile-only", action="store_true",
-                    help="run only the timed iterations (for kernel profilers); prints the phase times")
+                    help="run only the headline's timed iterations (for kernel profilers)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -262,77 +349,76 @@ def main():
         sys.exit(2)
 
     from paper_2501_13385_amd import _lib as L
-    from paper_2501_13385_amd import workloads as wl
 
     L.load()
-    pb = wl.named(WORKLOAD, seed=0)
-    pb.step = 0.9
-    log(f"workload {pb.name}: shape {pb.shape} ranks {pb.ranks} |Omega| {pb.n_obs}")
-    res = {}
-    for prec in (["fp64", "mixed"] if args.only == "both" else [args.only]):
-        log(f"gpu leg {prec}: warmup {args.warmup}, steps {args.steps}")
-        res[prec] = gpu_leg(pb, L, prec, args.steps, args.warmup, timed_only=args.profile_only)
-        log(f"  {prec}: {res[prec]['value']:.4g} samples*it/s, {res[prec]['ms_per_step']:.4f} ms/step, "
-            f"phases {res[prec]['phase_ms_per_step']}")
+    names = [w for w in args.workloads.split(",") if w]
+    head_name = names[0]
+    precs = ["fp64", "mixed"] if args.only == "both" else [args.only]
     if args.profile_only:
-        print(json.dumps({p: r["phase_ms_per_step"] for p, r in res.items()}), flush=True)
+        pb, res = workload_legs(head_name, L, precs, args.steps, args.warmup, phases=False)
+        print(json.dumps({p: {k: res[p][k] for k in ("ms_per_step", "k1_ms", "steps")} for p in precs}), flush=True)
         return
-    head = "fp64" if "fp64" in res else "mixed"
-    h = res[head]
+    pb, head = workload_legs(head_name, L, precs, args.steps, args.warmup)
+    hp = "fp64" if "fp64" in head else "mixed"
+    h = head[hp]
     flops = sampled_pass_flops(pb.shape, pb.ranks, pb.n_obs)
-    t_k1 = h["k1_ms_per_step"] * 1e-3
-    roof = {"kernel": "sampled pass, main kernel (k_sampled3)", "bound": "alu",
+    t_k1 = h["k1_ms"] * 1e-3
+    kname = MAIN_KERNEL.get(head_name, ("sampled pass",))[0]
+    roof = {"kernel": f"sampled pass, main kernel ({kname})", "bound": "alu",
             "achieved": flops / t_k1 / 1e12, "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": flops / t_k1 / 1e12 / PEAK_ALU_TFLOPS, "traffic": measured_traffic(head),
-            "hbm_GBs": sampled_pass_bytes(pb.shape, pb.n_obs, 8 if head == "fp64" else 4) / t_k1 / 1e9,
+            "frac": flops / t_k1 / 1e12 / PEAK_ALU_TFLOPS,
+            "traffic": measured_traffic(hp, head_name) if head_name in MAIN_KERNEL else None,
+            "hbm_GBs": sampled_pass_bytes(pb.shape, pb.n_obs, 8 if hp == "fp64" else 4) / t_k1 / 1e9,
             "flops_per_launch": flops, "avg_launch_us": 1e6 * t_k1,
-            "launches_timed": -(-args.steps // K1_STRIDE), "timed_every": K1_STRIDE}
+            "launches_timed": h["k1_launches_timed"], "timed_every": K1_STRIDE}
     line = {
         "metric": METRIC,
         "value": h["value"],
         "unit": "samples*iterations/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": h["steps"],
         "warmup": args.warmup,
         "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "dtype": "f64" if hp == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "order-3 TT completion, n=400, TT ranks (1,10,10,1), |Omega|=640000 (1%), "
-                               "noise 1e-3 RMS, int32 indices",
-                   "global_batch": pb.n_obs, "precision": head, "step_constant": pb.step},
-        "setup_s": h["setup_s"],
+        "config": {"workload": LEGS[head_name]["desc"], "global_batch": pb.n_obs, "precision": hp,
+                   "start": head["start"], "stop": head["stop"], "step": head["step"]},
         "time_to_tol_s": h["time_to_tol_s"],
         "iters_to_tol": h["iters_to_tol"],
-        "tol_rule": "relative change <= 1e-6",
         "rel_error_at_tol": h["rel_error_at_tol"],
-        "device_ms_per_step": 1e3 * h["device_seconds"] / args.steps,
+        "converged": h["converged"],
+        "setup_s": h["setup_s"],
+        "device_ms_per_step": h["device_ms_per_step"],
         "phase_ms_per_step": h["phase_ms_per_step"],
         "roofline": roof,
     }
-    if "mixed" in res and head != "mixed":
-        m = res["mixed"]
-        line["mixed"] = {"value": m["value"], "ms_per_step": m["ms_per_step"], "time_to_tol_s": m["time_to_tol_s"],
-                         "iters_to_tol": m["iters_to_tol"], "rel_error_at_tol": m["rel_error_at_tol"],
-                         "k1_ms_per_step": m["k1_ms_per_step"],
-                         "phase_ms_per_step": m["phase_ms_per_step"], "dtype": "f32+f64"}
-    # sketched spectral initialisation of the same workload (host inputs, the
-    # call includes the host-to-device copies and the per-mode sorts)
-    vals = L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices) + pb.noise_std * pb.noise
-    sk = max(pb.ranks) + 4
-    gauss = np.concatenate([a.ravel() for a in wl.sketch_gaussians(pb.shape, sk, wl.make_rng(1))])
-    L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, vals, gauss, sk)     # warm-up
-    t0 = time.perf_counter()
-    L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, vals, gauss, sk)
-    line["spectral_init_s"] = time.perf_counter() - t0
-    line["spectral_init_sketch"] = sk
+    if "mixed" in head and hp != "mixed":
+        m = head["mixed"]
+        line["mixed"] = {k: m[k] for k in ("value", "ms_per_step", "time_to_tol_s", "iters_to_tol",
+                                           "rel_error_at_tol", "converged", "k1_ms", "phase_ms_per_step")}
+        line["mixed"]["dtype"] = "f32+f64"
+    others = {}
+    for w in names[1:]:
+        try:
+            _, res = workload_legs(w, L, precs, 0, args.warmup)
+        except Exception as e:   # one workload's failure is reported, not fatal to the line
+            log(f"workload {w} failed: {e}")
+            res = {"error": str(e)}
+        res["workload"] = LEGS[w]["desc"]
+        others[w] = res
+    line["workloads"] = others
     if not args.no_serving:
         line["serving"] = serving_leg(L, args.serve_requests, args.serve_max_obs)
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: {args.cpu_iters} reference iterations")
-        line["cpu_baseline"] = cpu_baseline(pb, args.cpu_iters)
+        n_s = min(args.cpu_sample, pb.n_obs)
+        nc = host_cores()
+        log(f"cpu baseline: one reference iteration on {n_s} observations, {nc} threads")
+        line["cpu_baseline"] = cpu_baseline(pb, head_name, n_s, nc)
+        log(f"cpu baseline: one thread, {n_s // 4} observations")
+        line["cpu_baseline_1thread"] = cpu_baseline(pb, head_name, n_s // 4, 1)
     print(json.dumps(line), flush=True)
 
 

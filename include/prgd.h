@@ -66,6 +66,13 @@ typedef int32_t prgd_status;
                                 float64 (LDS), and ||R||^2, always summed in float64.
                                 Grams, factorisations, retraction, stopping test in
                                 float64                                                     */
+#define PRGD_PREC_MIXED_BF16 2 /* as PRGD_PREC_MIXED, and the tangent components
+                                (the three R x R slice products of Lemma 3's projection,
+                                X = omega^{-1} GL^{-1} Y H^{-1} - T Psi) on bfloat16
+                                matrix-core operations with float32 accumulation; every
+                                operand scaled by a power of two (per core for GL^{-1},
+                                H^{-1}, Psi; per slice for Y, T and GL^{-1} Y) so that it
+                                sits near unit size                                         */
 /* step policy (section 3.2.2 and Theorem 1) */
 #define PRGD_STEP_THEORY 0   /* alpha_l = step * eps_l^{1/2} / p, p = N / (n_1...n_m);
                                 Theorem 1 uses step = 1.001                                 */
@@ -122,7 +129,21 @@ typedef struct {
                                   and ranks <= 8 with |Omega| >= 65536 when the stored
                                   interfaces take at most 8 GiB).  Results agree to
                                   rounding either way.                                      */
+  int32_t pass_kind;           /* sampled pass for orders >= 4 (section 2.1 evaluation,
+                                  section 3.2.1 slice norms, the gradient of f):
+                                  PRGD_PASS_AUTO = the one-pass chain kernel when every
+                                  core from some split on has n_k <= (16/R)^2 (R the
+                                  rank padded to 2, 4 or 8; n_k <= 16 at R = 2) and the
+                                  modes before the split leave >= 1024 samples per
+                                  prefix, else the choice above; PRGD_PASS_CHAIN
+                                  requires the chain kernel (PRGD_ENOTSUP if it does not
+                                  apply); PRGD_PASS_MODES never uses it                     */
 } prgd_desc;
+
+/* pass_kind */
+#define PRGD_PASS_AUTO  0
+#define PRGD_PASS_CHAIN 1
+#define PRGD_PASS_MODES 2
 
 /* One row of the per-iteration record kept on the device. */
 typedef struct {

@@ -19,10 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libprgd.so")
 
 OK, NOT_CONVERGED, PENDING = 0, 1, 2
 EINVAL, EDUPLICATE, ENOMEM, EDEVICE, EBREAKDOWN, ESTATE, ENOTSUP = -1, -2, -3, -4, -5, -6, -7
-PREC = {"fp64": 0, "mixed": 1}
+PREC = {"fp64": 0, "mixed": 1, "mixed_bf16": 2}
 STEP = {"theory": 0, "const": 1, "adaptive": 2}
 METRIC = {"data": 0, "euclidean": 1}
 STOP = {"residual": 0, "change": 1, "error": 2, "none": 3}
+PASS = {"auto": 0, "chain": 1, "modes": 2}
 
 
 class PrgdError(RuntimeError):
@@ -54,6 +55,7 @@ class prgd_desc(C.Structure):
         ("stream", C.c_void_p),
         ("metric", C.c_int32),
         ("mode_interfaces", C.c_int32),
+        ("pass_kind", C.c_int32),
     ]
 
 
@@ -146,7 +148,8 @@ def exported_symbols() -> List[str]:
     return [n for n in ("prgd_cores_numel", "prgd_create", "prgd_iterate", "prgd_iterate_profiled", "prgd_iterate_timed",
                         "prgd_sync", "prgd_run",
                         "prgd_get_report", "prgd_get_cores", "prgd_get_history", "prgd_sampled_pass",
-                        "prgd_eval", "prgd_spectral_init", "prgd_destroy", "prgd_status_str", "prgd_last_error",
+                        "prgd_eval", "prgd_spectral_init", "prgd_destroy", "prgd_status_str",
+                        "prgd_last_error",
                         "prgd_server_create", "prgd_server_submit", "prgd_server_poll", "prgd_server_wait",
                         "prgd_server_stats", "prgd_server_destroy")]
 
@@ -198,7 +201,8 @@ def _ptr_of(a):
 
 def _make_desc(shape, ranks, indices, values, init_cores, *, truth_cores=None, precision="fp64",
                step_policy="theory", step=1.0, eps_fixed=0.0, stop_rule="residual", tol=1e-10,
-               max_iter=500, sort_mode=-1, stream=None, metric="data", mode_interfaces=0):
+               max_iter=500, sort_mode=-1, stream=None, metric="data", mode_interfaces=0,
+               pass_kind="auto"):
     """prgd_desc for the arguments, plus the objects that must outlive the call."""
     m = len(shape)
     keep = []
@@ -247,6 +251,7 @@ def _make_desc(shape, ranks, indices, values, init_cores, *, truth_cores=None, p
     d.stream = stream
     d.metric = METRIC[metric]
     d.mode_interfaces = int(mode_interfaces)
+    d.pass_kind = PASS[pass_kind]
     keep += [ns, rs]
     return d, keep
 

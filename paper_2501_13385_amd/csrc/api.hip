@@ -124,6 +124,37 @@ bool use_mode_passes(int m, const int *n, int R, int prec, long long N) {
   return false;
 }
 
+// One-pass chain kernel (orders >= 4, small mode sizes): the number u of
+// leading modes that are uniform within a chunk, or -1 when it does not apply.
+// Cores u..m-1 must fit one MFMA tile (n_k at most the kernel's slice range),
+// the prefixes must leave at least CHAIN_SEG_MIN samples each on average, and
+// the staged cores and per-wave slots must fit in LDS; the largest such u wins
+// (more of the chain shared per chunk).
+constexpr double CHAIN_SEG_MIN = 1024.0;
+int chain_plan(int m, const int *n, int R, int prec, long long N) {
+  if (m < 4 || (R != 2 && R != 4 && R != 8)) return -1;
+  const int nx = chain_nx(R);
+  int best = -1;
+  double span = 1.0;
+  for (int u = 0; u <= m - 2; ++u) {
+    if (u > 0) {
+      span *= (double)n[u - 1];
+      if (span > (double)(1 << 22) || (double)N / span < CHAIN_SEG_MIN) break;
+    }
+    bool fit = m - u <= 16;
+    for (int k = u; k < m && fit; ++k) fit = n[k] <= nx;
+    if (fit && chain_lds_bytes(m, u, n, R, prec) <= (size_t)159 * 1024) best = u;
+  }
+  return best;
+}
+
+// largest chunk of the chain kernel: 8 batches of 64 per wave of 4, fewer for
+// small Omega so that there are several hundred chunks
+long long chain_chunk_max(long long N) {
+  long long c = ((N / 512 + 63) / 64) * 64;
+  return std::max<long long>(64, std::min<long long>(2048, c));
+}
+
 // workgroups of one mode's pass
 long long mode_pass_wgs(long long N) { return std::min<long long>(1024, std::max<long long>(1, (N + 2047) / 2048)); }
 
@@ -229,12 +260,14 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
   if (N < 1 || N >= (1LL << 31)) return fail(PRGD_EINVAL, "n_obs must be in [1, 2^31)");
   if (!(ds->tol >= 0.0) || ds->max_iter < 0) return fail(PRGD_EINVAL, "tol must be >= 0 and max_iter >= 0");
   if (!(ds->step > 0.0) || !std::isfinite(ds->step)) return fail(PRGD_EINVAL, "step must be positive");
-  if (ds->precision != PRGD_PREC_FP64 && ds->precision != PRGD_PREC_MIXED) return fail(PRGD_EINVAL, "precision");
+  if (ds->precision != PRGD_PREC_FP64 && ds->precision != PRGD_PREC_MIXED && ds->precision != PRGD_PREC_MIXED_BF16)
+    return fail(PRGD_EINVAL, "precision");
   if (ds->step_policy != PRGD_STEP_THEORY && ds->step_policy != PRGD_STEP_CONST &&
       ds->step_policy != PRGD_STEP_ADAPTIVE)
     return fail(PRGD_EINVAL, "step_policy");
   if (ds->metric != PRGD_METRIC_DATA && ds->metric != PRGD_METRIC_EUCLIDEAN) return fail(PRGD_EINVAL, "metric");
   if (ds->mode_interfaces < -1 || ds->mode_interfaces > 1) return fail(PRGD_EINVAL, "mode_interfaces must be -1, 0 or 1");
+  if (ds->pass_kind < PRGD_PASS_AUTO || ds->pass_kind > PRGD_PASS_MODES) return fail(PRGD_EINVAL, "pass_kind");
   if (ds->step_policy == PRGD_STEP_CONST && ds->metric == PRGD_METRIC_DATA && !(ds->eps_fixed > 0.0))
     return fail(PRGD_EINVAL, "the constant step policy needs eps_fixed > 0");
   if (ds->stop_rule < PRGD_STOP_RESIDUAL || ds->stop_rule > PRGD_STOP_NONE) return fail(PRGD_EINVAL, "stop_rule");
@@ -271,6 +304,7 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
 
 hipError_t sampled_pass(prgd_solver s, int diag, hipEvent_t after_main = nullptr) {
   if (s->d.use3) return launch_sampled3(s->batch(), diag, s->stream, after_main);
+  if (s->d.use_chain) return launch_sampled_chain(s->batch(), diag, s->stream, after_main);
   if (s->d.use_modes) return launch_sampled_modes(s->batch(), diag, s->stream, after_main);
   return launch_sampled(s->batch(), diag, s->stream, after_main);
 }
@@ -305,11 +339,14 @@ namespace prgd {
 prgd_status set_error(prgd_status st, const char *msg) { return fail(st, msg); }
 
 hipError_t enqueue_batch_iterations(const Batch &bt, int iters, hipStream_t s) {
-  const bool use3 = bt.host[0].use3 != 0, modes = bt.host[0].use_modes != 0;
+  const bool use3 = bt.host[0].use3 != 0, modes = bt.host[0].use_modes != 0, chain = bt.host[0].use_chain != 0;
   bool truth = false;
   for (int i = 0; i < bt.ns; ++i) truth = truth || bt.host[i].has_truth;
   for (int it = 0; it < iters; ++it) {
-    hipError_t e = use3 ? launch_sampled3(bt, 0, s) : (modes ? launch_sampled_modes(bt, 0, s) : launch_sampled(bt, 0, s));
+    hipError_t e = use3    ? launch_sampled3(bt, 0, s)
+                   : chain ? launch_sampled_chain(bt, 0, s)
+                   : modes ? launch_sampled_modes(bt, 0, s)
+                           : launch_sampled(bt, 0, s);
     if (e != hipSuccess) return e;
     if ((e = launch_dense_iteration(bt, s, 0)) != hipSuccess) return e;
     if (truth && (e = launch_truth_sweep(bt, s, 0)) != hipSuccess) return e;
@@ -332,7 +369,8 @@ int64_t solver_footprint(const prgd_desc *ds) {
     pn += (int64_t)ds->mode_sizes[k] * R * R;
     soff += ds->mode_sizes[k];
   }
-  const bool mixed = ds->precision == PRGD_PREC_MIXED;
+  const bool mixed = ds->precision != PRGD_PREC_FP64;
+  const int wprec = mixed ? PREC_MIXED : PREC_FP64;   // working precision of the sampled pass
   const int64_t f = mixed ? 4 : 8, vb = ds->values_fp64 ? 8 : 4;
   int64_t b = 0;
   b += 4 * m * N;                                     // grouped indices
@@ -349,16 +387,24 @@ int64_t solver_footprint(const prgd_desc *ds) {
     long long tot = 0;
     int nbs = 1;
     std::vector<int> nv(ds->mode_sizes, ds->mode_sizes + m);
-    if (sampled_block_size(m, R, ds->precision) > 0) {
-      if (use_mode_passes(m, nv.data(), R, ds->precision, N)) {
+    const int cu = (ds->pass_kind == PRGD_PASS_MODES || m == 3) ? -1 : chain_plan(m, nv.data(), R, wprec, N);
+    if (cu >= 0) {
+      long long span = 1;
+      for (int k = 0; k < cu; ++k) span *= nv[k];
+      const int64_t nch = span + N / 64 + 1;                        // chunks (upper bound)
+      b += nch * (chain_part_width(m, cu, R) * f + 16);             // partials, rsq, chunk table
+      b += ((nch + 31) / 32) * soff * (R * R + 1) * 8;              // first-stage sums
+      b += 8 * span + 12 * N;                                       // host-side segment scan, sort keys
+    } else if (sampled_block_size(m, R, wprec) > 0) {
+      if (use_mode_passes(m, nv.data(), R, wprec, N)) {
         const int64_t segw = (int64_t)R * R + 1, nwg = mode_pass_wgs(N);
         b += (int64_t)(m - 1) * (4 * m * N + f * N);      // sorted copies per mode
         for (int k = 0; k < m; ++k) b += nwg * (KSEG * segw * f + 4) + (int64_t)nv[k] * (segw * f + 8);
         b += 8 * nwg + (int64_t)m * (int64_t)sizeof(ModeTab) + 64 * 256 * 6 * m;
-        if (use_stored_interfaces(ds->mode_interfaces, m, R, ds->precision, N))
+        if (use_stored_interfaces(ds->mode_interfaces, m, R, wprec, N))
           b += (int64_t)m * N * ((2 * R + 1) * f + 4) + 12 * N;   // records, position maps, permutations
       } else {
-        sampled_plan(m, nv.data(), R, ds->precision, N, off, tot, nbs);
+        sampled_plan(m, nv.data(), R, wprec, N, off, tot, nbs);
         b += (int64_t)nbs * tot * f;
       }
     }
@@ -475,7 +521,8 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   Dev &d = s->d;
   d.m = m;
   d.R = R;
-  d.prec = ds->precision;
+  d.prec = ds->precision == PRGD_PREC_FP64 ? PREC_FP64 : PREC_MIXED;
+  d.tangent_bf16 = ds->precision == PRGD_PREC_MIXED_BF16 ? 1 : 0;
   d.step_policy = ds->step_policy;
   d.metric = ds->metric;
   d.stop_rule = ds->stop_rule;
@@ -518,7 +565,11 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   // sampled-pass variant (decided here because the stored-interface form needs
   // the permutation of the first grouping)
   const bool use3_cand = m == 3 && sm == 1 && sampled3_lds_bytes(s->n[0], s->n[2], R, d.prec, 0) <= 163840;
-  const bool modes_cand = !use3_cand && use_mode_passes(m, s->n.data(), R, d.prec, N);
+  const int chain_u = ds->pass_kind == PRGD_PASS_MODES ? -1 : chain_plan(m, s->n.data(), R, d.prec, N);
+  if (ds->pass_kind == PRGD_PASS_CHAIN && chain_u < 0)
+    return cleanup(fail(PRGD_ENOTSUP, "the one-pass chain kernel does not apply to this shape"));
+  const bool chain_cand = !use3_cand && chain_u >= 0;
+  const bool modes_cand = !use3_cand && !chain_cand && use_mode_passes(m, s->n.data(), R, d.prec, N);
   const bool want_iface = modes_cand && use_stored_interfaces(ds->mode_interfaces, m, R, d.prec, N);
   int *perm0 = nullptr, *perm_k = nullptr, *inv_k = nullptr;
   // allocations
@@ -560,8 +611,10 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   if (want_iface && (!A(s->alloc(&perm0, N)) || !A(s->alloc(&perm_k, N)) || !A(s->alloc(&inv_k, N))))
     return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
   {
-    hipError_t e = group_by_mode(m, N, sm, s->n[sm], idx_dev, val_dev, ds->values_fp64, idx_sorted, y64, y32, s->stream,
-                                 perm0);
+    hipError_t e = chain_cand ? group_by_prefix(m, N, chain_u, s->n.data(), idx_dev, val_dev, ds->values_fp64,
+                                                idx_sorted, y64, y32, s->stream)
+                              : group_by_mode(m, N, sm, s->n[sm], idx_dev, val_dev, ds->values_fp64, idx_sorted, y64,
+                                              y32, s->stream, perm0);
     if (e != hipSuccess) return cleanup(fail(PRGD_EDEVICE, std::string("grouping Omega: ") + hipGetErrorString(e)));
   }
 
@@ -677,7 +730,57 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   d.rpos = nullptr;
   d.ifl = nullptr;
   d.ifr = nullptr;
-  if (!d.use3 && modes_cand) {
+  d.use_chain = 0;
+  d.ch_u = 0;
+  d.ch_nchunks = 0;
+  d.ch_start = d.ch_len = nullptr;
+  d.ch_part = nullptr;
+  d.ch_rsq = d.ch_red = nullptr;
+  if (!d.use3 && chain_cand) {
+    // segments of equal leading indices (the sort above is stable and by
+    // that key, so segment v occupies [seg[v], seg[v+1])), cut into chunks
+    const int u = chain_u;
+    long long span = 1;
+    for (int k = 0; k < u; ++k) span *= s->n[k];
+    std::vector<long long> seg((size_t)span + 1, 0);
+    for (long long j = 0; j < N; ++j) {
+      long long key = 0;
+      for (int k = 0; k < u; ++k) key = key * s->n[k] + idx_h[(long long)k * N + j];
+      seg[key + 1]++;
+    }
+    for (long long v = 0; v < span; ++v) seg[v + 1] += seg[v];
+    const long long cmax = chain_chunk_max(N);
+    std::vector<int> cstart, clen;
+    for (long long v = 0; v < span; ++v) {
+      const long long a = seg[v], b = seg[v + 1];
+      if (b <= a) continue;
+      const long long pieces = (b - a + cmax - 1) / cmax;
+      for (long long p = 0; p < pieces; ++p) {
+        const long long lo = a + (b - a) * p / pieces, hi = a + (b - a) * (p + 1) / pieces;
+        cstart.push_back((int)lo);
+        clen.push_back((int)(hi - lo));
+      }
+    }
+    const int nch = (int)cstart.size();
+    const long long W = chain_part_width(m, u, R);
+    const long long nout = (long long)soff * (R * R + 1);
+    const long long ng = (nch + 31) / 32;
+    int *dst = nullptr, *dln = nullptr;
+    unsigned char *pp = nullptr;
+    if (!A(s->alloc(&dst, nch)) || !A(s->alloc(&dln, nch)) || !A(s->alloc(&pp, (long long)nch * W * (mixed ? 4 : 8))) ||
+        !A(s->alloc(&d.ch_rsq, nch)) || !A(s->alloc(&d.ch_red, ng * nout)))
+      return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
+    if (hipMemcpyAsync(dst, cstart.data(), nch * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(dln, clen.data(), nch * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return cleanup(fail(PRGD_EDEVICE, "upload of the chunk table failed"));
+    d.ch_start = dst;
+    d.ch_len = dln;
+    d.ch_part = pp;
+    d.ch_u = u;
+    d.ch_nchunks = nch;
+    d.use_chain = 1;
+  } else if (!d.use3 && modes_cand) {
     const long long f = mixed ? 4 : 8;
     const long long segw = (long long)R * R + 1;
     std::vector<ModeTab> mt(m);

@@ -301,6 +301,140 @@ __global__ void __launch_bounds__(1024) k_tangent(const Dev *__restrict__ dt) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// tangent components with the three R x R contractions per slice on the
+// matrix cores in bfloat16 (float32 accumulation), one wave per slice
+// ---------------------------------------------------------------------------
+typedef short bf_s4 __attribute__((ext_vector_type(4)));
+typedef float bf_f4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ short to_bf16(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// power of two p with max|v| * p in [0.5, 1) (1 for an all-zero matrix): exact
+// scaling that puts the bfloat16 operands of each core near unit size
+__device__ __forceinline__ double unit_scale(double amax) {
+  if (!(amax > 0.0)) return 1.0;
+  int e;
+  (void)frexp(amax, &e);
+  return ldexp(1.0, -e);
+}
+
+// Same result as k_tangent (X_c(x) = omega^{-1} GL_c^{-1} Y_c(x) H_{c+1}^{-1}
+// - T_c(x) Psi_c) with the slice products on 16x16x16 bfloat16 MFMAs.  The
+// R x R operands are zero-padded to 16 x 16.  Lane l of a wave holds row or
+// column l % 16 and the four k indices 4 (l / 16) .. +3.  The first product is
+// formed transposed, (GL^{-1} Y)^T = Y^T GL^{-T}, so that its result lands in
+// the A-operand layout of the second.  Scales: one power of two per core for
+// GL^{-1}, H^{-1} and Psi, one per slice for Y(x), T(x) and GL^{-1} Y(x).
+__global__ void __launch_bounds__(1024) k_tangent_bf16(const Dev *__restrict__ dt) {
+  const Dev &d = dt[blockIdx.y];
+  if ((int)blockIdx.x >= d.blk_off[d.m] || d.st->done) return;
+  __shared__ double smem[6 * RMAX * RMAX];
+  __shared__ double samax[32];
+  int c, x0, x1;
+  block_core(d, c, x0, x1);
+  const int R = d.R, RR = R * R, m = d.m;
+  double *GI = smem, *HI = smem + RR, *PS = smem + 2 * RR;
+  double *G1 = smem + 3 * RR, *TH = G1 + RR, *T1 = TH + RR;
+  const bool psi = c < m - 1;
+  const double *gi = sm_slot(d, c, S_GLI), *hi = sm_slot(d, c + 1, S_HI);
+  const double *g1 = sm_slot(d, psi ? c + 1 : c, S_GLI), *th = sm_slot(d, c, S_TH);
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    GI[t] = gi[t];
+    HI[t] = hi[t];
+    G1[t] = g1[t];
+    TH[t] = th[t];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    const int a = t / R, b = t - a * R;
+    double v = 0.0;
+    for (int k = 0; k < R; ++k) v = fma(G1[a * R + k], TH[k * R + b], v);
+    T1[t] = v;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    const int a = t / R, b = t - a * R;
+    double v = 0.0;
+    for (int k = 0; k < R; ++k) v = fma(T1[a * R + k], HI[k * R + b], v);
+    PS[t] = psi ? v : 0.0;
+  }
+  __syncthreads();
+  // per-core scales of GL^{-1}, H^{-1}, Psi
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (w < 3) {
+    const double *Mx = w == 0 ? GI : (w == 1 ? HI : PS);
+    double a = 0.0;
+    for (int t = lane; t < RR; t += 64) a = fmax(a, fabs(Mx[t]));
+    a = wave_max(a);
+    if (lane == 0) samax[w] = a;
+  }
+  __syncthreads();
+  const double sG = unit_scale(samax[0]), sH = unit_scale(samax[1]), sP = unit_scale(samax[2]);
+  const int i = lane & 15, q = lane >> 4;
+  // B operands fixed for the core: (GL^{-1})^T[k][i] = GL^{-1}[i][k], H^{-1}[k][i], Psi[k][i]
+  bf_s4 bG, bH, bP;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int k = 4 * q + v;
+    const bool in = i < R && k < R;
+    bG[v] = to_bf16(in ? (float)(GI[i * R + k] * sG) : 0.0f);
+    bH[v] = to_bf16(in ? (float)(HI[k * R + i] * sH) : 0.0f);
+    bP[v] = to_bf16(in ? (float)(PS[k * R + i] * sP) : 0.0f);
+  }
+  const bf_f4 zero = {0.f, 0.f, 0.f, 0.f};
+  for (int x = x0 + w; x < x1; x += nw) {
+    const long long off = d.coff[c] + (long long)x * RR;
+    // A of the first product: Y^T[i][k] = Y[k][i]; A of the third: T[i][k]
+    double yv[4], tv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = 4 * q + v;
+      const bool in = i < R && k < R;
+      yv[v] = in ? load_grad(d, off + (long long)k * R + i) : 0.0;
+      tv[v] = in ? glb(d.cores)[off + (long long)i * R + k] : 0.0;
+    }
+    double ya = fmax(fmax(fabs(yv[0]), fabs(yv[1])), fmax(fabs(yv[2]), fabs(yv[3])));
+    double ta = fmax(fmax(fabs(tv[0]), fabs(tv[1])), fmax(fabs(tv[2]), fabs(tv[3])));
+    ya = wave_max(ya);
+    ta = wave_max(ta);
+    const double sY = unit_scale(ya), sT = unit_scale(ta);
+    bf_s4 aY, aT;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      aY[v] = to_bf16((float)(yv[v] * sY));
+      aT[v] = to_bf16((float)(tv[v] * sT));
+    }
+    // (GL^{-1} Y)^T, scaled by sY sG: element v of lane l is (GL^{-1} Y)[i][4q + v]
+    const bf_f4 gy = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aY, bG, zero, 0, 0, 0);
+    double ga = fmax(fmax(fabs((double)gy[0]), fabs((double)gy[1])), fmax(fabs((double)gy[2]), fabs((double)gy[3])));
+    ga = wave_max(ga);
+    const double sM = unit_scale(ga);
+    bf_s4 aM;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) aM[v] = to_bf16((float)(gy[v] * sM));
+    const bf_f4 vv = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aM, bH, zero, 0, 0, 0);
+    const bf_f4 uu = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aT, bP, zero, 0, 0, 0);
+    const double iw = 1.0 / glb(d.omega)[d.soff[c] + x];
+    const double kv = iw / (sY * sG * sM * sH), ku = 1.0 / (sT * sP);
+    // element v: row 4q + v, column i
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 4 * q + v;
+      if (r < R && i < R) glb(d.X)[off + (long long)r * R + i] = (double)vv[v] * kv - (double)uu[v] * ku;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = 4 * q + v;
+      if (i < R && k < R) zero_grad(d, off + (long long)k * R + i);
+    }
+  }
+}
+
 // block core C_c(x) of W_l = T_l - alpha xi as a 2R x 2R matrix in LDS
 __device__ inline void build_block(const Dev &d, int c, const double *sT, const double *sX, double alpha,
                                    double *C, int tl, int tpg) {
@@ -942,7 +1076,10 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
     hipLaunchKernelGGL(k_gram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, j);
   }
   const int g = max_over(bt, [&](const Dev &d) { return d.blk_off[m]; });
-  hipLaunchKernelGGL(k_tangent, dim3(g, ns), dim3(1024), 0, s, bt.dt);
+  if (bt.host[0].tangent_bf16)   // the whole batch shares the variant
+    hipLaunchKernelGGL(k_tangent_bf16, dim3(g, ns), dim3(1024), 0, s, bt.dt);
+  else
+    hipLaunchKernelGGL(k_tangent, dim3(g, ns), dim3(1024), 0, s, bt.dt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_adaptive_step(bt, s);    // members with the adaptive step only

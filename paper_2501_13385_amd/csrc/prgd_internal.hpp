@@ -5,7 +5,8 @@
 //             R >= max r_k is the padded slice dimension.  Entries outside the
 //             true ranks are exactly zero.  Core 0 uses row 0 only, core m-1
 //             column 0 only.
-//   idx     : int32 [m][N], Omega grouped (stably sorted) by mode `sort_mode`.
+//   idx     : int32 [m][N], Omega grouped (stably sorted) by mode `sort_mode`,
+//             or by its first ch_u mode indices for the one-pass chain kernel.
 //   y       : observed values [N] in the working precision, same order.
 //   Y       : gradient accumulator, layout of the cores (float or double).
 //   X       : tangent components, layout of the cores (double).
@@ -111,6 +112,7 @@ struct Dev {
   int m;
   int R;                       // padded slice dimension
   int prec;
+  int tangent_bf16;            // 1: tangent contractions on bfloat16 MFMAs (prec is then PREC_MIXED)
   int step_policy;
   int metric;                  // Metric
   int stop_rule;
@@ -169,7 +171,34 @@ struct Dev {
   void *ifl;                   // [m][N][R] in the working precision
   void *ifr;                   // [m][N][R + 1] in the working precision
   S3 q3;
+  // one-pass sampled pass for small mode sizes (see sampled_chain.hip): Omega
+  // sorted by its first ch_u mode indices and cut into chunks that keep that
+  // prefix; every chunk writes one partial of ch_W elements
+  int use_chain;
+  int ch_u;                    // leading modes uniform within a chunk
+  int ch_nchunks;
+  const int *ch_start;         // [ch_nchunks] first sample of each chunk
+  const int *ch_len;           // [ch_nchunks] samples of each chunk
+  void *ch_part;               // [ch_nchunks][width] in the working precision
+  double *ch_rsq;              // [ch_nchunks] ||R||^2 of each chunk
+  double *ch_red;              // [groups][outputs] first-stage sums
 };
+
+// Sizes of the one-pass chain kernel (sampled_chain.hip), shared with the host plan.
+__host__ __device__ inline int chain_nx(int R) {
+  const int xh = 16 / R;
+  return xh * xh < 16 ? xh * xh : 16;
+}
+// LDS stride of one staged slice: R^2 plus 16 bytes, so that the slices of a
+// core start on different banks
+__host__ __device__ inline int chain_slice_stride(int R, int fbytes) { return R * R + 16 / fbytes; }
+__host__ __device__ inline int chain_slot_width(int R) { return R * 67 + (R == 2 ? 2 : 0); }
+// width of one chunk's partial (elements): tiles, slice sums, uniform gradients
+__host__ __device__ inline int chain_part_width(int m, int u, int R) {
+  const int nc = m - u;
+  return nc * 256 + nc * chain_nx(R) + u * R * R;
+}
+__host__ __device__ inline int chain_nslots(int nc) { return nc - 2 > 1 ? nc - 2 : 1; }
 
 // Blocks of a slice-parallel reduction kernel over n slices: at least
 // `target` slices per block and at most 128 blocks, so that the finishing

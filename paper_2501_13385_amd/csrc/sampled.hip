@@ -192,8 +192,8 @@ template <typename F>
 __global__ void __launch_bounds__(1024) k_sampled_fin(const Dev *__restrict__ dt, int diag) {
   const Dev &d = dt[blockIdx.y];
   if (!diag && d.st->done) return;
-  const double *rsq_part = d.use3 ? d.q3.part_rsq : (d.use_modes ? d.mp_rsq : d.part);
-  const int nb = d.use3 ? d.q3.nwg : (d.use_modes ? d.mt[0].nwg : d.nb_sampled);
+  const double *rsq_part = d.use3 ? d.q3.part_rsq : (d.use_chain ? d.ch_rsq : (d.use_modes ? d.mp_rsq : d.part));
+  const int nb = d.use3 ? d.q3.nwg : (d.use_chain ? d.ch_nchunks : (d.use_modes ? d.mt[0].nwg : d.nb_sampled));
   double v = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) v += rsq_part[i];
   sampled_finish_total<F>(d, (F *)d.s, v, diag);   // v: this thread's share of ||R||^2

@@ -1,0 +1,565 @@
+// One pass over Omega for orders >= 4 with small mode sizes (n_k R^2 <= 256,
+// R the padded rank in {2, 4, 8}): the order-14, n = 4 workload and its kind.
+//
+// What is computed (section 2.1, TT format; section 3.2.1, metric weights):
+// for every sample x^(j) the entry T(x) = l_k T_k(x_k) r_{k+1} with the left
+// interface l_k = T_1(x_1) ... T_{k-1}(x_{k-1}) (row vector, l_1 = e_1) and
+// the right interface r_{k+1} = T_{k+1}(x_{k+1}) ... T_m(x_m) (column vector,
+// r_{m+1} = e_1), the residual R_j = T(x) - y_j, and for every core k
+//   dT_k(x_k) += R_j l_k^T r_{k+1}^T     (chain rule on the TT format)
+//   s_k(x_k)  += R_j^2                   (squared mode-slice norm)
+// plus ||R||^2.
+//
+// How (one HIP workgroup per chunk of Omega):
+//   * Omega is sorted by its first u mode indices (mixed radix, mode 1 most
+//     significant) and split into chunks that never straddle a change of that
+//     prefix.  Within a chunk x_1..x_u are the same for every sample, so
+//     l_{u+1} is one vector per chunk, and the contributions to cores 1..u
+//     reduce to V_{u+1} = sum_j R_j r_{u+1}(x^(j)): dT_k(x_k) += l_k^T V_{k+1}^T
+//     with V_k = T_k(x_k) V_{k+1}, formed once per chunk.
+//   * Lane = sample.  A right sweep forms r_m, ..., r_{u+1} (slices of the
+//     cores u+1..m staged in LDS, rows of a slice read as 16-byte vectors) and
+//     parks r_{k+1} in LDS for the gradient; the residual follows from l_{u+1}
+//     and r_{u+1}; a left sweep then carries l_k.
+//   * Gradient of core k >= u+1: a 16x16 MFMA tile whose rows are (x_hi, a)
+//     and columns (x_lo, b), x_k = x_hi * (16/R) + x_lo, holds the whole
+//     n_k x R x R gradient (n_k <= (16/R)^2).  A K-step takes the four samples
+//     16 q + S (q = MFMA k index = lane / 16): A = l_k[a] of that sample when its
+//     x_hi matches the row, B = R_j r_{k+1}[b] when its x_lo matches the column.
+//     Each wave keeps one accumulator tile per core in registers for its whole
+//     share of the chunk.
+//   * Slice sums of cores >= u+1: a butterfly over the wave leaves every lane
+//     the sum for one slice value, accumulated per lane across batches.
+//   * Per chunk: the waves' tiles, slice sums and V_{u+1} are summed in LDS in
+//     wave order and written as one partial; two reduction kernels sum the
+//     partials over groups of chunks and then over groups, in a fixed order.
+// No atomics: float64 results repeat bit for bit.
+#include <algorithm>
+#include <utility>
+
+#include "prgd_internal.hpp"
+#include "block_ops.hpp"
+
+namespace prgd {
+
+typedef double c_d4v __attribute__((ext_vector_type(4)));
+typedef float c_f4v __attribute__((ext_vector_type(4)));
+
+template <typename F>
+struct MmaC;
+template <>
+struct MmaC<double> {
+  typedef c_d4v acc_t;
+  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of the 16x16 result held in element v of lane l (column l % 16)
+  __device__ static int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct MmaC<float> {
+  typedef c_f4v acc_t;
+  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+// value of lane 16 (l / 16) + N in lane l (DPP row_newbcast)
+template <int N>
+__device__ __forceinline__ int cbcast(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false);
+}
+template <int N>
+__device__ __forceinline__ float cbcast(float v) {
+  return __int_as_float(cbcast<N>(__float_as_int(v)));
+}
+template <int N>
+__device__ __forceinline__ double cbcast(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = cbcast<N>((int)b), hi = cbcast<N>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ void chain_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Sizes shared by the host plan and the kernel.
+template <int R>
+struct ChainShape {
+  static constexpr int RR = R * R;
+  static constexpr int XH = 16 / R;                          // slice values per tile side
+  static constexpr int NX = XH * XH < 16 ? XH * XH : 16;     // slice values per core
+  static constexpr int TILE = 256;
+  // staging slot: 64 samples x R values; sample s at R (s + s / 16), so that
+  // the four samples of a K-step (one per group of 16) and their R values
+  // fall on distinct banks
+  static constexpr int SLOTW = R * 67 + (R == 2 ? 2 : 0);
+};
+
+// Sum of v over the lanes whose index agrees in the top log2(NX) bits after
+// a reduce-scatter of the one-hot vector (v at slot x) across the wave:
+// returns, in lane l, the sum of v over the lanes {l ^ t} (t over the top
+// bits) whose x equals l >> (6 - log2 NX).
+template <typename F, int NX>
+__device__ __forceinline__ F slice_scatter(F v, int x, int lane) {
+  constexpr int H0 = NX / 2;
+  const F vp = __shfl_xor(v, 32, 64);
+  const int xp = __shfl_xor(x, 32, 64);
+  const int base = (lane & 32) ? H0 : 0;
+  F kept[H0];
+#pragma unroll
+  for (int i = 0; i < H0; ++i) kept[i] = (x == base + i ? v : (F)0) + (xp == base + i ? vp : (F)0);
+#pragma unroll
+  for (int H = H0, off = 16; H > 1; H >>= 1, off >>= 1) {
+    const bool hb = (lane & off) != 0;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) {
+      const F send = hb ? kept[i] : kept[H / 2 + i];
+      const F recv = __shfl_xor(send, off, 64);
+      kept[i] = (hb ? kept[H / 2 + i] : kept[i]) + recv;
+    }
+  }
+  return kept[0];
+}
+
+// the operands of one K-step S for core c and the MFMA
+template <typename F, int R, int S>
+__device__ __forceinline__ void chain_kstep(typename MmaC<F>::acc_t &acc, int xc, int xl, F res, F lamA,
+                                            const F *stg, bool stg_ok, const F *bsl, int bmode, const F *tlast,
+                                            int SL, F bE, int lane) {
+  constexpr int XH = 16 / R;
+  const int q = lane >> 4, i = lane & 15, a = i % R, h = i / R;
+  const int s = 16 * q + S;
+  const int xs = cbcast<S>(xc);
+  const F rs = cbcast<S>(res);
+  F av = stg_ok ? stg[R * (s + q) + a] : lamA;
+  av = (xs / XH == h) ? av : (F)0;
+  F bv;
+  if (bmode == 0) {
+    bv = bsl[R * (s + q) + a];
+  } else if (bmode == 1) {
+    const int xls = cbcast<S>(xl);
+    bv = tlast[xls * SL + a * R];
+  } else {
+    bv = bE;
+  }
+  bv = (xs % XH == h) ? rs * bv : (F)0;
+  acc = MmaC<F>::step(av, bv, acc);
+}
+
+template <typename F, int R, int... S>
+__device__ __forceinline__ void chain_mfma(typename MmaC<F>::acc_t &acc, int xc, int xl, F res, F lamA,
+                                           const F *stg, bool stg_ok, const F *bsl, int bmode, const F *tlast,
+                                           int SL, F bE, int lane, std::integer_sequence<int, S...>) {
+  (chain_kstep<F, R, S>(acc, xc, xl, res, lamA, stg, stg_ok, bsl, bmode, tlast, SL, bE, lane), ...);
+}
+
+template <typename F, int R, int MAXC, int NW>
+__global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
+  if ((int)blockIdx.x >= d.ch_nchunks || (!diag && d.st->done)) return;
+  typedef MmaC<F> M;
+  constexpr int RR = R * R;
+  constexpr int NT = NW * 64;
+  constexpr int NX = ChainShape<R>::NX;
+  constexpr int SLOTW = ChainShape<R>::SLOTW;
+  constexpr int SL = RR + 16 / (int)sizeof(F);
+  const int m = d.m, u = d.ch_u, nc = m - u;
+  const long long N = d.N;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const bool mixed = d.prec == PREC_MIXED;
+  const auto gcores = glb((const F *)(mixed ? (const void *)d.cores32 : (const void *)d.cores));
+  const auto idx = glb(d.idx);
+  const auto y = glb((const F *)(mixed ? (const void *)d.y32 : (const void *)d.y64));
+  extern __shared__ unsigned char lds_raw[];
+  F *lc = reinterpret_cast<F *>(lds_raw);
+  // LDS offsets of the staged cores u+1..m (core u + c at loff[c], slice x at x SL)
+  int loff[MAXC];
+  int lo = 0;
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) {
+    loff[c] = lo;
+    if (c < nc) lo += d.n[u + c] * SL;
+  }
+  const int lo_last = lo - d.n[m - 1] * SL;
+  const int nslots = chain_nslots(nc);
+  F *wsl = lc + lo + (long long)w * nslots * SLOTW;
+  for (int c = 0; c < nc; ++c) {
+    const int k = u + c, nk = d.n[k];
+    int base = 0;
+    for (int cc = 0; cc < c; ++cc) base += d.n[u + cc] * SL;
+    for (int i = threadIdx.x; i < nk * RR; i += NT) lc[base + (i / RR) * SL + i % RR] = gcores[d.coff[k] + i];
+  }
+  const int cs = glb(d.ch_start)[blockIdx.x], cl = glb(d.ch_len)[blockIdx.x];
+  // l_{u+1}: the same for every sample of the chunk
+  F lamu[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) lamu[a] = a == 0 ? (F)1 : (F)0;
+  for (int k = 0; k < u; ++k) {
+    const int x = __builtin_amdgcn_readfirstlane(idx[(long long)k * N + cs]);
+    const auto sl = gcores + d.coff[k] + (long long)x * RR;
+    F nl[R];
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      F t = (F)0;
+#pragma unroll
+      for (int a = 0; a < R; ++a) t = fma(lamu[a], sl[a * R + b], t);
+      nl[b] = t;
+    }
+#pragma unroll
+    for (int b = 0; b < R; ++b) lamu[b] = nl[b];
+  }
+  const int iA = lane & 15, aA = iA % R;
+  F lamA = (F)0;
+#pragma unroll
+  for (int a = 0; a < R; ++a)
+    if (a == aA) lamA = lamu[a];
+  const F bE = aA == 0 ? (F)1 : (F)0;
+  __syncthreads();
+
+  typename M::acc_t acc[MAXC];
+  F ssacc[MAXC];
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) {
+    acc[c] = M::zero();
+    ssacc[c] = (F)0;
+  }
+  F vacc[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) vacc[a] = (F)0;
+  double rsq = 0.0;
+  const F *tlast = lc + lo_last;
+  const int nbt = (cl + 63) >> 6;
+  for (int bt = w; bt < nbt; bt += NW) {
+    const int jj = bt * 64 + lane;
+    const bool act = jj < cl;
+    const long long j = (long long)cs + (act ? jj : 0);
+    int xk[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) xk[c] = (c < nc && act) ? idx[(long long)(u + c) * N + j] : 0;
+    const int xl = act ? idx[(long long)(m - 1) * N + j] : 0;
+    const F yv = act ? y[j] : (F)0;
+    chain_wave_sync();   // the previous batch's reads of the slots are done
+    // right sweep: r_m = T_m(:, x_m, 0), then r_k = T_k(x_k) r_{k+1}; r_{k+1}
+    // of cores u+1..m-2 parked in slot c
+    F rho[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) rho[a] = tlast[xl * SL + a * R];
+#pragma unroll
+    for (int c = MAXC - 2; c >= 0; --c) {
+      if (c <= nc - 2) {
+        if (c <= nc - 3) {
+          F *dst = wsl + c * SLOTW + R * (lane + (lane >> 4));
+#pragma unroll
+          for (int a = 0; a < R; ++a) dst[a] = rho[a];
+        }
+        const F *sl = lc + loff[c] + xk[c] * SL;
+        F nr[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+          F t = (F)0;
+#pragma unroll
+          for (int b = 0; b < R; ++b) t = fma(sl[a * R + b], rho[b], t);
+          nr[a] = t;
+        }
+#pragma unroll
+        for (int a = 0; a < R; ++a) rho[a] = nr[a];
+      }
+    }
+    F t = (F)0;
+#pragma unroll
+    for (int a = 0; a < R; ++a) t = fma(lamu[a], rho[a], t);
+    const F res = act ? t - yv : (F)0;
+    const F r2 = res * res;
+    rsq += (double)r2;
+#pragma unroll
+    for (int a = 0; a < R; ++a) vacc[a] = fma(res, rho[a], vacc[a]);
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+      if (c < nc) ssacc[c] += slice_scatter<F, NX>(r2, xk[c], lane);
+    // left sweep with the gradient tiles
+    F lam[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) lam[a] = lamu[a];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+      if (c < nc) {
+        F *stg = wsl + (c == 0 ? 0 : (c - 1 < nslots - 1 ? c - 1 : nslots - 1)) * SLOTW;
+        if (c >= 1) {
+          F *dst = stg + R * (lane + (lane >> 4));
+#pragma unroll
+          for (int a = 0; a < R; ++a) dst[a] = lam[a];
+        }
+        chain_wave_sync();
+        const int bmode = c <= nc - 3 ? 0 : (c == nc - 2 ? 1 : 2);
+        const F *bsl = wsl + (c <= nc - 3 ? c : 0) * SLOTW;
+        chain_mfma<F, R>(acc[c], xk[c], xl, res, lamA, stg, c >= 1, bsl, bmode, tlast, SL, bE, lane,
+                         std::make_integer_sequence<int, 16>{});
+        if (c < nc - 1) {
+          const F *sl = lc + loff[c] + xk[c] * SL;
+          F nl[R];
+#pragma unroll
+          for (int b = 0; b < R; ++b) nl[b] = (F)0;
+#pragma unroll
+          for (int a = 0; a < R; ++a)
+#pragma unroll
+            for (int b = 0; b < R; ++b) nl[b] = fma(lam[a], sl[a * R + b], nl[b]);
+#pragma unroll
+          for (int b = 0; b < R; ++b) lam[b] = nl[b];
+        }
+        chain_wave_sync();
+      }
+    }
+  }
+
+  // ---- per-chunk partial: waves summed in LDS in wave order ----
+  __shared__ double sbuf[16];
+  const double rs_tot = block_sum(rsq, sbuf);    // ends with a barrier: every wave is past its slots
+  const int WT = nc * 256, WS = nc * NX;
+  const int WR = WT + WS + R;                    // per-wave region: tiles, slice sums, V
+  F *red = lc + lo;                              // reuses the slots
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) {
+    if (c < nc) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w * WR + c * 256 + M::row(lane, v) * 16 + (lane & 15)] = acc[c][v];
+      // slice value of this lane: its top log2(NX) bits; sum over the rest
+      F sv = ssacc[c];
+#pragma unroll
+      for (int o = 64 / NX / 2; o >= 1; o >>= 1) sv += __shfl_xor(sv, o, 64);
+      if ((lane & (64 / NX - 1)) == 0) red[w * WR + WT + c * NX + lane / (64 / NX)] = sv;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < R; ++a) {
+    const double v = wave_sum((double)vacc[a]);
+    if (lane == 0) red[w * WR + WT + WS + a] = (F)v;
+  }
+  __syncthreads();
+  const int W = chain_part_width(m, u, R);
+  const auto part = glb((F *)d.ch_part) + (long long)blockIdx.x * W;
+  for (int e = threadIdx.x; e < WT + WS; e += NT) {
+    F v = red[e];
+#pragma unroll
+    for (int ww = 1; ww < NW; ++ww) v += red[ww * WR + e];
+    part[e] = v;
+  }
+  if (threadIdx.x == 0) glb(d.ch_rsq)[blockIdx.x] = rs_tot;
+  // cores 1..u: l_k^T V_{k+1}^T at the chunk's x_k, with V_{u+1} the sum of
+  // the waves' R_j r_{u+1} and V_k = T_k(x_k) V_{k+1} (one wave)
+  if (u > 0 && w == 0) {
+    F V[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      F v = red[WT + WS + a];
+#pragma unroll
+      for (int ww = 1; ww < NW; ++ww) v += red[ww * WR + WT + WS + a];
+      V[a] = v;
+    }
+    for (int k = u - 1; k >= 0; --k) {
+      // l_k from the chunk's prefix
+      F l[R];
+#pragma unroll
+      for (int a = 0; a < R; ++a) l[a] = a == 0 ? (F)1 : (F)0;
+      for (int kk = 0; kk < k; ++kk) {
+        const int x = __builtin_amdgcn_readfirstlane(idx[(long long)kk * N + cs]);
+        const auto sl = gcores + d.coff[kk] + (long long)x * RR;
+        F nl[R];
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+          F t = (F)0;
+#pragma unroll
+          for (int a = 0; a < R; ++a) t = fma(l[a], sl[a * R + b], t);
+          nl[b] = t;
+        }
+#pragma unroll
+        for (int b = 0; b < R; ++b) l[b] = nl[b];
+      }
+      if (lane < RR) {
+        F g = (F)0;
+#pragma unroll
+        for (int a = 0; a < R; ++a)
+#pragma unroll
+          for (int b = 0; b < R; ++b)
+            if (a * R + b == lane) g = l[a] * V[b];
+        part[WT + WS + k * RR + lane] = g;
+      }
+      const int x = __builtin_amdgcn_readfirstlane(idx[(long long)k * N + cs]);
+      const auto sl = gcores + d.coff[k] + (long long)x * RR;
+      F nv[R];
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        F t = (F)0;
+#pragma unroll
+        for (int b = 0; b < R; ++b) t = fma(sl[a * R + b], V[b], t);
+        nv[a] = t;
+      }
+#pragma unroll
+      for (int a = 0; a < R; ++a) V[a] = nv[a];
+    }
+  }
+}
+
+// Output o of the chain pass: core k, slice x, entry e (e < R^2: gradient
+// (a, b) = (e / R, e % R); e = R^2: slice sum).  Outputs are core-major with
+// n_k (R^2 + 1) per core, so core k starts at soff[k] (R^2 + 1).
+template <typename F, int R>
+__device__ __forceinline__ void chain_output(const Dev &d, long long o, int &k, int &x, int &e, int &off) {
+  constexpr int RR = R * R;
+  constexpr int XH = 16 / R;
+  const int m = d.m, u = d.ch_u, nc = m - u;
+  k = 0;
+  while (k + 1 < m && (long long)d.soff[k + 1] * (RR + 1) <= o) ++k;
+  const long long r = o - (long long)d.soff[k] * (RR + 1);
+  x = (int)(r / (RR + 1));
+  e = (int)(r % (RR + 1));
+  const int NXv = chain_nx(R);
+  if (k >= u) {
+    const int c = k - u;
+    if (e < RR) {
+      const int a = e / R, b = e % R;
+      off = c * 256 + ((x / XH) * R + a) * 16 + (x % XH) * R + b;
+    } else {
+      off = nc * 256 + c * NXv + x;
+    }
+  } else {
+    off = nc * 256 + nc * NXv + k * RR + (e < RR ? e : 0);
+  }
+}
+
+constexpr int CHAIN_GROUP = 32;   // chunks summed per thread in the first reduction
+
+// First reduction: output o, chunk group g (CHAIN_GROUP consecutive chunks).
+template <typename F, int R>
+__global__ void __launch_bounds__(256) k_chain_reduce1(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
+  constexpr int RR = R * R;
+  const long long nout = (long long)d.soff[d.m] * (RR + 1);
+  const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.z;
+  const int c0 = g * CHAIN_GROUP;
+  if (o >= nout || c0 >= d.ch_nchunks || (!diag && d.st->done)) return;
+  const int c1 = min(d.ch_nchunks, c0 + CHAIN_GROUP);
+  int k, x, e, off;
+  chain_output<F, R>(d, o, k, x, e, off);
+  const int W = chain_part_width(d.m, d.ch_u, R);
+  const auto part = glb((const F *)d.ch_part);
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  if (k >= d.ch_u) {
+    int c = c0;
+    for (; c + 4 <= c1; c += 4) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a[t] += (double)part[(long long)(c + t) * W + off];
+    }
+    for (; c < c1; ++c) a[0] += (double)part[(long long)c * W + off];
+  } else {
+    const auto idx = glb(d.idx);
+    const auto st = glb(d.ch_start);
+    const long long krow = (long long)k * d.N;
+    for (int c = c0; c < c1; ++c) {
+      if (idx[krow + st[c]] != x) continue;
+      a[c & 3] += e < RR ? (double)part[(long long)c * W + off] : glb(d.ch_rsq)[c];
+    }
+  }
+  glb(d.ch_red)[(long long)g * nout + o] = (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+// Second reduction: the group sums of output o into the gradient or the slice sums.
+template <typename F, int R>
+__global__ void __launch_bounds__(256) k_chain_reduce2(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
+  constexpr int RR = R * R;
+  const long long nout = (long long)d.soff[d.m] * (RR + 1);
+  const long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nout || (!diag && d.st->done)) return;
+  const int ng = (d.ch_nchunks + CHAIN_GROUP - 1) / CHAIN_GROUP;
+  const auto red = glb(d.ch_red);
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  int g = 0;
+  for (; g + 4 <= ng; g += 4) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) a[t] += red[(long long)(g + t) * nout + o];
+  }
+  for (; g < ng; ++g) a[0] += red[(long long)g * nout + o];
+  const double v = (a[0] + a[1]) + (a[2] + a[3]);
+  int k, x, e, off;
+  chain_output<F, R>(d, o, k, x, e, off);
+  if (e < RR) glb((F *)d.Y)[d.coff[k] + (long long)x * RR + e] = (F)v;
+  else glb((F *)d.s)[d.soff[k] + x] = (F)v;
+}
+
+hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s);
+
+size_t chain_lds_bytes(int m, int u, const int *n, int R, int prec) {
+  const size_t f = prec == PREC_MIXED ? 4 : 8;
+  const int nc = m - u;
+  size_t cores = 0;
+  for (int k = u; k < m; ++k) cores += (size_t)n[k] * chain_slice_stride(R, (int)f);
+  const size_t slots = (size_t)chain_nslots(nc) * chain_slot_width(R);
+  const size_t red = (size_t)nc * (256 + chain_nx(R)) + R;
+  return (cores + 4 * std::max(slots, red)) * f;
+}
+
+int chain_maxc(int nc) { return nc <= 4 ? 4 : (nc <= 8 ? 8 : (nc <= 10 ? 10 : (nc <= 12 ? 12 : 16))); }
+
+template <typename F, int R, int MAXC>
+static hipError_t launch_chain_c(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main) {
+  constexpr int NW = 4;
+  int g = 1;
+  size_t lds = 0;
+  long long nout = 1;
+  int ng = 1;
+  for (int i = 0; i < bt.ns; ++i) {
+    const Dev &h = bt.host[i];
+    g = std::max(g, h.ch_nchunks);
+    lds = std::max(lds, chain_lds_bytes(h.m, h.ch_u, h.n, R, h.prec));
+    nout = std::max<long long>(nout, (long long)h.soff[h.m] * (R * R + 1));
+    ng = std::max(ng, (h.ch_nchunks + CHAIN_GROUP - 1) / CHAIN_GROUP);
+  }
+  hipLaunchKernelGGL((k_chain<F, R, MAXC, NW>), dim3(g, bt.ns), dim3(NW * 64), lds, st, bt.dt, diag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (after_main && (e = hipEventRecord(after_main, st)) != hipSuccess) return e;
+  const int nb = (int)((nout + 255) / 256);
+  hipLaunchKernelGGL((k_chain_reduce1<F, R>), dim3(nb, bt.ns, ng), dim3(256), 0, st, bt.dt, diag);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_chain_reduce2<F, R>), dim3(nb, bt.ns), dim3(256), 0, st, bt.dt, diag);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_sampled_fin(bt, diag, st);
+}
+
+template <typename F, int R>
+static hipError_t launch_chain_r(const Batch &bt, int diag, hipStream_t st, hipEvent_t ev) {
+  int nc = 1;
+  for (int i = 0; i < bt.ns; ++i) nc = std::max(nc, bt.host[i].m - bt.host[i].ch_u);
+  switch (chain_maxc(nc)) {
+    case 4: return launch_chain_c<F, R, 4>(bt, diag, st, ev);
+    case 8: return launch_chain_c<F, R, 8>(bt, diag, st, ev);
+    case 10: return launch_chain_c<F, R, 10>(bt, diag, st, ev);
+    case 12: return launch_chain_c<F, R, 12>(bt, diag, st, ev);
+    default: return launch_chain_c<F, R, 16>(bt, diag, st, ev);
+  }
+}
+
+template <typename F>
+static hipError_t launch_chain_f(const Batch &bt, int diag, hipStream_t st, hipEvent_t ev) {
+  switch (bt.host[0].R) {
+    case 2: return launch_chain_r<F, 2>(bt, diag, st, ev);
+    case 4: return launch_chain_r<F, 4>(bt, diag, st, ev);
+    case 8: return launch_chain_r<F, 8>(bt, diag, st, ev);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sampled_chain(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main) {
+  if (bt.host[0].prec == PREC_MIXED) return launch_chain_f<float>(bt, diag, st, after_main);
+  return launch_chain_f<double>(bt, diag, st, after_main);
+}
+
+}  // namespace prgd

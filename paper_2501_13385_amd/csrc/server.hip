@@ -231,8 +231,8 @@ void prgd_server_s::admit() {
       q->vals.shrink_to_fit();
     }
     const Dev &d = s->d;
-    const int variant = d.use3 ? 1 : (d.use_modes ? (d.use_iface ? 3 : 2) : 0);    // sampled-pass kernel family
-    const GroupKey key{d.m, d.R, d.prec, variant, d.use3 ? d.q3.stage : 0};
+    const int variant = d.use3 ? 1 : (d.use_chain ? 4 : (d.use_modes ? (d.use_iface ? 3 : 2) : 0));   // sampled-pass kernel family
+    const GroupKey key{d.m, d.R, d.prec + 2 * d.tangent_bf16, variant, d.use3 ? d.q3.stage : 0};
     auto it = groups.find(key);
     if (it == groups.end()) {
       auto g = std::make_unique<Group>();

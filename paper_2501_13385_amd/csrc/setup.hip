@@ -114,6 +114,69 @@ hipError_t group_by_mode(int m, long long N, int mode, int n_mode, const int *id
   return hipStreamSynchronize(s);
 }
 
+// mixed-radix key of the first u mode indices (mode 1 most significant)
+__global__ void k_prefix_key(int u, long long N, const int *__restrict__ idx, const int *__restrict__ n,
+                             unsigned *__restrict__ key) {
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += (long long)gridDim.x * blockDim.x) {
+    unsigned v = 0;
+    for (int k = 0; k < u; ++k) v = v * (unsigned)n[k] + (unsigned)idx[(long long)k * N + j];
+    key[j] = v;
+  }
+}
+
+hipError_t group_by_prefix(int m, long long N, int u, const int *n, const int *idx_in, const void *values_in,
+                           int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s) {
+  hipError_t e;
+  unsigned *keys_in = nullptr, *keys_out = nullptr;
+  int *perm_in = nullptr, *perm_out = nullptr, *nd = nullptr;
+  void *temp = nullptr;
+  size_t temp_bytes = 0;
+  struct Scratch {
+    hipStream_t s;
+    void **p[6];
+    ~Scratch() {
+      (void)hipStreamSynchronize(s);
+      for (void **q : p)
+        if (*q) (void)hipFree(*q);
+    }
+  } scratch{s, {(void **)&keys_in, (void **)&keys_out, (void **)&perm_in, (void **)&perm_out, (void **)&nd, &temp}};
+  unsigned long long span = 1;
+  for (int k = 0; k < u; ++k) span *= (unsigned long long)n[k];
+  unsigned end_bit = 0;
+  while (end_bit < 32 && (1ull << end_bit) < span) ++end_bit;
+  if ((e = hipMalloc((void **)&perm_out, N * sizeof(int))) != hipSuccess) return e;
+  if (end_bit == 0) {
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(N)), dim3(256), 0, s, perm_out, N);
+  } else {
+    if ((e = hipMalloc((void **)&keys_in, N * sizeof(unsigned))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&keys_out, N * sizeof(unsigned))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&perm_in, N * sizeof(int))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&nd, (size_t)(u > 0 ? u : 1) * sizeof(int))) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(nd, n, (size_t)u * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_prefix_key, dim3(grid_for(N)), dim3(256), 0, s, u, N, idx_in, (const int *)nd, keys_in);
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(N)), dim3(256), 0, s, perm_in, N);
+    e = rocprim::radix_sort_pairs(nullptr, temp_bytes, keys_in, keys_out, perm_in, perm_out, (size_t)N, 0, end_bit, s);
+    if (e != hipSuccess) return e;
+    if ((e = hipMalloc(&temp, temp_bytes ? temp_bytes : 16)) != hipSuccess) return e;
+    e = rocprim::radix_sort_pairs(temp, temp_bytes, keys_in, keys_out, perm_in, perm_out, (size_t)N, 0, end_bit, s);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_gather_idx, dim3(grid_for(N)), dim3(256), 0, s, m, N, idx_in, perm_out, idx_out);
+  if (values_fp64) {
+    if (y64) hipLaunchKernelGGL((k_gather_val<double, double>), dim3(grid_for(N)), dim3(256), 0, s, N,
+                                (const double *)values_in, perm_out, y64);
+    if (y32) hipLaunchKernelGGL((k_gather_val<double, float>), dim3(grid_for(N)), dim3(256), 0, s, N,
+                                (const double *)values_in, perm_out, y32);
+  } else {
+    if (y64) hipLaunchKernelGGL((k_gather_val<float, double>), dim3(grid_for(N)), dim3(256), 0, s, N,
+                                (const float *)values_in, perm_out, y64);
+    if (y32) hipLaunchKernelGGL((k_gather_val<float, float>), dim3(grid_for(N)), dim3(256), 0, s, N,
+                                (const float *)values_in, perm_out, y32);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipStreamSynchronize(s);
+}
+
 __global__ void k_invert_perm(long long N, const int *__restrict__ perm, int *__restrict__ pos) {
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (long long)gridDim.x * blockDim.x)
     pos[perm[p]] = (int)p;

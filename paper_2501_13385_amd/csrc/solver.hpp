@@ -38,6 +38,12 @@ size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage);
 hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main = nullptr);
 hipError_t launch_sampled_modes(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main = nullptr);
 size_t sampled_modes_lds_bytes(int R, int prec);
+hipError_t launch_sampled_chain(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main = nullptr);
+size_t chain_lds_bytes(int m, int u, const int *n, int R, int prec);
+// Stable grouping of Omega by the mixed-radix key of its first u mode indices
+// (mode 1 most significant); u = 0 copies it unchanged.
+hipError_t group_by_prefix(int m, long long N, int u, const int *n, const int *idx_in, const void *values_in,
+                           int values_fp64, int *idx_out, double *y64, float *y32, hipStream_t s);
 // one PRGD iteration for every member of the batch (sampled pass, dense stage,
 // truth sweep where a member has truth cores)
 hipError_t enqueue_batch_iterations(const Batch &bt, int iters, hipStream_t s);

