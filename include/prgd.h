@@ -287,6 +287,26 @@ prgd_status prgd_spectral_init(int32_t m, const int32_t *n, const int32_t *r, in
                                const int32_t *indices, const double *values, int32_t sketch,
                                const double *gauss, double *cores_out, void *stream);
 
+/* prgd_eval for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+   same values as prgd_eval with mem_device = 1, computed by the same kernel,
+   but every argument is device memory and nothing is allocated.
+     cores_dev    device float64, packed like prgd_eval's cores
+     indices_dev  device int32 SoA [m * n_obs]; indices must be in range (not
+                  checked: checking would need a copy to the host)
+     out_dev      device float64 [n_obs]
+     stream       hipStream_t or NULL; the work is queued on it and the call
+                  returns at once (no synchronisation): out_dev is valid once
+                  the stream has reached this point.
+   The padded cores are staged in a fixed 4 MiB workspace that each GPU holds
+   for the life of the process: sum_k n_k R^2 + 64 <= 2^19 doubles, R the
+   largest TT rank padded up to 2, 4, 6, 8, 10, 12 or 16, else PRGD_ENOMEM.
+   Calls that overlap on one GPU (two streams, two threads) share that
+   workspace and race; serialise them.  Errors: PRGD_EINVAL, PRGD_ENOTSUP
+   (ranks above 16), PRGD_ENOMEM (workspace too small), PRGD_EDEVICE. */
+prgd_status prgd_eval_noalloc(int32_t m, const int32_t *n, const int32_t *r, const double *cores_dev,
+                              int64_t n_obs, const int32_t *indices_dev, double *out_dev, void *stream);
+
 prgd_status prgd_destroy(prgd_solver s);
 
 /* ------------------------------------------------------------------------

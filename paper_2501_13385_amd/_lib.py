@@ -126,6 +126,7 @@ def load() -> C.CDLL:
         "prgd_sampled_pass": (i32, [vp, dp, dp, dp]),
         "prgd_eval": (i32, [i32, i32p, i32p, dp, i64, vp, vp, i32, vp]),
         "prgd_spectral_init": (i32, [i32, i32p, i32p, i64, vp, vp, i32, vp, vp, vp]),
+        "prgd_eval_noalloc": (i32, [i32, i32p, i32p, vp, i64, vp, vp, vp]),
         "prgd_destroy": (i32, [vp]),
         "prgd_status_str": (C.c_char_p, [i32]),
         "prgd_last_error": (C.c_char_p, []),
@@ -148,7 +149,7 @@ def exported_symbols() -> List[str]:
     return [n for n in ("prgd_cores_numel", "prgd_create", "prgd_iterate", "prgd_iterate_profiled", "prgd_iterate_timed",
                         "prgd_sync", "prgd_run",
                         "prgd_get_report", "prgd_get_cores", "prgd_get_history", "prgd_sampled_pass",
-                        "prgd_eval", "prgd_spectral_init", "prgd_destroy", "prgd_status_str",
+                        "prgd_eval", "prgd_eval_noalloc", "prgd_spectral_init", "prgd_destroy", "prgd_status_str",
                         "prgd_last_error",
                         "prgd_server_create", "prgd_server_submit", "prgd_server_poll", "prgd_server_wait",
                         "prgd_server_stats", "prgd_server_destroy")]
@@ -387,6 +388,17 @@ def prgd_eval(shape, ranks, cores, indices, out=None, stream=None):
     _check(lib.prgd_eval(m, _i32arr(shape), _i32arr(ranks), flat.ctypes.data_as(C.POINTER(C.c_double)),
                          n_obs, idx.ctypes.data, res.ctypes.data, 0, stream))
     return res
+
+
+def prgd_eval_noalloc(shape, ranks, cores_dev, indices_dev, out_dev, stream=None) -> None:
+    """prgd_eval on device memory without allocating: ``cores_dev`` (packed float64),
+    ``indices_dev`` (m, N) int32 and ``out_dev`` (N,) float64 are torch CUDA tensors.
+    Queues the work on ``stream`` (a hipStream_t handle or None) and returns."""
+    lib = load()
+    m = len(shape)
+    n_obs = int(indices_dev.shape[1])
+    _check(lib.prgd_eval_noalloc(m, _i32arr(shape), _i32arr(ranks), int(cores_dev.data_ptr()), n_obs,
+                                 int(indices_dev.data_ptr()), int(out_dev.data_ptr()), stream))
 
 
 def prgd_destroy(h) -> None:
