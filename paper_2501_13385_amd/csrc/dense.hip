@@ -69,8 +69,8 @@ __device__ inline void zero_grad(const Dev &d, long long i) {
 }
 
 // core index and slice range of this block for slice-parallel kernels over all cores
-__device__ inline void block_core(const Dev &d, int &c, int &x0, int &x1) {
-  const int b = blockIdx.x;
+__device__ inline void block_core(const Dev &d, int bx, int &c, int &x0, int &x1) {
+  const int b = bx;
   c = 0;
   while (c + 1 < d.m && d.blk_off[c + 1] <= b) ++c;
   const int lb = b - d.blk_off[c];
@@ -88,15 +88,16 @@ __device__ inline void block_core(const Dev &d, int &c, int &x0, int &x1) {
 // ---------------------------------------------------------------------------
 // blocks [0, nbL): core j-1 -> GL_j and Theta_{j-1}
 // blocks [nbL, nbL+nbH): core m-j -> H_{m-j}
-__global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j) {
-  const Dev &d = dt[blockIdx.y];
+__device__ __forceinline__ void gram_body(const Dev &d, int bx_, int j, double *smem_) {
+  (void)bx_;
+  (void)smem_;
   const int R = d.R, RR = R * R, m = d.m;
   const int nbL = nblocks_for(d.n[j - 1], 8), nbH = nblocks_for(d.n[m - j], 8);
-  if ((int)blockIdx.x >= nbL + nbH || d.st->done) return;
-  __shared__ double smem[SMEM];
-  const bool left = (int)blockIdx.x < nbL;
+  if (bx_ >= nbL + nbH || d.st->done) return;
+  double *smem = smem_;
+  const bool left = bx_ < nbL;
   const int c = left ? j - 1 : m - j;
-  const int lb = left ? (int)blockIdx.x : (int)blockIdx.x - nbL;
+  const int lb = left ? bx_ : bx_ - nbL;
   const int nbk = left ? nbL : nbH;
   const int per = (d.n[c] + nbk - 1) / nbk;
   const int x0 = lb * per;
@@ -191,11 +192,17 @@ __global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j
   }
 }
 
-// finish of a Gram sweep step (one block): totals and inverses
-__global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, int j) {
-  const Dev &d = dt[blockIdx.y];
-  if (d.st->done) return;
+__global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j) {
   __shared__ double smem[SMEM];
+  gram_body(dt[blockIdx.y], (int)blockIdx.x, j, smem);
+}
+
+// finish of a Gram sweep step (one block): totals and inverses
+__device__ __forceinline__ void gram_fin_body(const Dev &d, int bx_, int j, double *smem_) {
+  (void)bx_;
+  (void)smem_;
+  if (d.st->done) return;
+  double *smem = smem_;
   const int R = d.R, RR = R * R, m = d.m;
   const int nbL = nblocks_for(d.n[j - 1], 8), nbT = nbL + nblocks_for(d.n[m - j], 8);
 
@@ -228,15 +235,21 @@ __global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, i
   }
 }
 
+__global__ void __launch_bounds__(1024) k_gram_fin(const Dev *__restrict__ dt, int j) {
+  __shared__ double smem[SMEM];
+  gram_fin_body(dt[blockIdx.y], (int)blockIdx.x, j, smem);
+}
+
 // ---------------------------------------------------------------------------
 // tangent components X_c(x) (all cores, slice-parallel); clears Y
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_tangent(const Dev *__restrict__ dt) {
-  const Dev &d = dt[blockIdx.y];
-  if ((int)blockIdx.x >= d.blk_off[d.m] || d.st->done) return;
-  __shared__ double smem[SMEM];
+__device__ __forceinline__ void tangent_body(const Dev &d, int bx_, double *smem_) {
+  (void)bx_;
+  (void)smem_;
+  if (bx_ >= d.blk_off[d.m] || d.st->done) return;
+  double *smem = smem_;
   int c, x0, x1;
-  block_core(d, c, x0, x1);
+  block_core(d, bx_, c, x0, x1);
   const int R = d.R, RR = R * R, m = d.m;
   double *GI = smem, *HI = smem + RR, *PS = smem + 2 * RR;
   // Psi_c = GL_{c+1}^{-1} Theta_c H_{c+1}^{-1} (zero for the last core), formed
@@ -301,6 +314,11 @@ __global__ void __launch_bounds__(1024) k_tangent(const Dev *__restrict__ dt) {
   }
 }
 
+__global__ void __launch_bounds__(1024) k_tangent(const Dev *__restrict__ dt) {
+  __shared__ double smem[SMEM];
+  tangent_body(dt[blockIdx.y], (int)blockIdx.x, smem);
+}
+
 // ---------------------------------------------------------------------------
 // tangent components with the three R x R contractions per slice on the
 // matrix cores in bfloat16 (float32 accumulation), one wave per slice
@@ -330,13 +348,14 @@ __device__ __forceinline__ double unit_scale(double amax) {
 // formed transposed, (GL^{-1} Y)^T = Y^T GL^{-T}, so that its result lands in
 // the A-operand layout of the second.  Scales: one power of two per core for
 // GL^{-1}, H^{-1} and Psi, one per slice for Y(x), T(x) and GL^{-1} Y(x).
-__global__ void __launch_bounds__(1024) k_tangent_bf16(const Dev *__restrict__ dt) {
-  const Dev &d = dt[blockIdx.y];
-  if ((int)blockIdx.x >= d.blk_off[d.m] || d.st->done) return;
-  __shared__ double smem[6 * RMAX * RMAX];
+__device__ __forceinline__ void tangent_bf16_body(const Dev &d, int bx_, double *smem_) {
+  (void)bx_;
+  (void)smem_;
+  if (bx_ >= d.blk_off[d.m] || d.st->done) return;
+  double *smem = smem_;
   __shared__ double samax[32];
   int c, x0, x1;
-  block_core(d, c, x0, x1);
+  block_core(d, bx_, c, x0, x1);
   const int R = d.R, RR = R * R, m = d.m;
   double *GI = smem, *HI = smem + RR, *PS = smem + 2 * RR;
   double *G1 = smem + 3 * RR, *TH = G1 + RR, *T1 = TH + RR;
@@ -435,6 +454,11 @@ __global__ void __launch_bounds__(1024) k_tangent_bf16(const Dev *__restrict__ d
   }
 }
 
+__global__ void __launch_bounds__(1024) k_tangent_bf16(const Dev *__restrict__ dt) {
+  __shared__ double smem[SMEM];
+  tangent_bf16_body(dt[blockIdx.y], (int)blockIdx.x, smem);
+}
+
 // block core C_c(x) of W_l = T_l - alpha xi as a 2R x 2R matrix in LDS
 __device__ inline void build_block(const Dev &d, int c, const double *sT, const double *sX, double alpha,
                                    double *C, int tl, int tpg) {
@@ -516,20 +540,21 @@ __device__ void gram_first_cut(const Dev &d, int lb) {
   }
 }
 
-__global__ void __launch_bounds__(1024) k_rgram(const Dev *__restrict__ dt, int b) {
-  const Dev &d = dt[blockIdx.y];
+__device__ __forceinline__ void rgram_body(const Dev &d, int bx_, int b, double *smem_) {
+  (void)bx_;
+  (void)smem_;
   const int nb = nblocks_for(d.n[b], 4);
   const int m = d.m;
   if (d.st->done) return;
-  if ((int)blockIdx.x >= nb) {
-    const int lb = (int)blockIdx.x - nb;
+  if (bx_ >= nb) {
+    const int lb = bx_ - nb;
     if (b == m - 1 && lb < nblocks_for(d.n[0], 4)) gram_first_cut(d, lb);
     return;
   }
-  __shared__ double smem[SMEM];
+  double *smem = smem_;
   const int R = d.R, R2 = 2 * R, NE = R2 * R2;
   const int per = (d.n[b] + nb - 1) / nb;
-  const int x0 = blockIdx.x * per, x1 = min(d.n[b], x0 + per);
+  const int x0 = bx_ * per, x1 = min(d.n[b], x0 + per);
   const double alpha = d.st->alpha_n;
   double *GN = smem;   // GR_{b+1}
   const double *gn = sm_slot(d, b + 1, S_GR);
@@ -592,7 +617,7 @@ __global__ void __launch_bounds__(1024) k_rgram(const Dev *__restrict__ dt, int 
     for (int t = q.tl; t < NE; t += q.TPG, ++u) red[q.g * NE + t] = acc[u];
   }
   __syncthreads();
-  auto mypart = glb(d.part) + (long long)blockIdx.x * (R2 * (R2 + 1) / 2);
+  auto mypart = glb(d.part) + (long long)bx_ * (R2 * (R2 + 1) / 2);
   for (int t = threadIdx.x; t < NE; t += blockDim.x) {
     const int a = t / R2, bb = t - a * R2;
     if (a > bb) continue;
@@ -602,12 +627,18 @@ __global__ void __launch_bounds__(1024) k_rgram(const Dev *__restrict__ dt, int 
   }
 }
 
+__global__ void __launch_bounds__(1024) k_rgram(const Dev *__restrict__ dt, int b) {
+  __shared__ double smem[SMEM];
+  rgram_body(dt[blockIdx.y], (int)blockIdx.x, b, smem);
+}
+
 // finish of a right-Gram step (one block): total GR_b and its pivoted Cholesky factor
-__global__ void __launch_bounds__(1024) k_rgram_fin(const Dev *__restrict__ dt, int b) {
-  const Dev &d = dt[blockIdx.y];
+__device__ __forceinline__ void rgram_fin_body(const Dev &d, int bx_, int b, double *smem_) {
+  (void)bx_;
+  (void)smem_;
   const int nb = nblocks_for(d.n[b], 4);
   if (d.st->done) return;
-  __shared__ double smem[SMEM];
+  double *smem = smem_;
   const int R = d.R, R2 = 2 * R, NE = R2 * R2;
 
   double *GR = sm_slot(d, b, S_GR);
@@ -641,17 +672,23 @@ __global__ void __launch_bounds__(1024) k_rgram_fin(const Dev *__restrict__ dt, 
   }
 }
 
+__global__ void __launch_bounds__(1024) k_rgram_fin(const Dev *__restrict__ dt, int b) {
+  __shared__ double smem[SMEM];
+  rgram_fin_body(dt[blockIdx.y], (int)blockIdx.x, b, smem);
+}
+
 // ---------------------------------------------------------------------------
 // left sweep of the retraction, cut i = 1..m-1 (core c = i-1)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i) {
-  const Dev &d = dt[blockIdx.y];
+__device__ __forceinline__ void left_body(const Dev &d, int bx_, int i, double *smem_) {
+  (void)bx_;
+  (void)smem_;
   const int nb = nblocks_for(d.n[i - 1], 4);
-  if ((int)blockIdx.x >= nb || d.st->done) return;
-  __shared__ double smem[SMEM];
+  if (bx_ >= nb || d.st->done) return;
+  double *smem = smem_;
   const int R = d.R, R2 = 2 * R, NE = R2 * R2, m = d.m, c = i - 1;
   const int per = (d.n[c] + nb - 1) / nb;
-  const int x0 = blockIdx.x * per, x1 = min(d.n[c], x0 + per);
+  const int x0 = bx_ * per, x1 = min(d.n[c], x0 + per);
   const double alpha = d.st->alpha_n;
   double *P = smem;    // R x 2R
   const double *ps = sm_slot(d, c, S_P);
@@ -714,7 +751,7 @@ __global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i
     for (int t = q.tl; t < NE; t += q.TPG, ++u) red[q.g * NE + t] = acc[u];
   }
   __syncthreads();
-  auto mypart = glb(d.part) + (long long)blockIdx.x * (R2 * (R2 + 1) / 2);
+  auto mypart = glb(d.part) + (long long)bx_ * (R2 * (R2 + 1) / 2);
   for (int t = threadIdx.x; t < NE; t += blockDim.x) {
     const int a = t / R2, bb = t - a * R2;
     if (a > bb) continue;
@@ -722,6 +759,11 @@ __global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i
     for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
     mypart[sym_index(a, bb, R2)] = v;
   }
+}
+
+__global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i) {
+  __shared__ double smem[SMEM];
+  left_body(dt[blockIdx.y], (int)blockIdx.x, i, smem);
 }
 
 // finish of a left-sweep cut (one block): S = F^T (B^T B) F, eigen-decomposition,
@@ -809,25 +851,32 @@ __device__ __forceinline__ void left_cut(const Dev &d, int i, double *smem) {
   }
 }
 
-__global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, int i) {
-  const Dev &d = dt[blockIdx.y];
+__device__ __forceinline__ void left_fin_body(const Dev &d, int bx_, int i, double *smem_) {
+  (void)bx_;
+  (void)smem_;
   const int nb = nblocks_for(d.n[i - 1], 4);
   if (d.st->done) return;
-  __shared__ double smem[SMEM];
+  double *smem = smem_;
   reduce_sym_partials(d.part, nb, 2 * d.R, smem, smem + 5120, smem + 1024);
   left_cut(d, i, smem);
+}
+
+__global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, int i) {
+  __shared__ double smem[SMEM];
+  left_fin_body(dt[blockIdx.y], (int)blockIdx.x, i, smem);
 }
 
 // ---------------------------------------------------------------------------
 // output: new cores T'_c(x) = P_c C_c(x) Tr_{c+1} (c < m-1), P_{m-1} C_{m-1}(x);
 // stop-test reductions ||T'||^2 = ||T'_{m-1}||^2 and <T', T>
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_output(const Dev *__restrict__ dt, int init) {
-  const Dev &d = dt[blockIdx.y];
-  if ((int)blockIdx.x >= d.blk_off[d.m] || d.st->done) return;
-  __shared__ double smem[SMEM];
+__device__ __forceinline__ void output_body(const Dev &d, int bx_, int init, double *smem_) {
+  (void)bx_;
+  (void)smem_;
+  if (bx_ >= d.blk_off[d.m] || d.st->done) return;
+  double *smem = smem_;
   int c, x0, x1;
-  block_core(d, c, x0, x1);
+  block_core(d, bx_, c, x0, x1);
   const int R = d.R, R2 = 2 * R, m = d.m, RR = R * R;
   const double alpha = d.st->alpha_n;
   double *P = smem;                  // R x 2R
@@ -921,14 +970,20 @@ __global__ void __launch_bounds__(1024) k_output(const Dev *__restrict__ dt, int
   nn = block_sum(nn, sbuf);
   cr = block_sum(cr, sbuf);
   if (threadIdx.x == 0) {
-    glb(d.part)[2 * blockIdx.x] = nn;
-    glb(d.part)[2 * blockIdx.x + 1] = cr;
+    glb(d.part)[2 * bx_] = nn;
+    glb(d.part)[2 * bx_ + 1] = cr;
   }
 }
 
+__global__ void __launch_bounds__(1024) k_output(const Dev *__restrict__ dt, int init) {
+  __shared__ double smem[SMEM];
+  output_body(dt[blockIdx.y], (int)blockIdx.x, init, smem);
+}
+
 // finish of the output step (one block): relative change, iteration count, stop test
-__global__ void __launch_bounds__(1024) k_output_fin(const Dev *__restrict__ dt, int init) {
-  const Dev &d = dt[blockIdx.y];
+__device__ __forceinline__ void output_fin_body(const Dev &d, int bx_, int init, double *smem_) {
+  (void)bx_;
+  (void)smem_;
   const int nb = d.blk_off[d.m];
   if (d.st->done) return;
   __shared__ double sbuf[32];
@@ -965,18 +1020,23 @@ __global__ void __launch_bounds__(1024) k_output_fin(const Dev *__restrict__ dt,
   }
 }
 
+__global__ void __launch_bounds__(1024) k_output_fin(const Dev *__restrict__ dt, int init) {
+  output_fin_body(dt[blockIdx.y], (int)blockIdx.x, init, nullptr);
+}
+
 // ---------------------------------------------------------------------------
 // cross Gram sweep with the truth: Z_{c+1} = sum_x A_c(x)^T Z_c B_c(x)
 // mode 0: A = iterate, B = truth (relative error); mode 1: A = B = truth (||T*||^2)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_cross(const Dev *__restrict__ dt, int c, int mode) {
-  const Dev &d = dt[blockIdx.y];
+__device__ __forceinline__ void cross_body(const Dev &d, int bx_, int c, int mode, double *smem_) {
+  (void)bx_;
+  (void)smem_;
   const int nb = nblocks_for(d.n[c], 4);
-  if ((int)blockIdx.x >= nb || !d.has_truth || (mode == 0 && !d.st->upd)) return;
-  __shared__ double smem[SMEM];
+  if (bx_ >= nb || !d.has_truth || (mode == 0 && !d.st->upd)) return;
+  double *smem = smem_;
   const int R = d.R, RR = R * R, m = d.m;
   const int per = (d.n[c] + nb - 1) / nb;
-  const int x0 = blockIdx.x * per, x1 = min(d.n[c], x0 + per);
+  const int x0 = bx_ * per, x1 = min(d.n[c], x0 + per);
   const double *Acore = (mode == 0) ? d.cores : d.truth;
   double *Z = smem;
   const double *zs = sm_slot(d, c, S_ZT);
@@ -1013,7 +1073,7 @@ __global__ void __launch_bounds__(1024) k_cross(const Dev *__restrict__ dt, int 
   __syncthreads();
   if (q.g < q.G && e < RR) red[q.g * RR + e] = acc;
   __syncthreads();
-  auto mypart = glb(d.part) + (long long)blockIdx.x * RR;
+  auto mypart = glb(d.part) + (long long)bx_ * RR;
   for (int t = threadIdx.x; t < RR; t += blockDim.x) {
     double v = 0.0;
     for (int g = 0; g < q.G; ++g) v += red[g * RR + t];
@@ -1021,12 +1081,18 @@ __global__ void __launch_bounds__(1024) k_cross(const Dev *__restrict__ dt, int 
   }
 }
 
+__global__ void __launch_bounds__(1024) k_cross(const Dev *__restrict__ dt, int c, int mode) {
+  __shared__ double smem[SMEM];
+  cross_body(dt[blockIdx.y], (int)blockIdx.x, c, mode, smem);
+}
+
 // finish of a cross-Gram step (one block)
-__global__ void __launch_bounds__(1024) k_cross_fin(const Dev *__restrict__ dt, int c, int mode) {
-  const Dev &d = dt[blockIdx.y];
+__device__ __forceinline__ void cross_fin_body(const Dev &d, int bx_, int c, int mode, double *smem_) {
+  (void)bx_;
+  (void)smem_;
   const int nb = nblocks_for(d.n[c], 4);
   if (!d.has_truth || (mode == 0 && !d.st->upd)) return;
-  __shared__ double smem[SMEM];
+  double *smem = smem_;
   const int R = d.R, RR = R * R, m = d.m;
   double *Zn = sm_slot(d, c + 1, S_ZT);
   reduce_partials(d.part, nb, RR, smem + 1024, smem);
@@ -1053,6 +1119,11 @@ __global__ void __launch_bounds__(1024) k_cross_fin(const Dev *__restrict__ dt, 
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(1024) k_cross_fin(const Dev *__restrict__ dt, int c, int mode) {
+  __shared__ double smem[SMEM];
+  cross_fin_body(dt[blockIdx.y], (int)blockIdx.x, c, mode, smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -192,7 +192,7 @@ __host__ __device__ inline int chain_nx(int R) {
 // LDS stride of one staged slice: R^2 plus 16 bytes, so that the slices of a
 // core start on different banks
 __host__ __device__ inline int chain_slice_stride(int R, int fbytes) { return R * R + 16 / fbytes; }
-__host__ __device__ inline int chain_slot_width(int R) { return R * 67 + (R == 2 ? 2 : 0); }
+__host__ __device__ inline int chain_slot_width(int R) { return R * 68; }
 // width of one chunk's partial (elements): tiles, slice sums, uniform gradients
 __host__ __device__ inline int chain_part_width(int m, int u, int R) {
   const int nc = m - u;

@@ -83,10 +83,42 @@ __device__ __forceinline__ double cbcast(double v) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-__device__ __forceinline__ void chain_wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+// Order of LDS accesses among the lanes of one wave.  A wave's LDS operations
+// are performed in issue order, so a store by one lane is seen by a later load
+// of another lane of the same wave; only the compiler must not move memory
+// operations across this point (no wait on the LDS counter is needed).
+__device__ __forceinline__ void chain_wave_order() {
   __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __asm__ __volatile__("" ::: "memory");
+}
+
+// value of lane l ^ 32 (v_permlane32_swap; whole wave active)
+__device__ __forceinline__ int xor32(int v, int lane) {
+  const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  // [0] holds the lower half's values in both halves, [1] the upper half's
+  return (lane & 32) ? (int)p[0] : (int)p[1];
+}
+// value of lane l ^ 16 (v_permlane16_swap; whole wave active)
+__device__ __forceinline__ int xor16(int v, int lane) {
+  const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  // [0] holds rows (0, 0, 2, 2) of the input, [1] rows (1, 1, 3, 3)
+  return (lane & 16) ? (int)p[0] : (int)p[1];
+}
+template <int OFF>
+__device__ __forceinline__ int xor_lane(int v, int lane) {
+  if constexpr (OFF == 32) return xor32(v, lane);
+  else if constexpr (OFF == 16) return xor16(v, lane);
+  else return __shfl_xor(v, OFF, 64);
+}
+template <int OFF>
+__device__ __forceinline__ float xor_lane(float v, int lane) {
+  return __int_as_float(xor_lane<OFF>(__float_as_int(v), lane));
+}
+template <int OFF>
+__device__ __forceinline__ double xor_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = xor_lane<OFF>((int)b, lane), hi = xor_lane<OFF>((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // Sizes shared by the host plan and the kernel.
@@ -96,54 +128,64 @@ struct ChainShape {
   static constexpr int XH = 16 / R;                          // slice values per tile side
   static constexpr int NX = XH * XH < 16 ? XH * XH : 16;     // slice values per core
   static constexpr int TILE = 256;
-  // staging slot: 64 samples x R values; sample s at R (s + s / 16), so that
-  // the four samples of a K-step (one per group of 16) and their R values
-  // fall on distinct banks
-  static constexpr int SLOTW = R * 67 + (R == 2 ? 2 : 0);
+  // staging slot: R rows of 64 samples, value a of sample s at
+  // a * 68 + s + s / 16: a wave's row store is consecutive, and the four
+  // samples of a K-step (one per group of 16) with their R values spread over
+  // the banks
+  static constexpr int SP = 68;
+  static constexpr int SLOTW = R * SP;
 };
 
 // Sum of v over the lanes whose index agrees in the top log2(NX) bits after
 // a reduce-scatter of the one-hot vector (v at slot x) across the wave:
 // returns, in lane l, the sum of v over the lanes {l ^ t} (t over the top
 // bits) whose x equals l >> (6 - log2 NX).
+template <typename F, int NX, int H, int OFF>
+__device__ __forceinline__ void scatter_halve(F (&kept)[NX / 2], int lane) {
+  if constexpr (H > 1) {
+    const bool hb = (lane & OFF) != 0;
+#pragma unroll
+    for (int i = 0; i < H / 2; ++i) {
+      const F send = hb ? kept[i] : kept[H / 2 + i];
+      const F recv = xor_lane<OFF>(send, lane);
+      kept[i] = (hb ? kept[H / 2 + i] : kept[i]) + recv;
+    }
+    scatter_halve<F, NX, H / 2, OFF / 2>(kept, lane);
+  }
+}
+
 template <typename F, int NX>
 __device__ __forceinline__ F slice_scatter(F v, int x, int lane) {
   constexpr int H0 = NX / 2;
-  const F vp = __shfl_xor(v, 32, 64);
-  const int xp = __shfl_xor(x, 32, 64);
+  const F vp = xor_lane<32>(v, lane);
+  const int xp = xor_lane<32>(x, lane);
   const int base = (lane & 32) ? H0 : 0;
   F kept[H0];
 #pragma unroll
   for (int i = 0; i < H0; ++i) kept[i] = (x == base + i ? v : (F)0) + (xp == base + i ? vp : (F)0);
-#pragma unroll
-  for (int H = H0, off = 16; H > 1; H >>= 1, off >>= 1) {
-    const bool hb = (lane & off) != 0;
-#pragma unroll
-    for (int i = 0; i < H / 2; ++i) {
-      const F send = hb ? kept[i] : kept[H / 2 + i];
-      const F recv = __shfl_xor(send, off, 64);
-      kept[i] = (hb ? kept[H / 2 + i] : kept[i]) + recv;
-    }
-  }
+  scatter_halve<F, NX, H0, 16>(kept, lane);
   return kept[0];
 }
 
-// the operands of one K-step S for core c and the MFMA
-template <typename F, int R, int S>
+// One K-step S of a core's gradient tile: the four samples 16 q + S.  AM: A
+// from the uniform l_{u+1} (0) or the staged l_k (1); BM: B from the parked
+// r_{k+1} (0), from column 0 of the last core's slice (1) or e_1 (2).
+template <typename F, int R, int S, int AM, int BM>
 __device__ __forceinline__ void chain_kstep(typename MmaC<F>::acc_t &acc, int xc, int xl, F res, F lamA,
-                                            const F *stg, bool stg_ok, const F *bsl, int bmode, const F *tlast,
-                                            int SL, F bE, int lane) {
+                                            const F *stg, const F *bsl, const F *tlast, int SL, F bE, int lane) {
   constexpr int XH = 16 / R;
   const int q = lane >> 4, i = lane & 15, a = i % R, h = i / R;
   const int s = 16 * q + S;
   const int xs = cbcast<S>(xc);
   const F rs = cbcast<S>(res);
-  F av = stg_ok ? stg[R * (s + q) + a] : lamA;
+  F av;
+  if constexpr (AM == 0) av = lamA;
+  else av = stg[a * 68 + s + q];
   av = (xs / XH == h) ? av : (F)0;
   F bv;
-  if (bmode == 0) {
-    bv = bsl[R * (s + q) + a];
-  } else if (bmode == 1) {
+  if constexpr (BM == 0) {
+    bv = bsl[a * 68 + s + q];
+  } else if constexpr (BM == 1) {
     const int xls = cbcast<S>(xl);
     bv = tlast[xls * SL + a * R];
   } else {
@@ -153,11 +195,105 @@ __device__ __forceinline__ void chain_kstep(typename MmaC<F>::acc_t &acc, int xc
   acc = MmaC<F>::step(av, bv, acc);
 }
 
-template <typename F, int R, int... S>
+template <typename F, int R, int AM, int BM, int... S>
 __device__ __forceinline__ void chain_mfma(typename MmaC<F>::acc_t &acc, int xc, int xl, F res, F lamA,
-                                           const F *stg, bool stg_ok, const F *bsl, int bmode, const F *tlast,
-                                           int SL, F bE, int lane, std::integer_sequence<int, S...>) {
-  (chain_kstep<F, R, S>(acc, xc, xl, res, lamA, stg, stg_ok, bsl, bmode, tlast, SL, bE, lane), ...);
+                                           const F *stg, const F *bsl, const F *tlast, int SL, F bE, int lane,
+                                           std::integer_sequence<int, S...>) {
+  (chain_kstep<F, R, S, AM, BM>(acc, xc, xl, res, lamA, stg, bsl, tlast, SL, bE, lane), ...);
+}
+
+// 16-byte LDS vector of the working precision
+template <typename F>
+struct V16;
+template <>
+struct V16<double> {
+  typedef double t __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+template <>
+struct V16<float> {
+  typedef float t __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+
+// G rows of the slice at sl (row-major R x R, 16-byte aligned) into registers,
+// all loads issued before any is used
+template <typename F, int R, int G>
+__device__ __forceinline__ void load_rows(F (&rows)[G][R], const F *sl, int a0) {
+  typedef typename V16<F>::t VT;
+  constexpr int VN = V16<F>::n;
+  if constexpr (R % VN == 0) {
+    const VT *v = reinterpret_cast<const VT *>(sl + a0 * R);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int b = 0; b < R / VN; ++b) {
+        const VT t = v[g * (R / VN) + b];
+#pragma unroll
+        for (int e = 0; e < VN; ++e) rows[g][b * VN + e] = t[e];
+      }
+  } else {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int b = 0; b < R; ++b) rows[g][b] = sl[(a0 + g) * R + b];
+  }
+}
+
+// rows per load group: enough loads in flight, bounded registers
+template <typename F, int R>
+struct RowGroup {
+  static constexpr int G = (R * (int)sizeof(F) * 4 <= 128 ? R : (R * (int)sizeof(F) <= 64 ? 4 : 2));
+};
+
+// l <- l T(x) for one sample per lane, T the slice at sl (row-major R x R)
+template <typename F, int R>
+__device__ __forceinline__ void chain_left_step(F (&lam)[R], const F *sl) {
+  constexpr int G = RowGroup<F, R>::G;
+  F nl[R];
+#pragma unroll
+  for (int b = 0; b < R; ++b) nl[b] = (F)0;
+#pragma unroll
+  for (int a0 = 0; a0 < R; a0 += G) {
+    F rows[G][R];
+    load_rows<F, R, G>(rows, sl, a0);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int b = 0; b < R; ++b) nl[b] = fma(lam[a0 + g], rows[g][b], nl[b]);
+  }
+#pragma unroll
+  for (int b = 0; b < R; ++b) lam[b] = nl[b];
+}
+
+// r <- T(x) r
+template <typename F, int R>
+__device__ __forceinline__ void chain_right_step(F (&rho)[R], const F *sl) {
+  constexpr int G = RowGroup<F, R>::G;
+  F nr[R];
+#pragma unroll
+  for (int a0 = 0; a0 < R; a0 += G) {
+    F rows[G][R];
+    load_rows<F, R, G>(rows, sl, a0);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      F t = (F)0;
+#pragma unroll
+      for (int b = 0; b < R; ++b) t = fma(rows[g][b], rho[b], t);
+      nr[a0 + g] = t;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < R; ++a) rho[a] = nr[a];
+}
+
+// Sum of v over the lanes that share lane's top log2(NX) bits (after
+// slice_scatter every such lane holds a part of the same slice's sum).
+template <typename F, int NX>
+__device__ __forceinline__ F slice_finish(F v, int lane) {
+#pragma unroll
+  for (int o = 64 / NX / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
 template <typename F, int R, int MAXC, int NW>
@@ -189,7 +325,13 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
   }
   const int lo_last = lo - d.n[m - 1] * SL;
   const int nslots = chain_nslots(nc);
-  F *wsl = lc + lo + (long long)w * nslots * SLOTW;
+  const int WT = nc * 256, WS = nc * NX;
+  const int WR = WT + WS;                                   // end-of-chunk sums per wave
+  const int region = nslots * SLOTW > WR ? nslots * SLOTW : WR;
+  F *wsl = lc + lo + (long long)w * region;
+  F *wss = lc + lo + (long long)NW * region + (long long)w * WS;   // this wave's slice sums
+  F *lamu_s = lc + lo + (long long)NW * region + (long long)NW * WS;   // l_{u+1}, shared
+  for (int i = lane; i < WS; i += 64) wss[i] = (F)0;
   for (int c = 0; c < nc; ++c) {
     const int k = u + c, nk = d.n[k];
     int base = 0;
@@ -215,151 +357,195 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
 #pragma unroll
     for (int b = 0; b < R; ++b) lamu[b] = nl[b];
   }
-  const int iA = lane & 15, aA = iA % R;
-  F lamA = (F)0;
+  if (threadIdx.x < R) {
+    F v = (F)0;
 #pragma unroll
-  for (int a = 0; a < R; ++a)
-    if (a == aA) lamA = lamu[a];
+    for (int a = 0; a < R; ++a)
+      if (a == (int)threadIdx.x) v = lamu[a];
+    lamu_s[threadIdx.x] = v;
+  }
+  // e_1 in the MFMA lane layout: the A operand of core u+1 (whose tile then
+  // holds G_x = sum R_j r_{u+2}; l_{u+1} is applied once per chunk) and the B
+  // operand of the last core (r_{m+1} = e_1)
+  const int aA = (lane & 15) % R;
   const F bE = aA == 0 ? (F)1 : (F)0;
+  const F lamA = bE;
   __syncthreads();
 
-  typename M::acc_t acc[MAXC];
-  F ssacc[MAXC];
+  // generic cores c = 0 .. nc-3 (core u + c): B from the parked r_{k+1};
+  // core nc-2: B from column 0 of the last core's slice; core nc-1: B = e_1
+  constexpr int MG = MAXC - 2;
+  typename M::acc_t acc[MG > 0 ? MG : 1];
 #pragma unroll
-  for (int c = 0; c < MAXC; ++c) {
-    acc[c] = M::zero();
-    ssacc[c] = (F)0;
-  }
-  F vacc[R];
-#pragma unroll
-  for (int a = 0; a < R; ++a) vacc[a] = (F)0;
+  for (int c = 0; c < MG; ++c) acc[c] = M::zero();
+  typename M::acc_t accP = M::zero(), accL = M::zero();
   double rsq = 0.0;
   const F *tlast = lc + lo_last;
+  const int lo_pen = nc >= 2 ? lo_last - d.n[m - 2] * SL : 0;
+  const int ng = nc - 2;                  // generic cores (may be <= 0)
+  const int stgP = nc - 2 >= 1 ? (nc - 3 < nslots - 1 ? nc - 3 : nslots - 1) : 0;   // staging slot of core nc-2
+  const int stgL = nc - 1 >= 1 ? (nc - 2 < nslots - 1 ? nc - 2 : nslots - 1) : 0;   // of core nc-1
   const int nbt = (cl + 63) >> 6;
   for (int bt = w; bt < nbt; bt += NW) {
     const int jj = bt * 64 + lane;
     const bool act = jj < cl;
     const long long j = (long long)cs + (act ? jj : 0);
-    int xk[MAXC];
+    int xk[MG > 0 ? MG : 1];
 #pragma unroll
-    for (int c = 0; c < MAXC; ++c) xk[c] = (c < nc && act) ? idx[(long long)(u + c) * N + j] : 0;
+    for (int c = 0; c < MG; ++c) xk[c] = (c < ng && act) ? idx[(long long)(u + c) * N + j] : 0;
     const int xl = act ? idx[(long long)(m - 1) * N + j] : 0;
+    const int xp = (nc >= 2 && act) ? idx[(long long)(m - 2) * N + j] : 0;
     const F yv = act ? y[j] : (F)0;
-    chain_wave_sync();   // the previous batch's reads of the slots are done
-    // right sweep: r_m = T_m(:, x_m, 0), then r_k = T_k(x_k) r_{k+1}; r_{k+1}
-    // of cores u+1..m-2 parked in slot c
+    chain_wave_order();   // the previous batch's reads of the slots come first
+    // right sweep: r_m = T_m(:, x_m, 0), r_{m-1} = T_{m-1}(x_{m-1}) r_m, then
+    // r_k = T_k(x_k) r_{k+1} parking r_{k+1} in slot c (k = u + c <= m-3)
     F rho[R];
 #pragma unroll
     for (int a = 0; a < R; ++a) rho[a] = tlast[xl * SL + a * R];
+    if (nc >= 2) chain_right_step<F, R>(rho, lc + lo_pen + xp * SL);
 #pragma unroll
-    for (int c = MAXC - 2; c >= 0; --c) {
-      if (c <= nc - 2) {
-        if (c <= nc - 3) {
-          F *dst = wsl + c * SLOTW + R * (lane + (lane >> 4));
+    for (int c = MG - 1; c >= 0; --c) {
+      if (c < ng) {
+        F *dst = wsl + c * SLOTW + lane + (lane >> 4);
 #pragma unroll
-          for (int a = 0; a < R; ++a) dst[a] = rho[a];
-        }
-        const F *sl = lc + loff[c] + xk[c] * SL;
-        F nr[R];
-#pragma unroll
-        for (int a = 0; a < R; ++a) {
-          F t = (F)0;
-#pragma unroll
-          for (int b = 0; b < R; ++b) t = fma(sl[a * R + b], rho[b], t);
-          nr[a] = t;
-        }
-#pragma unroll
-        for (int a = 0; a < R; ++a) rho[a] = nr[a];
+        for (int a = 0; a < R; ++a) dst[a * 68] = rho[a];
+        chain_right_step<F, R>(rho, lc + loff[c] + xk[c] * SL);
       }
     }
+    F lam[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) lam[a] = lamu_s[a];
     F t = (F)0;
 #pragma unroll
-    for (int a = 0; a < R; ++a) t = fma(lamu[a], rho[a], t);
+    for (int a = 0; a < R; ++a) t = fma(lam[a], rho[a], t);
     const F res = act ? t - yv : (F)0;
     const F r2 = res * res;
     rsq += (double)r2;
+    // slice sums: each wave adds one batch's per-slice totals to its table
+    // (lanes with low bits 0 hold them after the butterfly)
+    {
+      const bool lead = (lane & (64 / NX - 1)) == 0;
+      const int xs = lane / (64 / NX);
 #pragma unroll
-    for (int a = 0; a < R; ++a) vacc[a] = fma(res, rho[a], vacc[a]);
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c)
-      if (c < nc) ssacc[c] += slice_scatter<F, NX>(r2, xk[c], lane);
-    // left sweep with the gradient tiles
-    F lam[R];
-#pragma unroll
-    for (int a = 0; a < R; ++a) lam[a] = lamu[a];
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c) {
-      if (c < nc) {
-        F *stg = wsl + (c == 0 ? 0 : (c - 1 < nslots - 1 ? c - 1 : nslots - 1)) * SLOTW;
-        if (c >= 1) {
-          F *dst = stg + R * (lane + (lane >> 4));
-#pragma unroll
-          for (int a = 0; a < R; ++a) dst[a] = lam[a];
+      for (int c = 0; c < MG; ++c)
+        if (c < ng) {
+          const F v = slice_finish<F, NX>(slice_scatter<F, NX>(r2, xk[c], lane), lane);
+          if (lead) wss[c * NX + xs] += v;
         }
-        chain_wave_sync();
-        const int bmode = c <= nc - 3 ? 0 : (c == nc - 2 ? 1 : 2);
-        const F *bsl = wsl + (c <= nc - 3 ? c : 0) * SLOTW;
-        chain_mfma<F, R>(acc[c], xk[c], xl, res, lamA, stg, c >= 1, bsl, bmode, tlast, SL, bE, lane,
-                         std::make_integer_sequence<int, 16>{});
-        if (c < nc - 1) {
-          const F *sl = lc + loff[c] + xk[c] * SL;
-          F nl[R];
-#pragma unroll
-          for (int b = 0; b < R; ++b) nl[b] = (F)0;
-#pragma unroll
-          for (int a = 0; a < R; ++a)
-#pragma unroll
-            for (int b = 0; b < R; ++b) nl[b] = fma(lam[a], sl[a * R + b], nl[b]);
-#pragma unroll
-          for (int b = 0; b < R; ++b) lam[b] = nl[b];
-        }
-        chain_wave_sync();
+      if (nc >= 2) {
+        const F v = slice_finish<F, NX>(slice_scatter<F, NX>(r2, xp, lane), lane);
+        if (lead) wss[(nc - 2) * NX + xs] += v;
       }
+      const F v = slice_finish<F, NX>(slice_scatter<F, NX>(r2, xl, lane), lane);
+      if (lead) wss[(nc - 1) * NX + xs] += v;
+    }
+    // left sweep with the gradient tiles
+    chain_wave_order();   // the parked r_{k+1} before the tiles read them
+#pragma unroll
+    for (int c = 0; c < MG; ++c) {
+      if (c < ng) {
+        if (c == 0) {
+          chain_mfma<F, R, 0, 0>(acc[c], xk[c], xl, res, lamA, wsl, wsl + c * SLOTW, tlast, SL, bE, lane,
+                                 std::make_integer_sequence<int, 16>{});
+        } else {
+          F *stg = wsl + (c - 1) * SLOTW;   // r_{u+c} there was read by core c - 1
+          F *dst = stg + lane + (lane >> 4);
+#pragma unroll
+          for (int a = 0; a < R; ++a) dst[a * 68] = lam[a];
+          chain_wave_order();
+          chain_mfma<F, R, 1, 0>(acc[c], xk[c], xl, res, lamA, stg, wsl + c * SLOTW, tlast, SL, bE, lane,
+                                 std::make_integer_sequence<int, 16>{});
+        }
+        chain_wave_order();
+        chain_left_step<F, R>(lam, lc + loff[c] + xk[c] * SL);
+      }
+    }
+    if (nc >= 2) {   // core m-2
+      F *stg = wsl + stgP * SLOTW;
+      if (ng >= 1) {
+        F *dst = stg + lane + (lane >> 4);
+#pragma unroll
+        for (int a = 0; a < R; ++a) dst[a * 68] = lam[a];
+        chain_wave_order();
+        chain_mfma<F, R, 1, 1>(accP, xp, xl, res, lamA, stg, wsl, tlast, SL, bE, lane,
+                               std::make_integer_sequence<int, 16>{});
+      } else {
+        chain_mfma<F, R, 0, 1>(accP, xp, xl, res, lamA, stg, wsl, tlast, SL, bE, lane,
+                               std::make_integer_sequence<int, 16>{});
+      }
+      chain_wave_order();
+      chain_left_step<F, R>(lam, lc + lo_pen + xp * SL);
+    }
+    {   // core m-1
+      F *stg = wsl + stgL * SLOTW;
+      if (nc >= 2) {
+        F *dst = stg + lane + (lane >> 4);
+#pragma unroll
+        for (int a = 0; a < R; ++a) dst[a * 68] = lam[a];
+        chain_wave_order();
+        chain_mfma<F, R, 1, 2>(accL, xl, xl, res, lamA, stg, wsl, tlast, SL, bE, lane,
+                               std::make_integer_sequence<int, 16>{});
+      } else {
+        chain_mfma<F, R, 0, 2>(accL, xl, xl, res, lamA, stg, wsl, tlast, SL, bE, lane,
+                               std::make_integer_sequence<int, 16>{});
+      }
+      chain_wave_order();
     }
   }
 
   // ---- per-chunk partial: waves summed in LDS in wave order ----
   __shared__ double sbuf[16];
   const double rs_tot = block_sum(rsq, sbuf);    // ends with a barrier: every wave is past its slots
-  const int WT = nc * 256, WS = nc * NX;
-  const int WR = WT + WS + R;                    // per-wave region: tiles, slice sums, V
-  F *red = lc + lo;                              // reuses the slots
+  F *red = lc + lo;                              // reuses the slots: per wave tiles then slice sums
+  auto put_core = [&](int c, const typename M::acc_t &tile) {
 #pragma unroll
-  for (int c = 0; c < MAXC; ++c) {
-    if (c < nc) {
+    for (int v = 0; v < 4; ++v) red[w * region + c * 256 + M::row(lane, v) * 16 + (lane & 15)] = tile[v];
+  };
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red[w * WR + c * 256 + M::row(lane, v) * 16 + (lane & 15)] = acc[c][v];
-      // slice value of this lane: its top log2(NX) bits; sum over the rest
-      F sv = ssacc[c];
-#pragma unroll
-      for (int o = 64 / NX / 2; o >= 1; o >>= 1) sv += __shfl_xor(sv, o, 64);
-      if ((lane & (64 / NX - 1)) == 0) red[w * WR + WT + c * NX + lane / (64 / NX)] = sv;
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < R; ++a) {
-    const double v = wave_sum((double)vacc[a]);
-    if (lane == 0) red[w * WR + WT + WS + a] = (F)v;
-  }
+  for (int c = 0; c < MG; ++c)
+    if (c < ng) put_core(c, acc[c]);
+  if (nc >= 2) put_core(nc - 2, accP);
+  put_core(nc - 1, accL);
+  for (int i = lane; i < WS; i += 64) red[w * region + WT + i] = wss[i];
   __syncthreads();
   const int W = chain_part_width(m, u, R);
   const auto part = glb((F *)d.ch_part) + (long long)blockIdx.x * W;
-  for (int e = threadIdx.x; e < WT + WS; e += NT) {
+  // waves summed in wave order; core u+1's tile holds G_x (A = e_1) and is
+  // written as l_{u+1}[a] G_x[b] below, the rest as it is
+  for (int e = threadIdx.x; e < WR; e += NT) {
     F v = red[e];
 #pragma unroll
-    for (int ww = 1; ww < NW; ++ww) v += red[ww * WR + e];
-    part[e] = v;
+    for (int ww = 1; ww < NW; ++ww) v += red[ww * region + e];
+    red[e] = v;
+    if (e >= 256) part[e] = v;
+  }
+  __syncthreads();
+  {
+    constexpr int XH = 16 / R;
+    const int nu = d.n[u];
+    for (int e = threadIdx.x; e < 256; e += NT) {
+      const int i = e >> 4, jc = e & 15, a = i % R;
+      const int x = (i / R) * XH + jc / R;
+      const F g = x < nu ? red[((i / R) * R) * 16 + jc] : (F)0;    // G_x[b] sits in row (x_hi, 0)
+      part[e] = lamu_s[a] * g;
+    }
   }
   if (threadIdx.x == 0) glb(d.ch_rsq)[blockIdx.x] = rs_tot;
   // cores 1..u: l_k^T V_{k+1}^T at the chunk's x_k, with V_{u+1} the sum of
   // the waves' R_j r_{u+1} and V_k = T_k(x_k) V_{k+1} (one wave)
   if (u > 0 && w == 0) {
+    // V_{u+1} = sum_x T_{u+1}(x) G_x (core u+1 staged at loff[0])
+    constexpr int XH = 16 / R;
     F V[R];
 #pragma unroll
     for (int a = 0; a < R; ++a) {
-      F v = red[WT + WS + a];
+      F v = (F)0;
+      for (int x = 0; x < d.n[u]; ++x) {
+        const F *sl = lc + x * SL;
+        const int rowb = ((x / XH) * R) * 16 + (x % XH) * R;
 #pragma unroll
-      for (int ww = 1; ww < NW; ++ww) v += red[ww * WR + WT + WS + a];
+        for (int b = 0; b < R; ++b) v = fma(sl[a * R + b], red[rowb + b], v);
+      }
       V[a] = v;
     }
     for (int k = u - 1; k >= 0; --k) {
@@ -502,8 +688,9 @@ size_t chain_lds_bytes(int m, int u, const int *n, int R, int prec) {
   size_t cores = 0;
   for (int k = u; k < m; ++k) cores += (size_t)n[k] * chain_slice_stride(R, (int)f);
   const size_t slots = (size_t)chain_nslots(nc) * chain_slot_width(R);
-  const size_t red = (size_t)nc * (256 + chain_nx(R)) + R;
-  return (cores + 4 * std::max(slots, red)) * f;
+  const size_t red = (size_t)nc * (256 + chain_nx(R));
+  const size_t wss = (size_t)nc * chain_nx(R);
+  return (cores + 4 * std::max(slots, red) + 4 * wss + R) * f;
 }
 
 int chain_maxc(int nc) { return nc <= 4 ? 4 : (nc <= 8 ? 8 : (nc <= 10 ? 10 : (nc <= 12 ? 12 : 16))); }
