@@ -444,7 +444,10 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
 #pragma unroll
     for (int c = 0; c < MG; ++c) {
       if (c < ng) {
+        // l_{k+1} is formed alongside core k's MFMA steps (independent work
+        // for the scheduler to interleave); core k's A operand is the staged l_k
         if (c == 0) {
+          chain_left_step<F, R>(lam, lc + loff[c] + xk[c] * SL);
           chain_mfma<F, R, 0, 0>(acc[c], xk[c], xl, res, lamA, wsl, wsl + c * SLOTW, tlast, SL, bE, lane,
                                  std::make_integer_sequence<int, 16>{});
         } else {
@@ -453,11 +456,11 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
 #pragma unroll
           for (int a = 0; a < R; ++a) dst[a * 68] = lam[a];
           chain_wave_order();
+          chain_left_step<F, R>(lam, lc + loff[c] + xk[c] * SL);
           chain_mfma<F, R, 1, 0>(acc[c], xk[c], xl, res, lamA, stg, wsl + c * SLOTW, tlast, SL, bE, lane,
                                  std::make_integer_sequence<int, 16>{});
         }
         chain_wave_order();
-        chain_left_step<F, R>(lam, lc + loff[c] + xk[c] * SL);
       }
     }
     if (nc >= 2) {   // core m-2
@@ -467,14 +470,15 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
 #pragma unroll
         for (int a = 0; a < R; ++a) dst[a * 68] = lam[a];
         chain_wave_order();
+        chain_left_step<F, R>(lam, lc + lo_pen + xp * SL);
         chain_mfma<F, R, 1, 1>(accP, xp, xl, res, lamA, stg, wsl, tlast, SL, bE, lane,
                                std::make_integer_sequence<int, 16>{});
       } else {
+        chain_left_step<F, R>(lam, lc + lo_pen + xp * SL);
         chain_mfma<F, R, 0, 1>(accP, xp, xl, res, lamA, stg, wsl, tlast, SL, bE, lane,
                                std::make_integer_sequence<int, 16>{});
       }
       chain_wave_order();
-      chain_left_step<F, R>(lam, lc + lo_pen + xp * SL);
     }
     {   // core m-1
       F *stg = wsl + stgL * SLOTW;
