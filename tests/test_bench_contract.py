@@ -59,8 +59,10 @@ def test_recorded_traffic_matches_the_current_kernel_source(bench, workload):
     for prec in ("fp64", "mixed"):
         leg = rec[prec]
         assert bench.measured_traffic(prec, workload) == leg["bytes_per_launch"]
-        # what the counters saw is at least the index/value stream itself
-        assert leg["bytes_per_launch"] >= leg["algorithmic_bytes_per_launch"]
+        # what the counters saw is of the order of the index/value stream: the
+        # chain kernel reads the shared leading index rows once per chunk, so
+        # it may read less than the full stream, never a small fraction of it
+        assert leg["bytes_per_launch"] >= 0.5 * leg["algorithmic_bytes_per_launch"]
 
 
 def test_recorded_traffic_is_dropped_once_the_kernel_changes(bench, monkeypatch):

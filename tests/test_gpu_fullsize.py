@@ -1,8 +1,19 @@
 """Parity at the full workload sizes (the benchmark's n = 400 order-3 case, the
 256 x 256 x 128 rank-16 cube and the order-14 MPS-shaped case) in the launch
-configuration the benchmark uses: float64 iterates within 1e-10 of the
-reference for the first iterations, and the mixed-precision sampled pass
-within 1e-4 of the float64 gradient."""
+configuration the benchmark uses:
+
+* float64 iterates within 1e-10 of the reference for the first iterations;
+* the mixed-precision sampled pass entry by entry within the float32 rounding
+  bound c_b * sum_j (|R_j| + |t|_j + |y_j|) |l_j| |r_j| (absolute-value chains,
+  t the entry of the absolute-core tensor), c_b = (2 m R + 4096) 2^-24: every
+  chain product and the residual carry at most 2 m R roundings, and no
+  float32 sum in the kernels runs over more than 4096 terms;
+* mixed precision (and mixed with the bfloat16 tangent contractions on the
+  cube) within 1e-5 of the reference's relative error against the truth: at
+  the n = 400 workload after running both to the relative-change rule, on
+  the cube and the order-14 workload after the first iterations the reference
+  affords (its iterations take 4 and 13 s on one core).
+"""
 
 import numpy as np
 import pytest
@@ -44,9 +55,10 @@ def test_full_size_iterates_match_reference(L, name, c, iters):
         s.close()
 
 
-@pytest.mark.parametrize("name", ["c2", "c3"])
+@pytest.mark.parametrize("name", ["c2", "c3", "c4"])
 def test_full_size_mixed_sampled_pass(L, name):
     pb = wl.named(name)
+    print("case", name, flush=True)
     y = tt.tt_eval(pb.truth, pb.indices) + pb.noise_std * pb.noise
     s = L.Solver(pb.shape, pb.ranks, pb.indices, y.astype(np.float32), pb.init, precision="mixed",
                  stop_rule="none", max_iter=0)
@@ -55,11 +67,62 @@ def test_full_size_mixed_sampled_pass(L, name):
         grads, ssq, rsq = s.sampled_pass()
     finally:
         s.close()
-    r = prgd.residual(cores, pb.indices, y)
+    y32 = y.astype(np.float32).astype(np.float64)       # the values the device holds
+    r = prgd.residual(cores, pb.indices, y32)
     ref_g = prgd.core_gradient(cores, pb.indices, r)
-    assert abs(rsq - float(r @ r)) <= 1e-4 * float(r @ r)
-    for k in range(pb.order):
-        assert np.linalg.norm(grads[k] - ref_g[k]) <= 1e-4 * np.linalg.norm(ref_g[k]), k
+    ref_s = prgd.slice_norms(pb.indices, r, pb.shape)
+    abs_cores = [np.abs(c) for c in cores]
+    w = np.abs(r) + tt.tt_eval(abs_cores, pb.indices) + np.abs(y32)
+    bound = prgd.core_gradient(abs_cores, pb.indices, w)
+    m, R = pb.order, max(pb.ranks)
+    cb = (2 * m * R + 4096) * 2.0 ** -24
+    assert abs(rsq - float(r @ r)) <= cb * float(w @ w)
+    for k in range(m):
+        excess = np.abs(grads[k] - ref_g[k]) - cb * bound[k]
+        assert excess.max() <= 0.0, (k, float(excess.max()))
+        sbound = prgd.slice_norms(pb.indices, w, pb.shape)[k]
+        assert np.all(np.abs(ssq[k] - ref_s[k]) <= cb * sbound), k
+
+
+def test_n400_mixed_final_error_matches_reference(L):
+    pb = wl.named("c2")
+    y = tt.tt_eval(pb.truth, pb.indices) + pb.noise_std * pb.noise
+    pol = prgd.Policy(step_rule="theory", c=0.9, stop_rule="change", tol=1e-6, max_iter=60)
+    ref = prgd.prgd(pb.init, pb.indices, y, pol, truth=pb.truth)
+    err_ref = tt.tt_dist(ref.cores, pb.truth) / tt.tt_norm(pb.truth)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y.astype(np.float32), pb.init, truth_cores=pb.truth,
+                 precision="mixed", step=0.9, stop_rule="change", tol=1e-6, max_iter=60)
+    try:
+        rep = s.run()
+    finally:
+        s.close()
+    print("reference", ref.iterations, err_ref, "device", rep["iterations"], rep["rel_error"], flush=True)
+    assert ref.status == "converged" and rep["status"] == 0
+    assert abs(rep["rel_error"] - err_ref) <= 1e-5
+
+
+@pytest.mark.parametrize("name,prec,policy,c,iters", [("c3", "mixed", "adaptive", 1.0, 2),
+                                                      ("c3", "mixed_bf16", "adaptive", 1.0, 2),
+                                                      ("c4", "mixed", "theory", 1.001, 2)])
+def test_mixed_error_after_first_iterations_matches_reference(L, name, prec, policy, c, iters):
+    pb = wl.named(name)
+    print("case", name, prec, flush=True)
+    y = tt.tt_eval(pb.truth, pb.indices)
+    pol = prgd.Policy(step_rule=policy, c=c)
+    ref = [x.copy() for x in pb.init]
+    for _ in range(iters):
+        ref, _ = prgd.prgd_step(ref, pb.indices, y, pol, pb.ranks)
+    err_ref = tt.tt_dist(ref, pb.truth) / tt.tt_norm(pb.truth)
+    s = L.Solver(pb.shape, pb.ranks, pb.indices, y.astype(np.float32), pb.init, precision=prec, step_policy=policy,
+                 step=c, stop_rule="none", max_iter=iters)
+    try:
+        s.iterate(iters)
+        got = s.cores()
+    finally:
+        s.close()
+    err = tt.tt_dist(got, pb.truth) / tt.tt_norm(pb.truth)
+    print("reference error", err_ref, "device", err, "iterate difference", rel_dist(got, ref), flush=True)
+    assert abs(err - err_ref) <= 1e-5
 
 
 def test_largest_size_sampled_pass_on_sampled_slices(L):
