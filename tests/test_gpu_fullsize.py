@@ -8,11 +8,12 @@ configuration the benchmark uses:
   t the entry of the absolute-core tensor), c_b = (2 m R + 4096) 2^-24: every
   chain product and the residual carry at most 2 m R roundings, and no
   float32 sum in the kernels runs over more than 4096 terms;
-* mixed precision (and mixed with the bfloat16 tangent contractions on the
-  cube) within 1e-5 of the reference's relative error against the truth: at
-  the n = 400 workload after running both to the relative-change rule, on
-  the cube and the order-14 workload after the first iterations the reference
-  affords (its iterations take 4 and 13 s on one core).
+* mixed precision within 1e-5 of the reference's relative error against the
+  truth: at the n = 400 workload after running both to the relative-change
+  rule, on the cube and the order-14 workload after the first iterations the
+  reference affords (its iterations take 4 and 13 s on one core); with the
+  bfloat16 tangent contractions on the cube within 1e-4 after those
+  iterations, and at convergence within 1e-5 of the float64 path.
 """
 
 import numpy as np
@@ -101,10 +102,13 @@ def test_n400_mixed_final_error_matches_reference(L):
     assert abs(rep["rel_error"] - err_ref) <= 1e-5
 
 
-@pytest.mark.parametrize("name,prec,policy,c,iters", [("c3", "mixed", "adaptive", 1.0, 2),
-                                                      ("c3", "mixed_bf16", "adaptive", 1.0, 2),
-                                                      ("c4", "mixed", "theory", 1.001, 2)])
-def test_mixed_error_after_first_iterations_matches_reference(L, name, prec, policy, c, iters):
+# bar: 1e-5 for float32 sampled passes; with the bfloat16 tangent contractions
+# the direction carries 2^-9 relative rounding, which over two iterations
+# that move the error by ~0.03 allows a difference of ~6e-5: bar 1e-4
+@pytest.mark.parametrize("name,prec,policy,c,iters,bar", [("c3", "mixed", "adaptive", 1.0, 2, 1e-5),
+                                                          ("c3", "mixed_bf16", "adaptive", 1.0, 2, 1e-4),
+                                                          ("c4", "mixed", "theory", 1.001, 2, 1e-5)])
+def test_mixed_error_after_first_iterations_matches_reference(L, name, prec, policy, c, iters, bar):
     pb = wl.named(name)
     print("case", name, prec, flush=True)
     y = tt.tt_eval(pb.truth, pb.indices)
@@ -122,7 +126,26 @@ def test_mixed_error_after_first_iterations_matches_reference(L, name, prec, pol
         s.close()
     err = tt.tt_dist(got, pb.truth) / tt.tt_norm(pb.truth)
     print("reference error", err_ref, "device", err, "iterate difference", rel_dist(got, ref), flush=True)
-    assert abs(err - err_ref) <= 1e-5
+    assert abs(err - err_ref) <= bar
+
+
+def test_cube_final_error_with_bf16_tangents_matches_float64(L):
+    # the reference needs ~400 iterations of 4 s here; the float64 device path,
+    # whose iterates match it to 1e-10 per iteration at this size, stands in
+    pb = wl.named("c3")
+    y = tt.tt_eval(pb.truth, pb.indices)
+    out = {}
+    for prec in ("fp64", "mixed_bf16"):
+        v = y if prec == "fp64" else y.astype(np.float32)
+        s = L.Solver(pb.shape, pb.ranks, pb.indices, v, pb.init, truth_cores=pb.truth, precision=prec,
+                     step_policy="adaptive", stop_rule="error", tol=1e-6, max_iter=1500)
+        try:
+            out[prec] = s.run()
+        finally:
+            s.close()
+        print(prec, out[prec], flush=True)
+        assert out[prec]["status"] == 0
+    assert abs(out["fp64"]["rel_error"] - out["mixed_bf16"]["rel_error"]) <= 1e-5
 
 
 def test_largest_size_sampled_pass_on_sampled_slices(L):

@@ -108,28 +108,20 @@ def test_full_size_image_workload(L):
     assert rel(got, ref) <= 1e-10
 
 
-def test_order14_workload_properties(L):
-    # 4^14 tensor, 2M samples: each mode value holds ~500k samples (the
-    # chunked accumulation); the reference at this size is too slow for a test,
-    # so check what holds at any size: left-orthonormal cores and a last core
-    # equal to the projection of the rescaled samples onto the built interface
+def test_order14_workload_matches_reference(L):
+    # 4^14 tensor, 2M samples (each mode value holds ~500k samples: the chunked
+    # accumulation), observations from the reference's evaluator; the
+    # reference takes ~10 s here.  Its own sensitivity to a 1e-13 relative
+    # change of y is ~1e-11, so 1e-10 is a meaningful bar.
     pb = wl.named("c4")
     print(f"spectral init order 14: ranks {pb.ranks} N {pb.n_obs}", flush=True)
-    rng = wl.make_rng(27)
-    y = L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices)
-    got = L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, y, wl.sketch_gaussians(pb.shape, 12, rng), 12)
-    for c in got[:-1]:
-        u = c.reshape(-1, c.shape[2])
-        assert np.abs(u.T @ u - np.eye(u.shape[1])).max() <= 1e-12
-    # last core = sum_j z_j ell_{m-1}(x^(j)) e_{x_m(j)}, on a subset of slices
-    # of the last mode recomputed from the device's interface cores
-    z = y * (4.0 ** 14 / pb.n_obs)
-    sel = np.nonzero(pb.indices[-1] == 1)[0]
-    ell = np.ones((sel.size, 1))
-    for k in range(13):
-        ell = np.einsum("ja,ajb->jb", ell, got[k][:, pb.indices[k, sel], :])
-    want = (z[sel, None] * ell).sum(axis=0)
-    assert np.allclose(got[-1][:, 1, 0], want, rtol=1e-9, atol=1e-9 * np.abs(want).max())
+    y = tt.tt_eval(pb.truth, pb.indices)
+    g = wl.sketch_gaussians(pb.shape, 12, wl.make_rng(27))
+    ref = prgd.spectral_init_sketch(pb.indices, y, pb.shape, pb.ranks, g)
+    got = L.prgd_spectral_init(pb.shape, pb.ranks, pb.indices, y, g, 12)
+    d = rel(got, ref)
+    print("device vs reference", d, flush=True)
+    assert d <= 1e-10
 
 
 def _two_scale_tensor(ratio, seed):
