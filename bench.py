@@ -63,6 +63,9 @@ LEGS = {
                     "noise 1e-3 RMS, int32 indices"),
     "c3": dict(start="perturbed", rule="error", tol=1e-6, policy="adaptive", c=1.0, max_iter=1500,
                desc="256x256x128 smooth-core cube, TT ranks (1,16,16,1), 5% observed, noiseless"),
+    "hbm3": dict(start="perturbed", rule="error", tol=1e-6, policy="theory", c=1.001, max_iter=500,
+                 desc="order-3 TT completion, n=1000, TT ranks (1,2,2,1), |Omega|=50,000,000 (5%), noiseless: "
+                      "a memory-bound shape (20 bytes, ~36 flop per sample)"),
     "c1": dict(start="spectral", rule="residual", tol=1e-10, policy="theory", c=1.001, max_iter=500,
                desc="order-4 TT completion, n=10, TT ranks (1,2,2,2,1), 3,000 of 10^4 entries, noiseless"),
 }
@@ -190,20 +193,28 @@ def workload_legs(name, L, precisions, steps, warmup, phases=True):
     return pb, res
 
 
-def serving_leg(L, n_req, max_obs, seed=0, max_iter=150, precisions=("fp64", "mixed")):
+def _serve_problem(q):
+    """One request's random ingredients (numpy only; runs in a worker process)."""
+    from paper_2501_13385_amd import workloads as wl
+    return wl.problem(q["shape"], q["ranks"], q["n_obs"], q["seed"], name="serve", truth_kind="unit", init_rel=0.1)
+
+
+def serving_leg(L, n_req, max_obs, pool, seed=0, max_iter=300, precisions=("fp64", "mixed")):
     """Request-server throughput and latency on a seeded stream of independent problems.
 
     Every request runs PRGD with the adaptive step (section 3.2.2): the theory
     step diverges on part of this mix (orders 8 with large mode sizes), the
-    adaptive step recovers most of it."""
+    adaptive step recovers most of it.  Each request stops at relative error
+    1e-6 against its ground truth (given to the server), so every precision is
+    timed to the same recovery error; a request that reaches max_iter first
+    counts as a failure and is listed."""
     from paper_2501_13385_amd import workloads as wl
 
     reqs = wl.serving_mix(n_req, seed, max_obs=max_obs)
-    probs = []
-    for q in reqs:
-        pb = wl.problem(q["shape"], q["ranks"], q["n_obs"], q["seed"], name="serve", truth_kind="unit",
-                        init_rel=0.1)
-        probs.append((pb, L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices)))
+    t_gen = time.perf_counter()
+    pbs = pool.map(_serve_problem, reqs, chunksize=1)
+    probs = [(pb, L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices)) for pb in pbs]
+    log(f"serving: {n_req} requests generated in {time.perf_counter() - t_gen:.1f} s")
     kw = dict(step_policy="adaptive", stop_rule="error", tol=1e-6, max_iter=max_iter)
 
     def run(prec, arrivals=None):
@@ -224,21 +235,27 @@ def serving_leg(L, n_req, max_obs, seed=0, max_iter=150, precisions=("fp64", "mi
         wait = np.array([r[1]["admit_s"] - r[1]["submit_s"] for r in res])
         errs = np.array([r[1]["rel_error"] for r in res])
         iters = np.array([r[1]["iterations"] for r in res])
+        ok = np.array([r[0] == 0 and e <= 1e-6 for r, e in zip(res, errs)])
+        fails = [{"order": len(pb.shape), "n": pb.shape[0], "rank": max(pb.ranks), "n_obs": pb.n_obs,
+                  "status": int(r[0]), "iterations": int(r[1]["iterations"]), "rel_error": float(r[1]["rel_error"])}
+                 for (pb, _), r, g in zip(probs, res, ok) if not g]
         return {"solves_per_s": n_req / (t1 - t0), "wall_s": t1 - t0,
                 "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
                 "p50_admission_wait_s": float(np.percentile(wait, 50)),
-                "converged": int(sum(1 for r in res if r[0] == 0)),
+                "success": int(ok.sum()), "success_rate": float(ok.mean()), "failures": fails,
                 "max_rel_error": float(np.nanmax(errs)), "median_iterations": float(np.median(iters)),
                 "samples_iterations_per_s": float(sum(pb.n_obs * it for (pb, _), it in zip(probs, iters)) / (t1 - t0))}
 
     out = {"requests": n_req, "max_obs": max_obs, "tol": "relative error <= 1e-6 (truth given)",
-           "step": "adaptive", "max_iter": max_iter,
+           "step": "adaptive", "max_iter": max_iter, "redraws": int(reqs[-1]["redraws"]) if reqs else 0,
            "orders": sorted({len(pb.shape) for pb, _ in probs}),
            "total_samples": int(sum(pb.n_obs for pb, _ in probs))}
     for prec in precisions:
         log(f"serving closed loop {prec}: {n_req} requests")
         out[f"closed_{prec}"] = run(prec)
-        log(f"  {out[f'closed_{prec}']}")
+        c = out[f"closed_{prec}"]
+        log(f"  {prec}: {c['solves_per_s']:.3g} solves/s, p50 {c['p50_latency_s']:.3g} s, p99 {c['p99_latency_s']:.3g} s, "
+            f"success {c['success']}/{n_req}")
     best = max(precisions, key=lambda p: out[f"closed_{p}"]["solves_per_s"])
     rate = 0.7 * out[f"closed_{best}"]["solves_per_s"]
     rng = np.random.Generator(np.random.PCG64(seed + 1))
@@ -246,7 +263,8 @@ def serving_leg(L, n_req, max_obs, seed=0, max_iter=150, precisions=("fp64", "mi
     log(f"serving open loop {best}: Poisson rate {rate:.3g}/s")
     out[f"open_{best}"] = run(best, arrivals)
     out[f"open_{best}"]["arrival_rate_per_s"] = rate
-    log(f"  {out[f'open_{best}']}")
+    c = out[f"open_{best}"]
+    log(f"  open: p50 {c['p50_latency_s']:.3g} s, p99 {c['p99_latency_s']:.3g} s, success {c['success']}/{n_req}")
     return out
 
 
@@ -329,10 +347,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0, help="timed iterations (0: the iterations to tolerance)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workloads", default="c4,c2,c3,c1", help="comma list; the first is the headline")
+    ap.add_argument("--workloads", default="c4,c2,c3,c1,hbm3", help="comma list; the first is the headline")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000, help="observations in the CPU baseline's sample")
-    ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-max-obs", type=int, default=1 << 19)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-max-obs", type=int, default=4_194_304)
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving leg (prints its JSON)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp64", "mixed", "both"], default="both")
@@ -348,9 +367,20 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
+    pool = None
+    if not args.no_serving and not args.profile_only:
+        # workers that draw the serving problems (numpy only), forked before
+        # anything in this process touches the GPU
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(max(1, min(16, host_cores())))
+
     from paper_2501_13385_amd import _lib as L
 
     L.load()
+    if args.serving_only:
+        print(json.dumps(serving_leg(L, args.serve_requests, args.serve_max_obs, pool)), flush=True)
+        pool.close()
+        return
     names = [w for w in args.workloads.split(",") if w]
     head_name = names[0]
     precs = ["fp64", "mixed"] if args.only == "both" else [args.only]
@@ -402,16 +432,25 @@ def main():
         line["mixed"]["dtype"] = "f32+f64"
     others = {}
     for w in names[1:]:
+        pbw = None
         try:
-            _, res = workload_legs(w, L, precs, 0, args.warmup)
+            pbw, res = workload_legs(w, L, precs, 0, args.warmup)
         except Exception as e:   # one workload's failure is reported, not fatal to the line
             log(f"workload {w} failed: {e}")
             res = {"error": str(e)}
         res["workload"] = LEGS[w]["desc"]
+        if pbw is not None:   # the main sampled kernel against the HBM roofline
+            for prec in ("fp64", "mixed"):
+                if prec in res and res[prec].get("k1_ms"):
+                    b = sampled_pass_bytes(pbw.shape, pbw.n_obs, 8 if prec == "fp64" else 4)
+                    gbs = b / (res[prec]["k1_ms"] * 1e-3) / 1e9
+                    res[prec]["hbm_roofline"] = {"bytes_per_launch": b, "achieved_GBs": gbs, "peak_GBs": PEAK_HBM_GBS,
+                                                 "frac": gbs / PEAK_HBM_GBS}
         others[w] = res
     line["workloads"] = others
     if not args.no_serving:
-        line["serving"] = serving_leg(L, args.serve_requests, args.serve_max_obs)
+        line["serving"] = serving_leg(L, args.serve_requests, args.serve_max_obs, pool)
+        pool.close()
     if not args.no_cpu_baseline:
         n_s = min(args.cpu_sample, pb.n_obs)
         nc = host_cores()

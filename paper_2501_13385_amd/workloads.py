@@ -277,6 +277,14 @@ def _c4(seed: int = 0) -> Problem:
                    init_rel=0.1)
 
 
+def _hbm3(seed: int = 0) -> Problem:
+    # order 3, n = 1000, ranks (1,2,2,1), 50,000,000 samples (5%), noiseless:
+    # 20 bytes and ~36 flop per sample, a shape where the sampled pass is bound
+    # by memory bandwidth rather than arithmetic
+    return problem([1000] * 3, [1, 2, 2, 1], 50_000_000, seed, name="hbm3_m3_n1000_r2", truth_kind="unit",
+                   stop_rule="error", tol=1e-6, max_iter=500, init_rel=0.1)
+
+
 def _c2_small(seed: int = 0) -> Problem:
     # a C2-shaped case small enough for the reference to iterate in seconds
     return problem([40, 36, 44], [1, 4, 4, 1], 6000, seed, name="c2_small_m3_r4",
@@ -290,6 +298,7 @@ NAMED = {
     "c3": _c3,
     "c4": _c4,
     "c2_small": _c2_small,
+    "hbm3": _hbm3,
 }
 
 
