@@ -212,7 +212,11 @@ def serving_leg(L, n_req, max_obs, pool, seed=0, max_iter=300, precisions=("fp64
 
     reqs = wl.serving_mix(n_req, seed, max_obs=max_obs)
     t_gen = time.perf_counter()
-    pbs = pool.map(_serve_problem, reqs, chunksize=1)
+    pbs = []
+    for i, pb in enumerate(pool.imap(_serve_problem, reqs, chunksize=1)):
+        pbs.append(pb)
+        if (i + 1) % 64 == 0 or i + 1 == n_req:
+            log(f"serving: {i + 1}/{n_req} requests drawn")
     probs = [(pb, L.prgd_eval(pb.shape, pb.ranks, pb.truth, pb.indices)) for pb in pbs]
     log(f"serving: {n_req} requests generated in {time.perf_counter() - t_gen:.1f} s")
     kw = dict(step_policy="adaptive", stop_rule="error", tol=1e-6, max_iter=max_iter)

@@ -42,6 +42,7 @@
 namespace prgd {
 
 constexpr int SMEM = 6656;   // doubles of static LDS used by the dense kernels
+constexpr int SMEM_CUT = SMEM + 1024;   // kernels that run a truncation (left_cut)
 
 // thread groups: G groups of TPG threads, each group working on its own slice
 struct Grp {
@@ -673,7 +674,7 @@ __device__ __forceinline__ void rgram_fin_body(const Dev &d, int bx_, int b, dou
 }
 
 __global__ void __launch_bounds__(1024) k_rgram_fin(const Dev *__restrict__ dt, int b) {
-  __shared__ double smem[SMEM];
+  __shared__ double smem[SMEM_CUT];
   rgram_fin_body(dt[blockIdx.y], (int)blockIdx.x, b, smem);
 }
 
@@ -776,11 +777,12 @@ __device__ __forceinline__ void left_cut(const Dev &d, int i, double *smem) {
   // last block: S = F^T GB F, eigen-decomposition, truncation to r_i
   double *GB = smem;                 // NE
   double *F = smem + 1024;           // 2R x rank (ld R2)
-  double *T1 = smem + 2048;          // GB F (2R x rank)
-  double *S = smem + 3072;           // rank x rank
-  double *V = smem + 4096;           // rank x rank
-  double *Vs = smem + 5120;          // Jacobi scratch (1024)
+  double *T1 = smem + 2048;          // GB F (2R x rank); then the Cholesky factor of S
+  double *S = smem + 3072;           // rank x rank; then eigen-solver scratch
+  double *W = smem + 4096;           // eigenvectors of the graded matrix
+  double *V = smem + 5120;           // eigenvectors of S (after the graded matrix, same area)
   double *w = smem + 6144;           // 32
+  double *W2 = smem + SMEM;          // eigen-solver scratch (1024)
   const double *fs = sm_slot(d, i, S_F);
   for (int t = threadIdx.x; t < NE; t += blockDim.x) F[t] = fs[t];
   __syncthreads();
@@ -814,7 +816,7 @@ __device__ __forceinline__ void left_cut(const Dev &d, int i, double *smem) {
     S[bcol * rk + a] = v;
   }
   __syncthreads();
-  block_jacobi_eig(S, rk, V, w, T1, Vs);  // T1 is free once S is formed
+  block_psd_eig(S, rk, V, w, T1, V, W, S, W2);  // T1 is free once S is formed
   if (threadIdx.x == 0) {
     const double s0 = w[0];
     if (!(w[ri - 1] > TRUNC_MIN_EIG_RATIO * s0) || !isfinite(s0)) bad = 1;
@@ -862,7 +864,7 @@ __device__ __forceinline__ void left_fin_body(const Dev &d, int bx_, int i, doub
 }
 
 __global__ void __launch_bounds__(1024) k_left_fin(const Dev *__restrict__ dt, int i) {
-  __shared__ double smem[SMEM];
+  __shared__ double smem[SMEM_CUT];
   left_fin_body(dt[blockIdx.y], (int)blockIdx.x, i, smem);
 }
 
@@ -1127,6 +1129,56 @@ __global__ void __launch_bounds__(1024) k_cross_fin(const Dev *__restrict__ dt, 
 }
 
 // ---------------------------------------------------------------------------
+// Steps with few slice blocks (small mode sizes): the blocks and the finish
+// in one launch.  One workgroup runs the g slice blocks in turn and then the
+// finish, which reads their partials after a workgroup barrier; arithmetic
+// and summation order are those of the two-launch form, so results are the
+// same bits.  This saves a launch and a kernel start per step on the long
+// chains of dependent one-block steps that orders >= 4 with small n produce.
+// ---------------------------------------------------------------------------
+constexpr int FUSE_MAX = 2;   // slice blocks run in turn by one workgroup
+
+__global__ void __launch_bounds__(1024) k_gram_fused(const Dev *__restrict__ dt, int j, int g) {
+  __shared__ double smem[SMEM];
+  const Dev &d = dt[blockIdx.y];
+  for (int bx = 0; bx < g; ++bx) {
+    gram_body(d, bx, j, smem);
+    __syncthreads();
+  }
+  gram_fin_body(d, 0, j, smem);
+}
+
+__global__ void __launch_bounds__(1024) k_rgram_fused(const Dev *__restrict__ dt, int b, int g) {
+  __shared__ double smem[SMEM_CUT];
+  const Dev &d = dt[blockIdx.y];
+  for (int bx = 0; bx < g; ++bx) {
+    rgram_body(d, bx, b, smem);
+    __syncthreads();
+  }
+  rgram_fin_body(d, 0, b, smem);
+}
+
+__global__ void __launch_bounds__(1024) k_left_fused(const Dev *__restrict__ dt, int i, int g) {
+  __shared__ double smem[SMEM_CUT];
+  const Dev &d = dt[blockIdx.y];
+  for (int bx = 0; bx < g; ++bx) {
+    left_body(d, bx, i, smem);
+    __syncthreads();
+  }
+  left_fin_body(d, 0, i, smem);
+}
+
+__global__ void __launch_bounds__(1024) k_cross_fused(const Dev *__restrict__ dt, int c, int mode, int g) {
+  __shared__ double smem[SMEM];
+  const Dev &d = dt[blockIdx.y];
+  for (int bx = 0; bx < g; ++bx) {
+    cross_body(d, bx, c, mode, smem);
+    __syncthreads();
+  }
+  cross_fin_body(d, 0, c, mode, smem);
+}
+
+// ---------------------------------------------------------------------------
 // launchers (grids sized for the largest member of the batch)
 // ---------------------------------------------------------------------------
 hipError_t launch_adaptive_step(const Batch &bt, hipStream_t s);
@@ -1143,8 +1195,12 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
   const int m = bt.host[0].m, ns = bt.ns;
   for (int j = 1; j <= m - 1; ++j) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 8) + nblocks_for(d.n[m - j], 8); });
-    hipLaunchKernelGGL(k_gram, dim3(g, ns), dim3(1024), 0, s, bt.dt, j);
-    hipLaunchKernelGGL(k_gram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, j);
+    if (g <= FUSE_MAX) {
+      hipLaunchKernelGGL(k_gram_fused, dim3(1, ns), dim3(1024), 0, s, bt.dt, j, g);
+    } else {
+      hipLaunchKernelGGL(k_gram, dim3(g, ns), dim3(1024), 0, s, bt.dt, j);
+      hipLaunchKernelGGL(k_gram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, j);
+    }
   }
   const int g = max_over(bt, [&](const Dev &d) { return d.blk_off[m]; });
   if (bt.host[0].tangent_bf16)   // the whole batch shares the variant
@@ -1163,13 +1219,21 @@ hipError_t launch_retract(const Batch &bt, hipStream_t s) {
     const int g = max_over(bt, [&](const Dev &d) {
       return nblocks_for(d.n[b], 4) + (b == m - 1 ? nblocks_for(d.n[0], 4) : 0);
     });
-    hipLaunchKernelGGL(k_rgram, dim3(g, ns), dim3(1024), 0, s, bt.dt, b);
-    hipLaunchKernelGGL(k_rgram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, b);   // b = 1 also truncates cut 1
+    if (g <= FUSE_MAX) {   // b = 1 also truncates cut 1
+      hipLaunchKernelGGL(k_rgram_fused, dim3(1, ns), dim3(1024), 0, s, bt.dt, b, g);
+    } else {
+      hipLaunchKernelGGL(k_rgram, dim3(g, ns), dim3(1024), 0, s, bt.dt, b);
+      hipLaunchKernelGGL(k_rgram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, b);
+    }
   }
   for (int i = 2; i <= m - 1; ++i) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[i - 1], 4); });
-    hipLaunchKernelGGL(k_left, dim3(g, ns), dim3(1024), 0, s, bt.dt, i);
-    hipLaunchKernelGGL(k_left_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, i);
+    if (g <= FUSE_MAX) {
+      hipLaunchKernelGGL(k_left_fused, dim3(1, ns), dim3(1024), 0, s, bt.dt, i, g);
+    } else {
+      hipLaunchKernelGGL(k_left, dim3(g, ns), dim3(1024), 0, s, bt.dt, i);
+      hipLaunchKernelGGL(k_left_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, i);
+    }
   }
   return hipGetLastError();
 }
@@ -1198,8 +1262,12 @@ hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode) {
   if (!any) return hipSuccess;
   for (int c = 0; c < m; ++c) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[c], 4); });
-    hipLaunchKernelGGL(k_cross, dim3(g, ns), dim3(1024), 0, s, bt.dt, c, mode);
-    hipLaunchKernelGGL(k_cross_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, c, mode);
+    if (g <= FUSE_MAX) {
+      hipLaunchKernelGGL(k_cross_fused, dim3(1, ns), dim3(1024), 0, s, bt.dt, c, mode, g);
+    } else {
+      hipLaunchKernelGGL(k_cross, dim3(g, ns), dim3(1024), 0, s, bt.dt, c, mode);
+      hipLaunchKernelGGL(k_cross_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, c, mode);
+    }
   }
   return hipGetLastError();
 }

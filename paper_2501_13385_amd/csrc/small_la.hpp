@@ -234,42 +234,29 @@ __device__ inline void block_sum2(double &a, double &b, double *sb) {
   }
 }
 
-// Cyclic Jacobi for a symmetric n x n matrix A (ld n, n <= 32), for a block of
-// at least 256 threads.  The matrix and the eigenvector matrix are held padded
-// to ne = n + (n & 1) (a zero row and column, on which every rotation is
-// exactly the identity) with ld ne.  Pairs sit in fixed slots (2P, 2P+1), and
-// the round-robin ordering moves the data instead: each round writes the
-// rotated matrix into the other buffer with rows and columns already moved to
-// their next slots (and V's columns likewise), so every thread reads and
-// writes the same addresses in every round and no index is computed inside
-// the loop; after a sweep of ne - 1 rounds all slots are back in place.
-// Thread (P, Q), P, Q < ne/2, owns the 2 x 2 block (P, Q) of A and the 2 x 2
-// block of V with rows 2P, 2P+1 and columns in pair Q; it computes the two
-// rotations it needs itself from the previous state, so a round costs one
-// barrier and at most four waves work (one per SIMD).  The off-diagonal mass
-// for the stopping rule is summed from the entries written in a sweep's last
-// round.  Sweeps stop once the off-diagonal Frobenius norm is at most 1e-15 of
-// the whole (a converged sweep leaves rounding residue near 3e-16 of it, so a
-// tighter bound would never be met), or once a sweep fails to shrink it (exact
-// rotations always do, so only rounding is left).  On exit w[0..n) holds the
-// eigenvalues in descending order and V (ld n) the eigenvectors as columns.
-// A is read first and its area (1024 doubles) then reused, as is V's; W1, W2:
-// scratch, 1024 doubles each.
-__device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, double *W1, double *W2) {
-  __shared__ double sb[32];
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int ne = n + (n & 1), np = ne / 2, m1 = ne - 1;
-  double *cur = W1, *nxt = W2, *vc = A;
-  double off = 0.0, dia = 0.0;
-  for (int e = t; e < ne * ne; e += nt) {
-    const int i = e / ne, j = e - i * ne;
-    const double v = (i < n && j < n) ? A[i * n + j] : 0.0;
-    cur[e] = v;
-    if (i == j) dia += v * v;
-    else off += v * v;
-  }
-  block_sum2(off, dia, sb);  // ends with a barrier: A has been read
-  for (int e = t; e < ne * ne; e += nt) vc[e] = (e / ne == e % ne) ? 1.0 : 0.0;
+// Sum of v over the wave, the same value in every lane: DPP rows of 16 (each
+// lane of a row ends with the same row total: every step adds a pair of
+// equal-order partial sums), then the four row totals read in a fixed order.
+__device__ __forceinline__ double wave_sum_uniform(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  v += dpp_f64<0x140>(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
+// The sweeps of the cyclic Jacobi method on the padded ne x ne matrix in W1
+// (eigenvector accumulator in A, identity on entry); returns true when the
+// result sits in (W2, V) rather than (W1, A).  WAVE: run by the first wave
+// alone (ne <= 16, so the np^2 <= 64 working threads are one wave): the
+// rounds are then ordered by the wave's in-order LDS accesses instead of
+// workgroup barriers, and the stopping sums are wave reductions.  off and dia
+// hold the initial off-diagonal and diagonal masses on entry.
+template <bool WAVE>
+__device__ __forceinline__ bool jacobi_sweeps(double *W1, double *W2, double *A, double *V, int ne, double off,
+                                              double dia, double *sb) {
+  const int t = threadIdx.x;
+  const int np = ne / 2, m1 = ne - 1;
   const bool act = t < np * np;
   const int P = act ? t / np : 0, Q = act ? t - P * np : 0;
   // this thread's fixed addresses: the reads at rows/columns 2P, 2P+1 and
@@ -278,7 +265,6 @@ __device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, 
   const int p1 = 2 * P * (ne + 1), q1 = 2 * Q * (ne + 1);
   const int nr1 = tournament_next(2 * P, np) * ne, nr2 = tournament_next(2 * P + 1, np) * ne;
   const int nc1 = tournament_next(c1, np), nc2 = tournament_next(c2, np);
-  __syncthreads();
   // one round from buffers (src, vsrc) into (dst, vdst); instantiated once per
   // direction so that every address is a fixed offset from a fixed buffer
   auto one_round = [&](const double *src, double *dst, const double *vsrc, double *vdst, bool last) {
@@ -315,7 +301,8 @@ __device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, 
         }
       }
     }
-    __syncthreads();
+    if constexpr (WAVE) wave_lds_sync();
+    else __syncthreads();
   };
   double prev = 0.0;  // off-diagonal mass before the last sweep
   bool flip = false;  // data in (W2, V) rather than (W1, A)
@@ -330,11 +317,68 @@ __device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, 
       else one_round(W1, W2, A, V, last);
       flip = !flip;
     }
-    block_sum2(off, dia, sb);
+    if constexpr (WAVE) {
+      off = wave_sum_uniform(off);
+      dia = wave_sum_uniform(dia);
+    } else {
+      block_sum2(off, dia, sb);
+    }
   }
-  cur = flip ? W2 : W1;
-  nxt = flip ? W1 : W2;
-  vc = flip ? V : A;
+  return flip;
+}
+
+// Cyclic Jacobi for a symmetric n x n matrix A (ld n, n <= 32), run by a whole
+// block of at least 256 threads.  The matrix and the eigenvector matrix are
+// held padded to ne = n + (n & 1) (a zero row and column, on which every
+// rotation is exactly the identity) with ld ne.  Pairs sit in fixed slots
+// (2P, 2P+1), and the round-robin ordering moves the data instead: each round
+// writes the rotated matrix into the other buffer with rows and columns
+// already moved to their next slots (and V's columns likewise), so every
+// thread reads and writes the same addresses in every round and no index is
+// computed inside the loop; after a sweep of ne - 1 rounds all slots are back
+// in place.  Thread (P, Q), P, Q < ne/2, owns the 2 x 2 block (P, Q) of A and
+// the 2 x 2 block of V with rows 2P, 2P+1 and columns in pair Q; it computes
+// the two rotations it needs itself from the previous state.  For ne <= 16
+// those threads are the first wave, which runs the sweeps alone with no
+// workgroup barrier; larger matrices take one barrier per round.  The
+// off-diagonal mass for the stopping rule is summed from the entries written
+// in a sweep's last round.  Sweeps stop once the off-diagonal Frobenius norm
+// is at most 1e-15 of the whole (a converged sweep leaves rounding residue
+// near 3e-16 of it, so a tighter bound would never be met), or once a sweep
+// fails to shrink it (exact rotations always do, so only rounding is left).
+// On exit w[0..n) holds the eigenvalues in descending order and V (ld n) the
+// eigenvectors as columns.  A is read first and its area (1024 doubles) then
+// reused, as is V's; W1, W2: scratch of ne * ne doubles each.
+__device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, double *W1, double *W2) {
+  __shared__ double sb[32];
+  __shared__ int flip_s;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int ne = n + (n & 1);
+  double off = 0.0, dia = 0.0;
+  for (int e = t; e < ne * ne; e += nt) {
+    const int i = e / ne, j = e - i * ne;
+    const double v = (i < n && j < n) ? A[i * n + j] : 0.0;
+    W1[e] = v;
+    if (i == j) dia += v * v;
+    else off += v * v;
+  }
+  block_sum2(off, dia, sb);  // ends with a barrier: A has been read
+  for (int e = t; e < ne * ne; e += nt) A[e] = (e / ne == e % ne) ? 1.0 : 0.0;
+  __syncthreads();
+  bool flip;
+  if (ne <= 16) {
+    if (t < 64) {
+      const bool f = jacobi_sweeps<true>(W1, W2, A, V, ne, off, dia, sb);
+      if (t == 0) flip_s = f ? 1 : 0;
+    }
+    __syncthreads();
+    flip = flip_s != 0;
+  } else {
+    flip = jacobi_sweeps<false>(W1, W2, A, V, ne, off, dia, sb);
+  }
+  const double *cur = flip ? W2 : W1;
+  double *nxt = flip ? W1 : W2;
+  const double *vc = flip ? V : A;
   // the eigenvectors now sit in vc, in slot order (= original order); if that
   // is V's own area, move them out of the way first
   if (vc == V) {
@@ -360,6 +404,48 @@ __device__ inline void block_jacobi_eig(double *A, int n, double *V, double *w, 
     V[rr * n + rank_of[i]] = vc[rr * ne + i];
   }
   __syncthreads();
+}
+
+// Eigen-decomposition of a symmetric positive semidefinite n x n matrix S
+// (ld n, n <= 32, read only) through its pivoted Cholesky factor: S = Fc Fc^T
+// (Fc: n x rank), S1 = Fc^T Fc has the same nonzero eigenvalues, and with
+// S1 = W diag(w) W^T the eigenvectors of S are Fc W diag(w)^{-1/2}.  The
+// pivoted factor grades S1 (large entries first, small couplings), so the
+// Jacobi sweeps on S1 converge in about half as many sweeps as on S itself;
+// see Demmel and Veselic (1992) on Jacobi for graded positive definite
+// matrices.  On exit w[0..n) holds the eigenvalues in descending order (zeros
+// past the rank) and V (ld n) the eigenvectors of the nonzero ones as columns
+// (zero columns past the rank).  Returns the rank.  Fc, S1, W, W1, W2: LDS
+// scratch, 1024 doubles each.  V may share S1's area and W1 may share S's
+// (each is dead by the time the other is written); no other two may alias.
+__device__ inline int block_psd_eig(const double *S, int n, double *V, double *w, double *Fc, double *S1, double *W,
+                                    double *W1, double *W2) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int rank = block_pivoted_cholesky(S, n, Fc);   // ends with a barrier
+  // S1 = Fc^T Fc, each entry of the upper triangle formed once and mirrored
+  for (int e = t; e < rank * rank; e += nt) {
+    const int a = e / rank, b = e - a * rank;
+    if (a > b) continue;
+    double v = 0.0;
+    for (int i = 0; i < n; ++i) v = fma(Fc[i * n + a], Fc[i * n + b], v);
+    S1[a * rank + b] = v;
+    S1[b * rank + a] = v;
+  }
+  __syncthreads();
+  if (rank > 0) block_jacobi_eig(S1, rank, W, w, W1, W2);
+  for (int e = t; e < n * n; e += nt) {
+    const int i = e / n, col = e - i * n;
+    double v = 0.0;
+    if (col < rank && w[col] > 0.0) {
+      for (int j = 0; j < rank; ++j) v = fma(Fc[i * n + j], W[j * rank + col], v);
+      v *= rsq_newton<2>(w[col]);
+    }
+    V[e] = v;
+  }
+  __syncthreads();
+  for (int i = rank + t; i < n; i += nt) w[i] = 0.0;
+  __syncthreads();
+  return rank;
 }
 
 // Inverses of two SPD matrices by Gauss-Jordan elimination on [A | I] (no
