@@ -413,6 +413,8 @@ int64_t solver_footprint(const prgd_desc *ds) {
     const int64_t L = (int64_t)(ds->mode_sizes[0] + ds->mode_sizes[2]) * (R + 1);
     const int64_t segw = (int64_t)R * R + 1;
     b += 256 * (L + KSEG * segw) * f + (int64_t)ds->mode_sizes[1] * (segw * f + 8) + 256 * 12;
+    if (R <= SAMPLED3W_MAX_R && L * 8 <= (int64_t)SAMPLED3W_MAX_LDS)   // one-wave chunks: up to 16 per CU
+      b += 4096 * ((L + 2 * segw) * f + 12);
   }
   // transient during creation: unsorted copies, sort keys/permutations and
   // the radix-sort scratch
@@ -670,7 +672,22 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   if (m == 3 && sm == 1 && sampled3_lds_bytes(s->n[0], s->n[2], R, d.prec, 0) <= 163840) {
     S3 &q = d.q3;
     q.stage = sampled3_lds_bytes(s->n[0], s->n[2], R, d.prec, 1) <= 163840 ? 1 : 0;
-    long long nwg = std::min<long long>(256, std::max<long long>(1, (N + 63) / 64));
+    // low ranks: one wave per chunk with its own table, as many chunks as can
+    // be resident at once, each chunk long enough that its table partial is at
+    // most half of the index/value bytes it reads
+    const size_t wlds = sampled3w_lds_bytes(s->n[0], s->n[2], R, d.prec);
+    q.wave = (R <= SAMPLED3W_MAX_R && wlds <= SAMPLED3W_MAX_LDS) ? 1 : 0;
+    long long nwg;
+    if (q.wave) {
+      // resident waves per CU: the tables' LDS and the registers of the
+      // deep load pipeline (about 390 VGPRs at R = 2, 180 at R = 4)
+      const long long per_cu = std::min<long long>(R <= 2 ? 4 : 8, 163840 / (long long)wlds);
+      const long long fb = mixed ? 4 : 8;
+      const long long min_chunk = std::max<long long>(256, 2 * (long long)wlds * fb / 8 / (12 + fb));
+      nwg = std::min<long long>(256 * per_cu, std::max<long long>(1, N / min_chunk));
+    } else {
+      nwg = std::min<long long>(256, std::max<long long>(1, (N + 63) / 64));
+    }
     q.chunk = (N + nwg - 1) / nwg;
     nwg = (N + q.chunk - 1) / q.chunk;
     q.nwg = (int)nwg;
@@ -678,10 +695,11 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     std::vector<long long> seg(n1 + 1, 0);
     for (long long j = 0; j < N; ++j) seg[idx_h[N + j] + 1]++;
     for (int v = 0; v < n1; ++v) seg[v + 1] += seg[v];
-    std::vector<int> vfirst(nwg), blo(n1), bhi(n1);
+    std::vector<int> vfirst(nwg), vlast(nwg), blo(n1), bhi(n1);
     for (long long b = 0; b < nwg; ++b) {
-      const long long j0 = b * q.chunk;
+      const long long j0 = b * q.chunk, jl = std::min(N, j0 + q.chunk) - 1;
       vfirst[b] = (int)(std::upper_bound(seg.begin(), seg.end(), j0) - seg.begin()) - 1;
+      vlast[b] = (int)(std::upper_bound(seg.begin(), seg.end(), jl) - seg.begin()) - 1;
     }
     for (int v = 0; v < n1; ++v) {
       if (seg[v + 1] > seg[v]) {
@@ -695,13 +713,15 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     const size_t f = mixed ? 4 : 8;
     const long long L = (long long)(s->n[0] + s->n[2]) * (R + 1);
     const long long segw = (long long)R * R + 1;
-    int *dvf = nullptr, *dlo = nullptr, *dhi = nullptr;
+    int *dvf = nullptr, *dvl = nullptr, *dlo = nullptr, *dhi = nullptr;
     unsigned char *pbnd = nullptr, *pseg = nullptr, *povf = nullptr;
-    if (!A(s->alloc(&dvf, nwg)) || !A(s->alloc(&dlo, n1)) || !A(s->alloc(&dhi, n1)) ||
-        !A(s->alloc(&pbnd, nwg * L * (long long)f)) || !A(s->alloc(&pseg, nwg * KSEG * segw * (long long)f)) ||
+    const long long nslot = q.wave ? 2 : KSEG;
+    if (!A(s->alloc(&dvf, nwg)) || !A(s->alloc(&dvl, nwg)) || !A(s->alloc(&dlo, n1)) || !A(s->alloc(&dhi, n1)) ||
+        !A(s->alloc(&pbnd, nwg * L * (long long)f)) || !A(s->alloc(&pseg, nwg * nslot * segw * (long long)f)) ||
         !A(s->alloc(&povf, n1 * segw * (long long)f)) || !A(s->alloc(&q.part_rsq, nwg)))
       return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
     if (hipMemcpyAsync(dvf, vfirst.data(), nwg * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(dvl, vlast.data(), nwg * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(dlo, blo.data(), n1 * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(dhi, bhi.data(), n1 * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess)
       return cleanup(fail(PRGD_EDEVICE, "upload of the segment map failed"));
@@ -709,6 +729,7 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     hipError_t fe = mixed ? fill_f32((float *)povf, novf, 0.0f, s->stream) : fill_f64((double *)povf, novf, 0.0, s->stream);
     if (fe != hipSuccess) return cleanup(fail(PRGD_EDEVICE, "fill failed"));
     q.vfirst = dvf;
+    q.vlast = dvl;
     q.blo = dlo;
     q.bhi = dhi;
     q.part_bnd = pbnd;

@@ -79,16 +79,23 @@ struct State {
 
 // order-3 sampled pass: per-workgroup partials (see sampled3.hip)
 constexpr int KSEG = 8;   // segment slots per workgroup table
+constexpr int SAMPLED3W_MAX_R = 4;   // padded ranks served by the one-wave-per-chunk variant
+template <int R>
+constexpr int sampled3w_group() { return R <= 2 ? 16 : 8; }   // batches of 64 samples per pipeline group in that variant
+constexpr size_t SAMPLED3W_MAX_LDS = 57344;   // table bytes for that variant (>= 2 waves per CU)
 
 struct S3 {
   long long chunk;       // samples per workgroup
   int nwg;
   int stage;             // 1: boundary vectors staged in LDS
+  int wave;              // 1: one wave per chunk with a private table (low ranks)
   const int *vfirst;     // [nwg] first segment (middle-mode index) of each workgroup's chunk
+  const int *vlast;      // [nwg] last segment of each chunk (wave variant)
   const int *blo;        // [n_1] first workgroup covering segment v (blo > bhi: empty segment)
   const int *bhi;        // [n_1]
   void *part_bnd;        // [nwg][L]: dT_0 [n_0 R] | dT_2 [n_2 R] | s_0 [n_0] | s_2 [n_2]
   void *part_seg;        // [nwg][KSEG][R*R + 1]: middle-core gradient pieces and s_1
+                         // (wave variant: [nwg][2][R*R + 1], the chunk's first and last segments)
   void *ovf;             // [n_1][R*R + 1] overflow accumulator (zero between passes)
   double *part_rsq;      // [nwg]
 };

@@ -24,6 +24,7 @@
 // weights.  The LDS atomics inside a workgroup add in an order that varies from
 // run to run, so results repeat to rounding, not bit for bit.
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 #include "prgd_internal.hpp"
@@ -268,7 +269,10 @@ __global__ void __launch_bounds__(NT) k_sampled3(const Dev *__restrict__ dt, int
 // Blocks [0, nbB): 64 boundary outputs each, the 4 waves splitting the
 // workgroup partials; blocks [nbB, grid): middle-core segments, one output
 // per thread (2-3 pieces each).
-template <typename F, int R>
+// WAVE: the partials of the low-rank variant (one wave per chunk; each
+// chunk's first and last segments in two slots, its inner segments already
+// written by the main kernel).
+template <typename F, int R, bool WAVE>
 __global__ void __launch_bounds__(256) k_sampled3_reduce(const Dev *__restrict__ dt, int diag) {
   const Dev &d = dt[blockIdx.y];
   const S3 &q = d.q3;
@@ -322,6 +326,21 @@ __global__ void __launch_bounds__(256) k_sampled3_reduce(const Dev *__restrict__
         s[d.soff[2] + (i - n1 * R - n3 * R - n1)] = (F)acc;
       }
     }
+  } else if (WAVE) {
+    const long long tot = (long long)n2 * SEGW;
+    const long long oo = (long long)(blockIdx.x - nbB) * blockDim.x + threadIdx.x;
+    if (oo < tot) {
+      const int v = (int)(oo / SEGW), e = (int)(oo % SEGW);
+      const int lo = glb(q.blo)[v], hi = glb(q.bhi)[v];
+      const bool inner = lo == hi && v != glb(q.vfirst)[lo] && v != glb(q.vlast)[lo];
+      if (!inner) {   // inner segments were written by the chunk that holds them
+        double acc = 0.0;   // stays zero for a segment without samples (lo > hi)
+        for (int b = lo; b <= hi; ++b)
+          acc += (double)ps[((long long)b * 2 + (v == glb(q.vfirst)[b] ? 0 : 1)) * SEGW + e];
+        if (e < RR) Y[d.coff[1] + (long long)v * RR + e] = (F)acc;
+        else s[d.soff[1] + v] = (F)acc;
+      }
+    }
   } else {
     const long long tot = (long long)n2 * SEGW;
     const long long oo = (long long)(blockIdx.x - nbB) * blockDim.x + threadIdx.x;
@@ -339,10 +358,279 @@ __global__ void __launch_bounds__(256) k_sampled3_reduce(const Dev *__restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// Low-rank variant (padded rank R <= 4): one wave per workgroup, owning its
+// LDS table of boundary-core gradients and slice sums.
+//
+// For small R the pass reads 16-20 bytes per sample and does a few dozen
+// flops with them, so it is bound by memory bandwidth.  Here every wave is
+// its own workgroup with a private table ((n_1 + n_3)(R + 1) float64
+// values), so no two waves add into the same LDS word: the
+// accumulation order is the wave's program order and a pass repeats bit for
+// bit.  The stream is read with G batches of 64 samples in flight per
+// group and the next group's loads issued before the current group is
+// processed, the boundary vectors are gathered from L2 (a few KB to tens of
+// KB, shared by all waves), and the middle-core gradient R x R block is an
+// outer product accumulated per lane and reduced across the wave only when
+// the segment changes.  Segments inside one wave's chunk are written to the
+// gradient directly (no other wave touches them); a chunk's first and last
+// segments go to two slots per wave that the reduction adds in wave order.
+// ---------------------------------------------------------------------------
+
+// Sum of v over the 64 lanes, the same bits in every lane: DPP rows of 16
+// (every step adds two partial sums formed in the same order, so the lanes
+// of a row agree), then the four row totals in a fixed order.
+__device__ __forceinline__ double wave_total(double v) {
+  auto dpp = [](double x, auto ctrl) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, decltype(ctrl)::value, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), decltype(ctrl)::value, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+  };
+  v += dpp(v, std::integral_constant<int, 0xB1>{});   // lane ^ 1
+  v += dpp(v, std::integral_constant<int, 0x4E>{});   // lane ^ 2
+  v += dpp(v, std::integral_constant<int, 0x141>{});  // row half mirror
+  v += dpp(v, std::integral_constant<int, 0x140>{});  // row mirror
+  auto rd = [](double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+  };
+  return (rd(v, 0) + rd(v, 16)) + (rd(v, 32) + rd(v, 48));
+}
+
+template <typename F, int R, int G>
+__global__ void __launch_bounds__(64) k_sampled3w(const Dev *__restrict__ dt, int diag) {
+  const Dev &d = dt[blockIdx.y];
+  const S3 &q = d.q3;
+  if ((int)blockIdx.x >= q.nwg || (!diag && d.st->done)) return;
+  constexpr int RR = R * R, RS = R + 1, SEGW = RR + 1;
+  const int lane = threadIdx.x;
+  const auto cores = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.cores32 : (const void *)d.cores));
+  const auto bnd = glb((const F *)d.bnd);
+  const auto y = glb((const F *)(d.prec == PREC_MIXED ? (const void *)d.y32 : (const void *)d.y64));
+  const int n1 = d.n[0], n3 = d.n[2];
+  const long long N = d.N;
+  // the table in float64 for both precisions (LDS float64 atomic adds
+  // measured several times faster than float32 ones for this scatter)
+  extern __shared__ unsigned char lds_raw[];
+  double *tab1 = reinterpret_cast<double *>(lds_raw);   // [n1][R + 1]: dT_1 row, then s_1
+  double *tab3 = tab1 + n1 * RS;                          // [n3][R + 1]: dT_3 row, then s_3
+  for (int i = lane; i < (n1 + n3) * RS; i += 64) tab1[i] = 0.0;
+  __syncthreads();
+  const auto T1 = bnd, T3 = bnd + (long long)n1 * R;
+  const int w = blockIdx.x;
+  const long long j0 = (long long)w * q.chunk, j1 = min(N, j0 + q.chunk);
+  const int vf = glb(q.vfirst)[w], vl = glb(q.vlast)[w];
+  const auto ix1 = glb(d.idx), ix2 = glb(d.idx) + N, ix3 = glb(d.idx) + 2 * N;
+  const long long co2 = d.coff[1];
+  const auto Yg = glb((F *)d.Y);
+  const auto sg = glb((F *)d.s);
+  const auto slots = glb((F *)q.part_seg) + (long long)w * 2 * SEGW;
+
+  F g2[RR];            // this lane's share of the current segment's R x R block
+  F s2 = (F)0;         // and of its slice sum
+#pragma unroll
+  for (int e = 0; e < RR; ++e) g2[e] = (F)0;
+  int wv = -1;         // segment held in g2 (wave-uniform)
+  double rsq = 0.0;
+
+  auto flush = [&]() {
+    if (wv >= 0) {
+      const bool inner = wv != vf && wv != vl;   // no other wave has samples in it
+      F *dst = inner ? (F *)(Yg + d.coff[1] + (long long)wv * RR) : (F *)(slots + (wv == vf ? 0 : SEGW));
+#pragma unroll
+      for (int e = 0; e < RR; ++e) {
+        const double t = wave_total((double)g2[e]);
+        if (lane == 0) dst[e] = (F)t;
+      }
+      const double t = wave_total((double)s2);
+      if (lane == 0) {
+        if (inner) sg[d.soff[1] + wv] = (F)t;
+        else dst[RR] = (F)t;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < RR; ++e) g2[e] = (F)0;
+    s2 = (F)0;
+  };
+
+  // one group of G batches of 64 samples: indices and values
+  struct Grp3 {
+    int x1[G], x2[G], x3[G];
+    F yv[G];
+  };
+  // every lane loads (past the end it re-reads the chunk's last sample, and
+  // its x2 is marked -1 when used), so the loads are straight-line code and
+  // a whole group is in flight at once
+  auto load = [&](Grp3 &b, long long jb) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const long long j = min(jb + 64 * g + lane, j1 - 1);
+      b.x1[g] = ix1[j];
+      b.x2[g] = ix2[j];
+      b.x3[g] = ix3[j];
+      b.yv[g] = y[j];
+    }
+  };
+  // one sample per lane, of segment v's slice S (in scalar registers): the
+  // residual, the boundary-table adds and this lane's share of the block
+  auto sample = [&](const F (&S)[RR], const F (&l1)[R], const F (&r3)[R], int x1, int x3, F yv) {
+    F u[R], l2[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      u[a] = (F)0;
+      l2[a] = (F)0;
+    }
+#pragma unroll
+    for (int a = 0; a < R; ++a)
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        u[a] = fma(S[a * R + b], r3[b], u[a]);
+        l2[b] = fma(l1[a], S[a * R + b], l2[b]);
+      }
+    F t = (F)0;
+#pragma unroll
+    for (int a = 0; a < R; ++a) t = fma(l1[a], u[a], t);
+    const F res = t - yv;
+    const F r2 = res * res;
+    rsq += (double)r2;
+    s2 += r2;
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      const F rl = res * l1[a];
+#pragma unroll
+      for (int b = 0; b < R; ++b) g2[a * R + b] = fma(rl, r3[b], g2[a * R + b]);
+    }
+    double *t1 = tab1 + x1 * RS;
+    double *t3 = tab3 + x3 * RS;
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+      atomicAdd(&t1[a], (double)(res * u[a]));
+      atomicAdd(&t3[a], (double)(res * l2[a]));
+    }
+    atomicAdd(&t1[R], (double)r2);
+    atomicAdd(&t3[R], (double)r2);
+  };
+  // the middle slice v, uniform across the wave: scalar loads (a wave-uniform
+  // address in the constant address space)
+  typedef __attribute__((address_space(4))) const F *cptr;
+  auto slice = [&](F (&S)[RR], int v) {
+    const long long sb = __builtin_amdgcn_readfirstlane((int)(co2 + (long long)v * RR));
+    const cptr Sp = (cptr)((const F *)cores + sb);
+#pragma unroll
+    for (int e = 0; e < RR; ++e) S[e] = Sp[e];
+  };
+  F Sw[RR];            // slice of the segment wv
+#pragma unroll
+  for (int e = 0; e < RR; ++e) Sw[e] = (F)0;
+
+  Grp3 cur, nxt;
+  load(cur, j0);
+  for (long long jb = j0; jb < j1; jb += 64 * G) {
+    // boundary vectors of the whole group, gathered before the next group's
+    // loads are issued: vector loads complete in order, so the wait for
+    // these gathers then leaves the next group's loads in flight
+    F l1[G][R], r3[G][R];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        l1[g][a] = T1[(long long)cur.x1[g] * R + a];
+        r3[g][a] = T3[(long long)cur.x3[g] * R + a];
+      }
+    if (jb + 64 * G < j1) load(nxt, jb + 64 * G);
+    // fast path (segments are long): every sample of the group in segment wv
+    bool other = false;
+#pragma unroll
+    for (int g = 0; g < G; ++g) other = other || (jb + 64 * g + lane < j1 && cur.x2[g] != wv);
+    if (__ballot(other) == 0) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (jb + 64 * g + lane < j1) sample(Sw, l1[g], r3[g], cur.x1[g], cur.x3[g], cur.yv[g]);
+    } else {
+      // a segment starts inside the group: batch by batch, segment by
+      // segment, reading the indices again (cached) so that nothing is
+      // indexed by a run-time batch number in registers
+#pragma unroll 1
+      for (int g = 0; g < G; ++g) {
+        if (jb + 64 * g >= j1) break;   // lane 0 is past the chunk: the rest is empty
+        const long long j = jb + 64 * g + lane;
+        const bool act = j < j1;
+        const long long jc = act ? j : j1 - 1;
+        const int x1 = ix1[jc], x3 = ix3[jc];
+        const int x2 = act ? ix2[jc] : -1;
+        const F yv = y[jc];
+        F lg[R], rg[R];
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+          lg[a] = T1[(long long)x1 * R + a];
+          rg[a] = T3[(long long)x3 * R + a];
+        }
+        unsigned long long pending = __ballot(act);
+        while (pending) {
+          const int first = __ffsll((long long)pending) - 1;
+          const int v = __builtin_amdgcn_readlane(x2, first);
+          const bool me = act && x2 == v;
+          pending &= ~__ballot(me);
+          if (v != wv) {
+            flush();
+            wv = v;
+            slice(Sw, v);
+          }
+          if (me) sample(Sw, lg, rg, x1, x3, yv);
+        }
+      }
+    }
+    cur = nxt;
+  }
+  flush();
+  __syncthreads();
+  // the table, in the compact partial layout: dT_1 rows, dT_3 rows, s_1, s_3
+  const int L = n1 * R + n3 * R + n1 + n3;
+  auto pb = glb((F *)q.part_bnd) + (long long)w * L;
+  for (int i = lane; i < L; i += 64) {
+    int p;
+    if (i < n1 * R) p = (i / R) * RS + i % R;
+    else if (i < (n1 + n3) * R) p = n1 * RS + ((i - n1 * R) / R) * RS + (i - n1 * R) % R;
+    else if (i < (n1 + n3) * R + n1) p = (i - (n1 + n3) * R) * RS + R;
+    else p = n1 * RS + (i - (n1 + n3) * R - n1) * RS + R;
+    pb[i] = (F)tab1[p];
+  }
+  const double tr = wave_total(rsq);
+  if (lane == 0) glb(q.part_rsq)[w] = tr;
+}
+
 hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s);
 
 template <typename F, int R>
+static hipError_t launch3w_t(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main) {
+  size_t lds = 0;
+  int nwg = 1, nred = 1;
+  for (int i = 0; i < bt.ns; ++i) {
+    const Dev &d = bt.host[i];
+    const int n1 = d.n[0], n3 = d.n[2];
+    lds = std::max(lds, (size_t)(n1 + n3) * (R + 1) * sizeof(double));
+    nwg = std::max(nwg, d.q3.nwg);
+    const int L = n1 * R + n3 * R + n1 + n3;
+    const long long nbS = ((long long)d.n[1] * (R * R + 1) + 255) / 256;
+    nred = std::max(nred, (int)((L + 63) / 64 + nbS));
+  }
+  hipLaunchKernelGGL((k_sampled3w<F, R, sampled3w_group<R>()>), dim3(nwg, bt.ns), dim3(64), lds, st, bt.dt, diag);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (after_main && (e = hipEventRecord(after_main, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sampled3_reduce<F, R, true>), dim3(nred, bt.ns), dim3(256), 0, st, bt.dt, diag);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sampled_fin(bt, diag, st);
+}
+
+template <typename F, int R>
 static hipError_t launch3_t(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main) {
+  if constexpr (R <= SAMPLED3W_MAX_R) {
+    if (bt.host[0].q3.wave) return launch3w_t<F, R>(bt, diag, st, after_main);   // the batch shares the variant
+  }
   size_t lds = 0;
   int nwg = 1, nred = 1;
   const int stage = bt.host[0].q3.stage;
@@ -364,7 +652,7 @@ static hipError_t launch3_t(const Batch &bt, int diag, hipStream_t st, hipEvent_
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (after_main && (e = hipEventRecord(after_main, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sampled3_reduce<F, R>), dim3(nred, bt.ns), dim3(256), 0, st, bt.dt, diag);
+  hipLaunchKernelGGL((k_sampled3_reduce<F, R, false>), dim3(nred, bt.ns), dim3(256), 0, st, bt.dt, diag);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sampled_fin(bt, diag, st);
@@ -393,6 +681,11 @@ size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage) {
 }
 
 int sampled3_kseg() { return KSEG; }
+
+size_t sampled3w_lds_bytes(int n1, int n3, int R, int prec) {
+  (void)prec;   // float64 tables for both precisions
+  return (size_t)(n1 + n3) * (R + 1) * 8;
+}
 
 hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main) {
   if (bt.host[0].prec == PREC_MIXED) return launch3_f<float>(bt, diag, st, after_main);

@@ -232,7 +232,7 @@ void prgd_server_s::admit() {
     }
     const Dev &d = s->d;
     const int variant = d.use3 ? 1 : (d.use_chain ? 4 : (d.use_modes ? (d.use_iface ? 3 : 2) : 0));   // sampled-pass kernel family
-    const GroupKey key{d.m, d.R, d.prec + 2 * d.tangent_bf16, variant, d.use3 ? d.q3.stage : 0};
+    const GroupKey key{d.m, d.R, d.prec + 2 * d.tangent_bf16, variant, d.use3 ? (d.q3.wave ? 2 : d.q3.stage) : 0};
     auto it = groups.find(key);
     if (it == groups.end()) {
       auto g = std::make_unique<Group>();

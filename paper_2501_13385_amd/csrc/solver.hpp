@@ -35,6 +35,7 @@ hipError_t fill_f64(double *p, long long n, double v, hipStream_t s);
 hipError_t fill_f32(float *p, long long n, float v, hipStream_t s);
 hipError_t convert_f64_f32(const double *src, float *dst, long long n, hipStream_t s);
 size_t sampled3_lds_bytes(int n1, int n3, int R, int prec, int stage);
+size_t sampled3w_lds_bytes(int n1, int n3, int R, int prec);
 hipError_t launch_sampled3(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main = nullptr);
 hipError_t launch_sampled_modes(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main = nullptr);
 size_t sampled_modes_lds_bytes(int R, int prec);
