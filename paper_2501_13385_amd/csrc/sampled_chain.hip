@@ -70,7 +70,9 @@ struct MmaC<float> {
 // value of lane 16 (l / 16) + N in lane l (DPP row_newbcast)
 template <int N>
 __device__ __forceinline__ int cbcast(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false);
+  // every lane reads a valid source, so the destination's old value is never
+  // kept: the form without one spares a move per broadcast
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + N, 0xF, 0xF, false);
 }
 template <int N>
 __device__ __forceinline__ float cbcast(float v) {
@@ -167,39 +169,55 @@ __device__ __forceinline__ F slice_scatter(F v, int x, int lane) {
   return kept[0];
 }
 
-// One K-step S of a core's gradient tile: the four samples 16 q + S.  AM: A
-// from the uniform l_{u+1} (0) or the staged l_k (1); BM: B from the parked
-// r_{k+1} (0), from column 0 of the last core's slice (1) or e_1 (2).
-template <typename F, int R, int S, int AM, int BM>
-__device__ __forceinline__ void chain_kstep(typename MmaC<F>::acc_t &acc, int xc, int xl, F res, F lamA,
-                                            const F *stg, const F *bsl, const F *tlast, int SL, F bE, int lane) {
+// F with every bit cleared where m = 0 (m is 0 or all ones)
+__device__ __forceinline__ double keep_if(double v, int m) {
+  const long long b = __double_as_longlong(v);
+  const int lo = (int)b & m, hi = (int)(b >> 32) & m;
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float keep_if(float v, int m) { return __int_as_float(__float_as_int(v) & m); }
+
+// A sample's tile position as one word: bit x_hi = x / (16/R) and bit
+// 8 + x_lo, x_lo = x % (16/R); a lane of tile row (or column) block h tests
+// its bit with one signed bit-field extract (0 or all ones)
+template <int R>
+__device__ __forceinline__ int chain_code(int x) {
   constexpr int XH = 16 / R;
-  const int q = lane >> 4, i = lane & 15, a = i % R, h = i / R;
-  const int s = 16 * q + S;
-  const int xs = cbcast<S>(xc);
-  const F rs = cbcast<S>(res);
-  F av;
-  if constexpr (AM == 0) av = lamA;
-  else av = stg[a * 68 + s + q];
-  av = (xs / XH == h) ? av : (F)0;
-  F bv;
-  if constexpr (BM == 0) {
-    bv = bsl[a * 68 + s + q];
-  } else if constexpr (BM == 1) {
-    const int xls = cbcast<S>(xl);
-    bv = tlast[xls * SL + a * R];
-  } else {
-    bv = bE;
-  }
-  bv = (xs % XH == h) ? rs * bv : (F)0;
+  return (1 << ((unsigned)x / XH)) | (256 << ((unsigned)x % XH));
+}
+
+// One K-step S of a core's gradient tile: the four samples 16 q + S, with
+// the operands av (the row's entry of R_j l_k, or of l_{u+1}) and bv (the
+// column's entry of r_{k+1}) already loaded; each is kept where the sample's
+// slice falls in the lane's row or column block.  AM = 0: A is the uniform
+// l_{u+1} and the residual scales B.
+template <typename F, int R, int S, int AM>
+__device__ __forceinline__ void chain_kstep(typename MmaC<F>::acc_t &acc, int wc, F res, F av, F bv, int lane) {
+  const int h = (lane & 15) / R;
+  const int ws = cbcast<S>(wc);   // the sample's chain_code
+  av = keep_if(av, __builtin_amdgcn_sbfe(ws, h, 1));
+  if constexpr (AM == 0) bv = cbcast<S>(res) * bv;
+  bv = keep_if(bv, __builtin_amdgcn_sbfe(ws, 8 + h, 1));
   acc = MmaC<F>::step(av, bv, acc);
 }
 
+// The 16 K-steps of a core's tile.  AM: A from the uniform l_{u+1} (0) or the
+// staged R_j l_k (1); BM: B from the parked r_{k+1} (0), from column 0 of the
+// last core's slice (1) or e_1 (2).  All operand loads are issued before the
+// first MFMA, so that they are in flight together.
 template <typename F, int R, int AM, int BM, int... S>
 __device__ __forceinline__ void chain_mfma(typename MmaC<F>::acc_t &acc, int xc, int xl, F res, F lamA,
                                            const F *stg, const F *bsl, const F *tlast, int SL, F bE, int lane,
                                            std::integer_sequence<int, S...>) {
-  (chain_kstep<F, R, S, AM, BM>(acc, xc, xl, res, lamA, stg, bsl, tlast, SL, bE, lane), ...);
+  const int q = lane >> 4, a = (lane & 15) % R;
+  const int wc = chain_code<R>(xc);
+  F av[sizeof...(S)], bv[sizeof...(S)];
+  if constexpr (AM == 0) ((av[S] = lamA), ...);
+  else ((av[S] = stg[a * 68 + 16 * q + S + q]), ...);
+  if constexpr (BM == 0) ((bv[S] = bsl[a * 68 + 16 * q + S + q]), ...);
+  else if constexpr (BM == 1) ((bv[S] = tlast[cbcast<S>(xl) * SL + a * R]), ...);
+  else ((bv[S] = bE), ...);
+  (chain_kstep<F, R, S, AM>(acc, wc, res, av[S], bv[S], lane), ...);
 }
 
 // 16-byte LDS vector of the working precision
@@ -454,7 +472,7 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
           F *stg = wsl + (c - 1) * SLOTW;   // r_{u+c} there was read by core c - 1
           F *dst = stg + lane + (lane >> 4);
 #pragma unroll
-          for (int a = 0; a < R; ++a) dst[a * 68] = lam[a];
+          for (int a = 0; a < R; ++a) dst[a * 68] = res * lam[a];
           chain_wave_order();
           chain_left_step<F, R>(lam, lc + loff[c] + xk[c] * SL);
           chain_mfma<F, R, 1, 0>(acc[c], xk[c], xl, res, lamA, stg, wsl + c * SLOTW, tlast, SL, bE, lane,
@@ -468,7 +486,7 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
       if (ng >= 1) {
         F *dst = stg + lane + (lane >> 4);
 #pragma unroll
-        for (int a = 0; a < R; ++a) dst[a * 68] = lam[a];
+        for (int a = 0; a < R; ++a) dst[a * 68] = res * lam[a];
         chain_wave_order();
         chain_left_step<F, R>(lam, lc + lo_pen + xp * SL);
         chain_mfma<F, R, 1, 1>(accP, xp, xl, res, lamA, stg, wsl, tlast, SL, bE, lane,
@@ -485,7 +503,7 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
       if (nc >= 2) {
         F *dst = stg + lane + (lane >> 4);
 #pragma unroll
-        for (int a = 0; a < R; ++a) dst[a * 68] = lam[a];
+        for (int a = 0; a < R; ++a) dst[a * 68] = res * lam[a];
         chain_wave_order();
         chain_mfma<F, R, 1, 2>(accL, xl, xl, res, lamA, stg, wsl, tlast, SL, bE, lane,
                                std::make_integer_sequence<int, 16>{});
