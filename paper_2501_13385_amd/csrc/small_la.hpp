@@ -96,6 +96,21 @@ __device__ __forceinline__ unsigned long long key_max32(unsigned long long k) {
   return o > k ? o : k;
 }
 
+// max of a 32-bit key over each group of 32 lanes: DPP exchanges inside rows
+// of 16 lanes (each folded by the compiler into a v_max_u32 with a DPP source)
+// and one swap of the rows.  Whole wave active.
+__device__ __forceinline__ unsigned key_max32_u32(unsigned k) {
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0xB1, 0xF, 0xF, false));   // lane ^ 1
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x4E, 0xF, 0xF, false));   // lane ^ 2
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x141, 0xF, 0xF, false));  // i <-> 7 - i in 8
+  k = max(k, (unsigned)__builtin_amdgcn_mov_dpp((int)k, 0x140, 0xF, 0xF, false));  // i <-> 15 - i in 16
+  const auto sw = __builtin_amdgcn_permlane16_swap(k, k, false, false);
+  // [0] holds rows (0, 0, 2, 2) and [1] rows (1, 1, 3, 3) of the input
+  const bool odd = (threadIdx.x >> 4) & 1;
+  const unsigned o = odd ? (unsigned)sw[0] : (unsigned)sw[1];
+  return max(k, o);
+}
+
 // Pivoted Cholesky of a symmetric positive semidefinite n x n matrix A (ld n,
 // n <= 32, read only): F (ld n) gets columns 0..rank-1 with F F^T = A up to
 // pivots below n * 2.3e-16 * max diag.  Returns the rank (in every thread).
@@ -104,9 +119,10 @@ __device__ __forceinline__ unsigned long long key_max32(unsigned long long k) {
 // holds half of row l & 31 of the working matrix in registers (columns
 // 16 (l >> 5) .. + 15) and that row's diagonal entry.  The pivot (largest
 // remaining diagonal entry) is found with a key holding the entry's bits
-// (monotone for non-negative doubles) above 5 bits of 31 - row, so among
-// entries equal to 27 bits the smallest row wins; its exact value is then read
-// from the owning lane.
+// (the high word of a non-negative double is monotone in its value) with its
+// low 5 bits replaced by 31 - row, so among entries equal to 15 mantissa bits
+// the smallest row wins (any such pivot is as good for the factorisation);
+// its exact value is then read from the owning lane.
 __device__ inline int block_pivoted_cholesky(const double *A, int n, double *F) {
   __shared__ double fcol[32];
   __shared__ int rank_s;
@@ -128,20 +144,17 @@ __device__ inline int block_pivoted_cholesky(const double *A, int n, double *F) 
     bool avail = i < n;  // row not yet a pivot
     int rank = 0;
     for (int k = 0; k < n; ++k) {
-      const unsigned long long bits = (unsigned long long)__double_as_longlong(fmax(dg, 0.0));
-      const unsigned long long key = avail ? ((bits & ~31ull) | (unsigned long long)(31 - i)) : 0ull;
-      const unsigned long long kmax = key_max32(key);
-      const int p = 31 - (int)(__builtin_amdgcn_readfirstlane((unsigned)kmax) & 31u);
+      const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(fmax(dg, 0.0)) >> 32);
+      const unsigned key = avail ? ((hi & ~31u) | (unsigned)(31 - i)) : 0u;
+      const unsigned kmax = __builtin_amdgcn_readfirstlane(key_max32_u32(key));
+      const int p = 31 - (int)(kmax & 31u);
       const double best = lane_value(dg, p);
-      if (kmax == 0ull || !(best > tol)) break;
+      if (kmax == 0u || !(best > tol)) break;
       rank = k + 1;
       const double rs = rsq_newton<2>(best);  // 1 / sqrt(pivot)
-      // this row's entry in column p, from the lane holding that column
-      const int cp = p & 15;
-      double colv = a[0];
-#pragma unroll
-      for (int c = 1; c < 16; ++c) colv = (c == cp) ? a[c] : colv;
-      const double x = half_value(colv, p >= 16);
+      // this row's entry in column p, from the lane holding that column (the
+      // register index is wave-uniform)
+      const double x = half_value(a[p & 15], p >= 16);
       const double f = (i == p || avail) && i < n ? x * rs : 0.0;
       if (i == p) avail = false;
       dg = fma(-f, f, dg);
