@@ -123,6 +123,30 @@ __device__ __forceinline__ double xor_lane(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// value of a partner lane that differs from lane in bit OFF and agrees with it
+// in the bits above OFF (the butterfly steps below need only that): OFF 32 and
+// 16 by permlane swaps, 8 and 4 by the row and half-row mirrors, 2 and 1 by
+// quad permutations (DPP, no LDS round trip)
+template <int OFF>
+__device__ __forceinline__ int pair_lane(int v, int lane) {
+  if constexpr (OFF == 32) return xor32(v, lane);
+  else if constexpr (OFF == 16) return xor16(v, lane);
+  else if constexpr (OFF == 8) return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);
+  else if constexpr (OFF == 4) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);
+  else if constexpr (OFF == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  else return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+}
+template <int OFF>
+__device__ __forceinline__ float pair_lane(float v, int lane) {
+  return __int_as_float(pair_lane<OFF>(__float_as_int(v), lane));
+}
+template <int OFF>
+__device__ __forceinline__ double pair_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = pair_lane<OFF>((int)b, lane), hi = pair_lane<OFF>((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Sizes shared by the host plan and the kernel.
 template <int R>
 struct ChainShape {
@@ -149,7 +173,7 @@ __device__ __forceinline__ void scatter_halve(F (&kept)[NX / 2], int lane) {
 #pragma unroll
     for (int i = 0; i < H / 2; ++i) {
       const F send = hb ? kept[i] : kept[H / 2 + i];
-      const F recv = xor_lane<OFF>(send, lane);
+      const F recv = pair_lane<OFF>(send, lane);
       kept[i] = (hb ? kept[H / 2 + i] : kept[i]) + recv;
     }
     scatter_halve<F, NX, H / 2, OFF / 2>(kept, lane);
@@ -309,8 +333,12 @@ __device__ __forceinline__ void chain_right_step(F (&rho)[R], const F *sl) {
 // slice_scatter every such lane holds a part of the same slice's sum).
 template <typename F, int NX>
 __device__ __forceinline__ F slice_finish(F v, int lane) {
-#pragma unroll
-  for (int o = 64 / NX / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  constexpr int G = 64 / NX;   // lanes per slice: 16 or 4
+  static_assert(G <= 16, "a slice's lanes must lie in one row of 16");
+  if constexpr (G >= 16) v += pair_lane<8>(v, lane);
+  if constexpr (G >= 8) v += pair_lane<4>(v, lane);
+  if constexpr (G >= 4) v += pair_lane<2>(v, lane);
+  if constexpr (G >= 2) v += pair_lane<1>(v, lane);
   return v;
 }
 
