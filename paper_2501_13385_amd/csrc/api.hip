@@ -770,7 +770,29 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
       seg[key + 1]++;
     }
     for (long long v = 0; v < span; ++v) seg[v + 1] += seg[v];
-    const long long cmax = chain_chunk_max(N);
+    // the largest chunk: from the base size up to four times it, the one
+    // whose chunk count fills the last round of resident workgroups best (the
+    // chunks of a launch run in rounds of one workgroup per CU and LDS slot;
+    // 1,043 chunks on 256 CUs would take five rounds for four rounds of work)
+    const long long resident =
+        256LL * std::max<long long>(1, (long long)(163840 / std::max<size_t>(1, chain_lds_bytes(m, u, s->n.data(), R, d.prec))));
+    auto chunks_for = [&](long long cm) {
+      long long c = 0;
+      for (long long v = 0; v < span; ++v)
+        if (seg[v + 1] > seg[v]) c += (seg[v + 1] - seg[v] + cm - 1) / cm;
+      return c;
+    };
+    const long long c0 = chain_chunk_max(N);
+    long long cmax = c0;
+    double best_fill = -1.0;
+    for (long long cm = c0; cm <= 4 * c0; cm += c0 / 4 > 64 ? c0 / 4 : 64) {
+      const long long c = chunks_for(cm);
+      const double fill = (double)c / (double)(((c + resident - 1) / resident) * resident);
+      if (fill > best_fill + 0.02) {
+        best_fill = fill;
+        cmax = cm;
+      }
+    }
     std::vector<int> cstart, clen;
     for (long long v = 0; v < span; ++v) {
       const long long a = seg[v], b = seg[v + 1];
