@@ -377,38 +377,52 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
   F *wsl = lc + lo + (long long)w * region;
   F *wss = lc + lo + (long long)NW * region + (long long)w * WS;   // this wave's slice sums
   F *lamu_s = lc + lo + (long long)NW * region + (long long)NW * WS;   // l_{u+1}, shared
+  F *pre_l = lamu_s + R;         // [u][R]: l_k = e_1^T T_0(x_0) .. T_{k-1}(x_{k-1})
+  F *pre_sl = lc + lo;           // [u][R^2]: the chunk's prefix slices T_k(x_k), k < u (in
+                                 // the wave slots, free until the batch loop)
   for (int i = lane; i < WS; i += 64) wss[i] = (F)0;
-  for (int c = 0; c < nc; ++c) {
-    const int k = u + c, nk = d.n[k];
-    int base = 0;
-    for (int cc = 0; cc < c; ++cc) base += d.n[u + cc] * SL;
-    for (int i = threadIdx.x; i < nk * RR; i += NT) lc[base + (i / RR) * SL + i % RR] = gcores[d.coff[k] + i];
-  }
   const int cs = glb(d.ch_start)[blockIdx.x], cl = glb(d.ch_len)[blockIdx.x];
-  // l_{u+1}: the same for every sample of the chunk
-  F lamu[R];
+  // one flat pass over the staged cores and the prefix slices, so that each
+  // thread's loads are independent and in flight together
+  {
+    int cend[MAXC];   // element ends of the staged cores
+    int acc_e = 0;
 #pragma unroll
-  for (int a = 0; a < R; ++a) lamu[a] = a == 0 ? (F)1 : (F)0;
-  for (int k = 0; k < u; ++k) {
-    const int x = __builtin_amdgcn_readfirstlane(idx[(long long)k * N + cs]);
-    const auto sl = gcores + d.coff[k] + (long long)x * RR;
-    F nl[R];
+    for (int c = 0; c < MAXC; ++c) {
+      if (c < nc) acc_e += d.n[u + c] * RR;
+      cend[c] = acc_e;
+    }
+    const int ntot = acc_e + u * RR;
+#pragma unroll 4
+    for (int i = threadIdx.x; i < ntot; i += NT) {
+      if (i < acc_e) {
+        int c = 0;
 #pragma unroll
-    for (int b = 0; b < R; ++b) {
+        for (int cc = 0; cc < MAXC - 1; ++cc) c += (i >= cend[cc]) ? 1 : 0;
+        const int rem = i - (c > 0 ? cend[c - 1] : 0);
+        lc[loff[c] + (rem / RR) * SL + rem % RR] = gcores[d.coff[u + c] + rem];
+      } else {
+        const int t = i - acc_e, k = t / RR, e = t % RR;
+        const int x = idx[(long long)k * N + cs];
+        pre_sl[t] = gcores[d.coff[k] + (long long)x * RR + e];
+      }
+    }
+  }
+  __syncthreads();
+  // l_0 .. l_u along the prefix: the same for every sample of the chunk
+  // (lanes b < R of the first wave, one vector-matrix step at a time)
+  if (threadIdx.x < R) {
+    const int b = threadIdx.x;
+    F lb = b == 0 ? (F)1 : (F)0;
+    for (int k = 0; k < u; ++k) {
+      pre_l[k * R + b] = lb;
+      chain_wave_order();
       F t = (F)0;
 #pragma unroll
-      for (int a = 0; a < R; ++a) t = fma(lamu[a], sl[a * R + b], t);
-      nl[b] = t;
+      for (int a = 0; a < R; ++a) t = fma(pre_l[k * R + a], pre_sl[k * RR + a * R + b], t);
+      lb = t;
     }
-#pragma unroll
-    for (int b = 0; b < R; ++b) lamu[b] = nl[b];
-  }
-  if (threadIdx.x < R) {
-    F v = (F)0;
-#pragma unroll
-    for (int a = 0; a < R; ++a)
-      if (a == (int)threadIdx.x) v = lamu[a];
-    lamu_s[threadIdx.x] = v;
+    lamu_s[b] = lb;
   }
   // e_1 in the MFMA lane layout: the A operand of core u+1 (whose tile then
   // holds G_x = sum R_j r_{u+2}; l_{u+1} is applied once per chunk) and the B
@@ -546,6 +560,17 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
   // ---- per-chunk partial: waves summed in LDS in wave order ----
   __shared__ double sbuf[16];
   const double rs_tot = block_sum(rsq, sbuf);    // ends with a barrier: every wave is past its slots
+  // the prefix slices again for the shared cores' gradients, in the staged
+  // cores past core u+1 (no longer read) when they fit there, else read from
+  // global memory one step at a time
+  const bool pre_in_lds = u * RR <= lo - loff[1 < MAXC ? 1 : 0];
+  F *pre_sl2 = lc + loff[1 < MAXC ? 1 : 0];
+  if (u > 0 && pre_in_lds)
+    for (int t = threadIdx.x; t < u * RR; t += NT) {
+      const int k = t / RR, e = t % RR;
+      const int x = idx[(long long)k * N + cs];
+      pre_sl2[t] = gcores[d.coff[k] + (long long)x * RR + e];
+    }
   F *red = lc + lo;                              // reuses the slots: per wave tiles then slice sums
   auto put_core = [&](int c, const typename M::acc_t &tile) {
 #pragma unroll
@@ -599,24 +624,10 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
       V[a] = v;
     }
     for (int k = u - 1; k >= 0; --k) {
-      // l_k from the chunk's prefix
+      // l_k and T_k(x_k) of the chunk's prefix, staged by the prologue
       F l[R];
 #pragma unroll
-      for (int a = 0; a < R; ++a) l[a] = a == 0 ? (F)1 : (F)0;
-      for (int kk = 0; kk < k; ++kk) {
-        const int x = __builtin_amdgcn_readfirstlane(idx[(long long)kk * N + cs]);
-        const auto sl = gcores + d.coff[kk] + (long long)x * RR;
-        F nl[R];
-#pragma unroll
-        for (int b = 0; b < R; ++b) {
-          F t = (F)0;
-#pragma unroll
-          for (int a = 0; a < R; ++a) t = fma(l[a], sl[a * R + b], t);
-          nl[b] = t;
-        }
-#pragma unroll
-        for (int b = 0; b < R; ++b) l[b] = nl[b];
-      }
+      for (int a = 0; a < R; ++a) l[a] = pre_l[k * R + a];
       if (lane < RR) {
         F g = (F)0;
 #pragma unroll
@@ -626,8 +637,10 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
             if (a * R + b == lane) g = l[a] * V[b];
         part[WT + WS + k * RR + lane] = g;
       }
-      const int x = __builtin_amdgcn_readfirstlane(idx[(long long)k * N + cs]);
-      const auto sl = gcores + d.coff[k] + (long long)x * RR;
+      const F *sl = pre_in_lds
+                        ? (const F *)(pre_sl2 + k * RR)
+                        : (const F *)(gcores + d.coff[k] +
+                                      (long long)__builtin_amdgcn_readfirstlane(idx[(long long)k * N + cs]) * RR);
       F nv[R];
 #pragma unroll
       for (int a = 0; a < R; ++a) {
@@ -740,7 +753,8 @@ size_t chain_lds_bytes(int m, int u, const int *n, int R, int prec) {
   const size_t slots = (size_t)chain_nslots(nc) * chain_slot_width(R);
   const size_t red = (size_t)nc * (256 + chain_nx(R));
   const size_t wss = (size_t)nc * chain_nx(R);
-  return (cores + 4 * std::max(slots, red) + 4 * wss + R) * f;
+  const size_t prefix = (size_t)u * R;   // the chunk's prefix interfaces
+  return (cores + 4 * std::max(slots, red) + 4 * wss + R + prefix) * f;
 }
 
 int chain_maxc(int nc) { return nc <= 4 ? 4 : (nc <= 8 ? 8 : (nc <= 10 ? 10 : (nc <= 12 ? 12 : 16))); }
