@@ -26,7 +26,7 @@
  *   - Host pointers are read only during the call that receives them; the
  *     library copies what it keeps.  Device pointers (mem_device = 1) must be
  *     device memory of the current HIP device, readable for the duration of
- *     the call.
+ *     the call; they are validated on the device (no copy to the host).
  *   - Return codes: prgd_status values below.  No exception crosses the ABI.
  *     A negative code leaves output buffers unspecified; prgd_last_error()
  *     returns a thread-local message for the last failing call.

@@ -242,6 +242,8 @@ bool has_repeated_multi_index(int m, const int32_t *n, long long N, const int32_
   return false;
 }
 
+// Checks of the descriptor; with idx and vals (host copies of Omega) also the
+// observations (indices in range, values finite, no repeated multi-index).
 prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *vals, int64_t &numel) {
   const int m = ds->order;
   if (m < 2 || m > MAXM) return fail(m < 2 ? PRGD_EINVAL : PRGD_ENOTSUP, "order must be in [2, 32]");
@@ -279,6 +281,7 @@ prgd_status validate_host(const prgd_desc *ds, const int32_t *idx, const void *v
   if (ds->truth_cores)
     for (int64_t i = 0; i < numel; ++i)
       if (!std::isfinite(ds->truth_cores[i])) return fail(PRGD_EINVAL, "truth_cores has a non-finite entry");
+  if (!idx || !vals) return PRGD_OK;   // device-resident Omega: checked on the device
   // indices in range, values finite
   for (int k = 0; k < m; ++k) {
     const int32_t *row = idx + (long long)k * N;
@@ -472,19 +475,11 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   const long long N = ds->n_obs;
   const size_t vbytes = ds->values_fp64 ? sizeof(double) : sizeof(float);
 
-  // host copies for validation (device inputs are brought over once)
-  std::vector<int32_t> hidx;
-  std::vector<unsigned char> hval;
-  const int32_t *idx_h = ds->indices;
-  const void *val_h = ds->values;
-  if (ds->mem_device) {
-    hidx.resize((size_t)m * N);
-    hval.resize((size_t)N * vbytes);
-    HIPCHECK(hipMemcpy(hidx.data(), ds->indices, hidx.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    HIPCHECK(hipMemcpy(hval.data(), ds->values, hval.size(), hipMemcpyDeviceToHost));
-    idx_h = hidx.data();
-    val_h = hval.data();
-  }
+  // Omega on the host, or (device buffers) checked and summarised on the
+  // device below without a copy back: idx_h / val_h are then null
+  const int32_t *idx_h = ds->mem_device ? nullptr : ds->indices;
+  const void *val_h = ds->mem_device ? nullptr : ds->values;
+  (void)vbytes;
   int64_t numel = 0;
   if (validated) {
     if (!checked_numel(m, ds->mode_sizes, ds->tt_ranks, numel)) return fail(PRGD_EINVAL, "invalid mode sizes or ranks");
@@ -506,6 +501,13 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return cleanup(fail(PRGD_EDEVICE, "hipStreamCreate failed"));
     s->own_stream = true;
+  }
+  // a device-resident Omega is checked (and y^2 summed) on the device
+  double ysq_dev = 0.0;
+  if (ds->mem_device) {
+    const prgd_status vs =
+        check_obs_device(m, N, ds->mode_sizes, ds->indices, ds->values, ds->values_fp64, ysq_dev, s->stream);
+    if (vs != PRGD_OK) return cleanup(vs);
   }
   s->m = m;
   s->N = N;
@@ -638,11 +640,12 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   }
   // state and constant small matrices
   State st0{};
-  double ysq = 0.0;
-  for (long long j = 0; j < N; ++j) {
-    const double v = ds->values_fp64 ? ((const double *)val_h)[j] : (double)((const float *)val_h)[j];
-    ysq += v * v;
-  }
+  double ysq = ysq_dev;
+  if (val_h)
+    for (long long j = 0; j < N; ++j) {
+      const double v = ds->values_fp64 ? ((const double *)val_h)[j] : (double)((const float *)val_h)[j];
+      ysq += v * v;
+    }
   st0.y_sq = ysq;
   st0.alpha_n = 0.0;
   st0.rel_change = NAN;
@@ -668,6 +671,22 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     if (fill_f64((double *)d.Y, pn, 0.0, s->stream) != hipSuccess || fill_f64((double *)d.s, soff, 0.0, s->stream) != hipSuccess)
       return cleanup(fail(PRGD_EDEVICE, "fill failed"));
   }
+  // samples per index value of `mode` (or per mixed-radix key of the first u
+  // modes when mode < 0) as offsets seg[0..bins]: from the host copy of Omega,
+  // or counted on the device from the grouped copy
+  auto counts = [&](int mode, int u, long long bins, std::vector<long long> &seg) -> bool {
+    if (!idx_h) return count_obs_device(m, N, ds->mode_sizes, d.idx, mode, u, bins, seg, s->stream) == hipSuccess;
+    seg.assign((size_t)bins + 1, 0);
+    for (long long j = 0; j < N; ++j) {
+      long long v = 0;
+      if (mode >= 0) v = idx_h[(long long)mode * N + j];
+      else
+        for (int k = 0; k < u; ++k) v = v * s->n[k] + idx_h[(long long)k * N + j];
+      seg[v + 1]++;
+    }
+    for (long long v = 0; v < bins; ++v) seg[v + 1] += seg[v];
+    return true;
+  };
   // order-3 grouped sampled pass: per-workgroup chunks of the samples sorted by the middle mode
   if (m == 3 && sm == 1 && sampled3_lds_bytes(s->n[0], s->n[2], R, d.prec, 0) <= 163840) {
     S3 &q = d.q3;
@@ -692,9 +711,8 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     nwg = (N + q.chunk - 1) / q.chunk;
     q.nwg = (int)nwg;
     const int n1 = s->n[1];
-    std::vector<long long> seg(n1 + 1, 0);
-    for (long long j = 0; j < N; ++j) seg[idx_h[N + j] + 1]++;
-    for (int v = 0; v < n1; ++v) seg[v + 1] += seg[v];
+    std::vector<long long> seg;
+    if (!counts(1, 0, n1, seg)) return cleanup(fail(PRGD_EDEVICE, "counting the middle-mode slices failed"));
     std::vector<int> vfirst(nwg), vlast(nwg), blo(n1), bhi(n1);
     for (long long b = 0; b < nwg; ++b) {
       const long long j0 = b * q.chunk, jl = std::min(N, j0 + q.chunk) - 1;
@@ -763,13 +781,8 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
     const int u = chain_u;
     long long span = 1;
     for (int k = 0; k < u; ++k) span *= s->n[k];
-    std::vector<long long> seg((size_t)span + 1, 0);
-    for (long long j = 0; j < N; ++j) {
-      long long key = 0;
-      for (int k = 0; k < u; ++k) key = key * s->n[k] + idx_h[(long long)k * N + j];
-      seg[key + 1]++;
-    }
-    for (long long v = 0; v < span; ++v) seg[v + 1] += seg[v];
+    std::vector<long long> seg;
+    if (!counts(-1, u, span, seg)) return cleanup(fail(PRGD_EDEVICE, "counting the index prefixes failed"));
     // the largest chunk: from the base size up to four times it, the one
     // whose chunk count fills the last round of resident workgroups best (the
     // chunks of a launch run in rounds of one workgroup per CU and LDS slot;
@@ -865,9 +878,8 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
       wg0 += (int)nwg;
       t.out0 = out0;
       out0 += (long long)nk * segw;
-      std::vector<long long> seg(nk + 1, 0);
-      for (long long j = 0; j < N; ++j) seg[idx_h[(long long)k * N + j] + 1]++;
-      for (int v = 0; v < nk; ++v) seg[v + 1] += seg[v];
+      std::vector<long long> seg;
+      if (!counts(k, 0, nk, seg)) return cleanup(fail(PRGD_EDEVICE, "counting the mode slices failed"));
       std::vector<int> vfirst(nwg), blo(nk), bhi(nk);
       for (long long b = 0; b < nwg; ++b)
         vfirst[b] = (int)(std::upper_bound(seg.begin(), seg.end(), b * t.chunk) - seg.begin()) - 1;

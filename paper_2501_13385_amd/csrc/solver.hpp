@@ -113,4 +113,11 @@ prgd_status validate_desc(const prgd_desc *ds, const int32_t *idx_host, const vo
 int64_t solver_footprint(const prgd_desc *ds);
 // Record a failure message for prgd_last_error() and return st.
 prgd_status set_error(prgd_status st, const char *msg);
+// observation set in device memory: range, finiteness and repeated
+// multi-index checks with sum of y^2 (validate.hip); sample counts per index
+// value of one mode (mode >= 0) or per mixed-radix key of the first u modes
+prgd_status check_obs_device(int m, long long N, const int *n, const int *idx, const void *val, int values_fp64,
+                             double &ysq, hipStream_t s);
+hipError_t count_obs_device(int m, long long N, const int *n, const int *idx, int mode, int u, long long bins,
+                            std::vector<long long> &seg, hipStream_t s);
 }  // namespace prgd
