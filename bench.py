@@ -292,6 +292,7 @@ def copy_calibration(reps=5):
 MAIN_KERNEL = {
     "c4": ("k_chain", "sampled_chain.hip"),
     "c2": ("k_sampled3", "sampled3.hip"),
+    "hbm3": ("k_sampled3w", "sampled3.hip"),
 }
 
 
@@ -448,8 +449,10 @@ def main():
                 if prec in res and res[prec].get("k1_ms"):
                     b = sampled_pass_bytes(pbw.shape, pbw.n_obs, 8 if prec == "fp64" else 4)
                     gbs = b / (res[prec]["k1_ms"] * 1e-3) / 1e9
-                    res[prec]["hbm_roofline"] = {"bytes_per_launch": b, "achieved_GBs": gbs, "peak_GBs": PEAK_HBM_GBS,
-                                                 "frac": gbs / PEAK_HBM_GBS}
+                    res[prec]["hbm_roofline"] = {"kernel": MAIN_KERNEL[w][0] if w in MAIN_KERNEL else None,
+                                                 "bytes_per_launch": b, "achieved_GBs": gbs, "peak_GBs": PEAK_HBM_GBS,
+                                                 "frac": gbs / PEAK_HBM_GBS,
+                                                 "traffic": measured_traffic(prec, w) if w in MAIN_KERNEL else None}
         others[w] = res
     line["workloads"] = others
     if not args.no_serving:

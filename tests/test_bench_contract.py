@@ -46,7 +46,7 @@ def test_sampled_pass_work_per_launch_for_the_order14_workload(bench):
     assert bench.sampled_pass_bytes(shape, 2_000_000, 8) == (4 * 14 + 8) * 2_000_000
 
 
-@pytest.mark.parametrize("workload", ["c2", "c4"])
+@pytest.mark.parametrize("workload", ["c2", "c4", "hbm3"])
 def test_recorded_traffic_matches_the_current_kernel_source(bench, workload):
     path = bench.traffic_path(workload)
     if not os.path.exists(path):
