@@ -1178,6 +1178,63 @@ __global__ void __launch_bounds__(1024) k_cross_fused(const Dev *__restrict__ dt
   cross_fin_body(d, 0, c, mode, smem);
 }
 
+// Whole sweeps in one launch when every step of the sweep is small (at most
+// FUSE_MAX slice blocks): one workgroup per solve runs the steps in order
+// with a workgroup barrier between dependent steps, in place of one launch
+// per step.  Steps, arithmetic and order are those of the per-step launches.
+__global__ void __launch_bounds__(1024) k_gram_sweep(const Dev *__restrict__ dt) {
+  __shared__ double smem[SMEM];
+  const Dev &d = dt[blockIdx.y];
+  const int m = d.m;
+  for (int j = 1; j <= m - 1; ++j) {
+    const int g = nblocks_for(d.n[j - 1], 8) + nblocks_for(d.n[m - j], 8);
+    for (int bx = 0; bx < g; ++bx) {
+      gram_body(d, bx, j, smem);
+      __syncthreads();
+    }
+    gram_fin_body(d, 0, j, smem);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_retract_sweep(const Dev *__restrict__ dt) {
+  __shared__ double smem[SMEM_CUT];
+  const Dev &d = dt[blockIdx.y];
+  const int m = d.m;
+  for (int b = m - 1; b >= 1; --b) {   // right Grams; b = 1 also truncates cut 1
+    const int g = nblocks_for(d.n[b], 4) + (b == m - 1 ? nblocks_for(d.n[0], 4) : 0);
+    for (int bx = 0; bx < g; ++bx) {
+      rgram_body(d, bx, b, smem);
+      __syncthreads();
+    }
+    rgram_fin_body(d, 0, b, smem);
+    __syncthreads();
+  }
+  for (int i = 2; i <= m - 1; ++i) {   // the truncated left sweep
+    const int g = nblocks_for(d.n[i - 1], 4);
+    for (int bx = 0; bx < g; ++bx) {
+      left_body(d, bx, i, smem);
+      __syncthreads();
+    }
+    left_fin_body(d, 0, i, smem);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_cross_sweep(const Dev *__restrict__ dt, int mode) {
+  __shared__ double smem[SMEM];
+  const Dev &d = dt[blockIdx.y];
+  for (int c = 0; c < d.m; ++c) {
+    const int g = nblocks_for(d.n[c], 4);
+    for (int bx = 0; bx < g; ++bx) {
+      cross_body(d, bx, c, mode, smem);
+      __syncthreads();
+    }
+    cross_fin_body(d, 0, c, mode, smem);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers (grids sized for the largest member of the batch)
 // ---------------------------------------------------------------------------
@@ -1193,7 +1250,11 @@ static int max_over(const Batch &b, Fn f) {
 // phase 1: metric-weighted Gram sweeps and the tangent components
 hipError_t launch_project(const Batch &bt, hipStream_t s) {
   const int m = bt.host[0].m, ns = bt.ns;
-  for (int j = 1; j <= m - 1; ++j) {
+  int gmax = 1;
+  for (int j = 1; j <= m - 1; ++j)
+    gmax = std::max(gmax, max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 8) + nblocks_for(d.n[m - j], 8); }));
+  if (gmax <= FUSE_MAX) hipLaunchKernelGGL(k_gram_sweep, dim3(1, ns), dim3(1024), 0, s, bt.dt);
+  for (int j = 1; j <= m - 1 && gmax > FUSE_MAX; ++j) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 8) + nblocks_for(d.n[m - j], 8); });
     if (g <= FUSE_MAX) {
       hipLaunchKernelGGL(k_gram_fused, dim3(1, ns), dim3(1024), 0, s, bt.dt, j, g);
@@ -1215,6 +1276,17 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
 // phase 2: retraction sweeps (right Grams of W_l, then the truncated left sweep)
 hipError_t launch_retract(const Batch &bt, hipStream_t s) {
   const int m = bt.host[0].m, ns = bt.ns;
+  int gmax = 1;
+  for (int b = m - 1; b >= 1; --b)
+    gmax = std::max(gmax, max_over(bt, [&](const Dev &d) {
+      return nblocks_for(d.n[b], 4) + (b == m - 1 ? nblocks_for(d.n[0], 4) : 0);
+    }));
+  for (int i = 2; i <= m - 1; ++i)
+    gmax = std::max(gmax, max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[i - 1], 4); }));
+  if (gmax <= FUSE_MAX) {
+    hipLaunchKernelGGL(k_retract_sweep, dim3(1, ns), dim3(1024), 0, s, bt.dt);
+    return hipGetLastError();
+  }
   for (int b = m - 1; b >= 1; --b) {
     const int g = max_over(bt, [&](const Dev &d) {
       return nblocks_for(d.n[b], 4) + (b == m - 1 ? nblocks_for(d.n[0], 4) : 0);
@@ -1260,6 +1332,12 @@ hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode) {
   bool any = false;
   for (int i = 0; i < ns; ++i) any = any || bt.host[i].has_truth;
   if (!any) return hipSuccess;
+  int gmax = 1;
+  for (int c = 0; c < m; ++c) gmax = std::max(gmax, max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[c], 4); }));
+  if (gmax <= FUSE_MAX) {
+    hipLaunchKernelGGL(k_cross_sweep, dim3(1, ns), dim3(1024), 0, s, bt.dt, mode);
+    return hipGetLastError();
+  }
   for (int c = 0; c < m; ++c) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[c], 4); });
     if (g <= FUSE_MAX) {
