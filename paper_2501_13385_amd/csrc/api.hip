@@ -772,7 +772,7 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
   d.use_chain = 0;
   d.ch_u = 0;
   d.ch_nchunks = 0;
-  d.ch_start = d.ch_len = nullptr;
+  d.ch_start = d.ch_len = d.ch_x = nullptr;
   d.ch_part = nullptr;
   d.ch_rsq = d.ch_red = nullptr;
   if (!d.use3 && chain_cand) {
@@ -806,7 +806,7 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
         cmax = cm;
       }
     }
-    std::vector<int> cstart, clen;
+    std::vector<int> cstart, clen, cx;
     for (long long v = 0; v < span; ++v) {
       const long long a = seg[v], b = seg[v + 1];
       if (b <= a) continue;
@@ -815,23 +815,34 @@ prgd_status solver_create(const prgd_desc *ds, prgd_solver *out, bool validated)
         const long long lo = a + (b - a) * p / pieces, hi = a + (b - a) * (p + 1) / pieces;
         cstart.push_back((int)lo);
         clen.push_back((int)(hi - lo));
+        // the prefix x_0 .. x_{u-1} of segment v (mixed radix, mode 1 most significant)
+        long long r = v;
+        const size_t at = cx.size();
+        cx.resize(at + (size_t)u);
+        for (int k = u - 1; k >= 0; --k) {
+          cx[at + k] = (int)(r % s->n[k]);
+          r /= s->n[k];
+        }
       }
     }
     const int nch = (int)cstart.size();
     const long long W = chain_part_width(m, u, R);
     const long long nout = (long long)soff * (R * R + 1);
     const long long ng = (nch + 31) / 32;
-    int *dst = nullptr, *dln = nullptr;
+    int *dst = nullptr, *dln = nullptr, *dcx = nullptr;
     unsigned char *pp = nullptr;
-    if (!A(s->alloc(&dst, nch)) || !A(s->alloc(&dln, nch)) || !A(s->alloc(&pp, (long long)nch * W * (mixed ? 4 : 8))) ||
+    if (!A(s->alloc(&dst, nch)) || !A(s->alloc(&dln, nch)) || !A(s->alloc(&dcx, std::max<long long>(1, (long long)nch * u))) ||
+        !A(s->alloc(&pp, (long long)nch * W * (mixed ? 4 : 8))) ||
         !A(s->alloc(&d.ch_rsq, nch)) || !A(s->alloc(&d.ch_red, ng * nout)))
       return cleanup(fail(PRGD_ENOMEM, "device allocation failed"));
     if (hipMemcpyAsync(dst, cstart.data(), nch * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(dln, clen.data(), nch * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        (u > 0 && hipMemcpyAsync(dcx, cx.data(), cx.size() * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess) ||
         hipStreamSynchronize(s->stream) != hipSuccess)
       return cleanup(fail(PRGD_EDEVICE, "upload of the chunk table failed"));
     d.ch_start = dst;
     d.ch_len = dln;
+    d.ch_x = dcx;
     d.ch_part = pp;
     d.ch_u = u;
     d.ch_nchunks = nch;

@@ -186,6 +186,7 @@ struct Dev {
   int ch_nchunks;
   const int *ch_start;         // [ch_nchunks] first sample of each chunk
   const int *ch_len;           // [ch_nchunks] samples of each chunk
+  const int *ch_x;             // [ch_nchunks][ch_u] the chunk's shared leading indices
   void *ch_part;               // [ch_nchunks][width] in the working precision
   double *ch_rsq;              // [ch_nchunks] ||R||^2 of each chunk
   double *ch_red;              // [groups][outputs] first-stage sums

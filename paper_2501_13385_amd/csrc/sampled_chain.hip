@@ -699,24 +699,32 @@ __global__ void __launch_bounds__(256) k_chain_reduce1(const Dev *__restrict__ d
   chain_output<F, R>(d, o, k, x, e, off);
   const int W = chain_part_width(d.m, d.ch_u, R);
   const auto part = glb((const F *)d.ch_part);
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  if (k >= d.ch_u) {
-    int c = c0;
-    for (; c + 4 <= c1; c += 4) {
+  // eight loads in flight per step; a shared core's output takes a chunk's
+  // value only where the chunk's prefix index x_k equals the output's slice
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool shared = k < d.ch_u;
+  const auto cxs = glb(d.ch_x);
+  const auto rsqc = glb(d.ch_rsq);
+  int c = c0;
+  for (; c + 8 <= c1; c += 8) {
+    double v[8];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) a[t] += (double)part[(long long)(c + t) * W + off];
+    for (int t = 0; t < 8; ++t)
+      v[t] = (shared && e == RR) ? rsqc[c + t] : (double)part[(long long)(c + t) * W + off];
+    if (shared) {
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if (cxs[(long long)(c + t) * d.ch_u + k] != x) v[t] = 0.0;
     }
-    for (; c < c1; ++c) a[0] += (double)part[(long long)c * W + off];
-  } else {
-    const auto idx = glb(d.idx);
-    const auto st = glb(d.ch_start);
-    const long long krow = (long long)k * d.N;
-    for (int c = c0; c < c1; ++c) {
-      if (idx[krow + st[c]] != x) continue;
-      a[c & 3] += e < RR ? (double)part[(long long)c * W + off] : glb(d.ch_rsq)[c];
-    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) a[t] += v[t];
   }
-  glb(d.ch_red)[(long long)g * nout + o] = (a[0] + a[1]) + (a[2] + a[3]);
+  for (; c < c1; ++c) {
+    double v = (shared && e == RR) ? rsqc[c] : (double)part[(long long)c * W + off];
+    if (shared && cxs[(long long)c * d.ch_u + k] != x) v = 0.0;
+    a[c & 7] += v;
+  }
+  glb(d.ch_red)[(long long)g * nout + o] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 // Second reduction: the group sums of output o into the gradient or the slice sums.
