@@ -38,6 +38,7 @@
 #include "prgd_internal.hpp"
 #include "block_ops.hpp"
 #include "small_la.hpp"
+#include "solver.hpp"
 
 namespace prgd {
 
@@ -506,16 +507,6 @@ __device__ __forceinline__ void reduce_sym_partials(const double *part, int nb, 
   __syncthreads();
 }
 
-// Breakdown rule of the truncation at a cut.  The kept singular vectors come
-// from the eigen-decomposition of S = M^T M, M the unfolding being truncated,
-// so the eigenvalues carry rounding of about eps * w[0] and the new core
-// M Z_r Sigma_r^{-1} departs from orthonormality by about
-// eps * (sigma_1 / sigma_r)^2.  A kept singular value below 1e-6 of the
-// largest (eigenvalue ratio 1e-12, orthonormality defect up to ~2e-4) stops
-// the solve with PRGD_EBREAKDOWN rather than continuing on inaccurate cores.
-// An SVD of M itself (Algorithm 1 as written) resolves ratios down to ~1e-15;
-// this limit belongs to the Gram form only.
-constexpr double TRUNC_MIN_EIG_RATIO = 1e-12;
 
 __device__ __forceinline__ void left_cut(const Dev &d, int i, double *smem);
 
@@ -1276,6 +1267,9 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
 // phase 2: retraction sweeps (right Grams of W_l, then the truncated left sweep)
 hipError_t launch_retract(const Batch &bt, hipStream_t s) {
   const int m = bt.host[0].m, ns = bt.ns;
+  bool wave = false;
+  const hipError_t ew = launch_retract_wave(bt, s, wave);
+  if (wave || ew != hipSuccess) return ew;
   int gmax = 1;
   for (int b = m - 1; b >= 1; --b)
     gmax = std::max(gmax, max_over(bt, [&](const Dev &d) {

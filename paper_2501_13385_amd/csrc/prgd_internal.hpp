@@ -222,6 +222,17 @@ __host__ __device__ inline int nblocks_for(int n, int target) {
 // device array `dt` of their descriptors and serves solve blockIdx.y; grids
 // are sized for the largest member and surplus blocks return at once.  All
 // members share m, R, the precision and the sampled-pass variant.
+// Breakdown rule of the truncation at a cut.  The kept singular vectors come
+// from the eigen-decomposition of S = M^T M, M the unfolding being truncated,
+// so the eigenvalues carry rounding of about eps * w[0] and the new core
+// M Z_r Sigma_r^{-1} departs from orthonormality by about
+// eps * (sigma_1 / sigma_r)^2.  A kept singular value below 1e-6 of the
+// largest (eigenvalue ratio 1e-12, orthonormality defect up to ~2e-4) stops
+// the solve with PRGD_EBREAKDOWN rather than continuing on inaccurate cores.
+// An SVD of M itself (Algorithm 1 as written) resolves ratios down to ~1e-15;
+// this limit belongs to the Gram form only.
+constexpr double TRUNC_MIN_EIG_RATIO = 1e-12;
+
 struct Batch {
   const Dev *dt;     // device array [ns]
   const Dev *host;   // host copies [ns] (grid sizing)

@@ -19,6 +19,9 @@ hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *
 hipError_t launch_dense_iteration(const Batch &bt, hipStream_t s, int init);
 hipError_t launch_project(const Batch &bt, hipStream_t s);
 hipError_t launch_retract(const Batch &bt, hipStream_t s);
+// one-wave retraction for small ranks and slices; used = false when it does
+// not apply to the batch (nothing launched)
+hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, bool &used);
 hipError_t launch_output(const Batch &bt, hipStream_t s, int init);
 hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode);
 // Stable grouping of Omega by one mode; perm (if not null) receives, for each
