@@ -1244,8 +1244,11 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
   int gmax = 1;
   for (int j = 1; j <= m - 1; ++j)
     gmax = std::max(gmax, max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 8) + nblocks_for(d.n[m - j], 8); }));
-  if (gmax <= FUSE_MAX) hipLaunchKernelGGL(k_gram_sweep, dim3(1, ns), dim3(1024), 0, s, bt.dt);
-  for (int j = 1; j <= m - 1 && gmax > FUSE_MAX; ++j) {
+  bool wave = false;
+  hipError_t ew = launch_gram_wave(bt, s, wave);
+  if (ew != hipSuccess) return ew;
+  if (!wave && gmax <= FUSE_MAX) hipLaunchKernelGGL(k_gram_sweep, dim3(1, ns), dim3(1024), 0, s, bt.dt);
+  for (int j = 1; j <= m - 1 && !wave && gmax > FUSE_MAX; ++j) {
     const int g = max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 8) + nblocks_for(d.n[m - j], 8); });
     if (g <= FUSE_MAX) {
       hipLaunchKernelGGL(k_gram_fused, dim3(1, ns), dim3(1024), 0, s, bt.dt, j, g);

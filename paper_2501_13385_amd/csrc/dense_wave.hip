@@ -136,6 +136,20 @@ __device__ __forceinline__ void stage(double *dst, const double *src, int n, int
   for (int e = base + lane; e < n; e += 64) dst[e] = g[e];
 }
 
+// the same for float data, widened to double
+__device__ __forceinline__ void stage_f32(double *dst, const float *src, int n, int lane) {
+  const auto g = glb(src);
+  int base = 0;
+  for (; base + 16 * 64 <= n; base += 16 * 64) {
+    float v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = g[base + k * 64 + lane];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) dst[base + k * 64 + lane] = (double)v[k];
+  }
+  for (int e = base + lane; e < n; e += 64) dst[e] = (double)g[e];
+}
+
 __device__ __forceinline__ void breakdown(const Dev &d, int lane) {
   if (lane == 0) {
     d.st->status = -5;
@@ -296,6 +310,166 @@ __global__ void __launch_bounds__(64) k_retract_wave(const Dev *__restrict__ dt)
   }
 }
 
+// ---------------------------------------------------------------------------
+// One-wave Gram sweep of the preconditioned projection (Lemma 3): step
+// j = 1..m-1 forms
+//   GL_j       = sum_x omega_{j-1}(x) T_{j-1}(x)^T GL_{j-1} T_{j-1}(x)
+//   H_{m-j}    = sum_x omega_{m-j}(x) T_{m-j}(x) H_{m-j+1} T_{m-j}(x)^T
+//   Theta_{j-1} = sum_x T_{j-1}(x)^T Y_{j-1}(x)
+// and the inverses of GL_j and H_{m-j} on their active blocks.  The two
+// chains are R x R (R <= 8), so one 16 x 16 tile carries both: the left
+// chain in rows and columns 0..7, the right one in 8..15.  With the slice
+// tile P(x) = diag(T_{j-1}(x), T_{m-j}(x)^T) and G = diag(GL_{j-1},
+// H_{m-j+1}),
+//   G P              = diag(GL T_{j-1}, H T_{m-j}^T)       (scaled per block by omega)
+//   P^T (G P)        = diag(T_{j-1}^T GL T_{j-1}, T_{m-j} H T_{m-j}^T)
+//   P^T diag(Y, 0)   = diag(T_{j-1}^T Y_{j-1}, 0)
+// in row layout, with G and P^T needing no transpose (G symmetric; P^T in
+// the A position takes P in row layout).  A core with fewer slices than the
+// other contributes zero tiles past its last slice.
+// ---------------------------------------------------------------------------
+constexpr int QOFF = 8;   // first row and column of the right chain in the tile
+
+// Inverses of the two SPD blocks of the symmetric tile G (ld 16): the left
+// Gram on rows and columns 0..7 (active size n1) and the right one on 8..15
+// (active size n2), by Gauss-Jordan elimination on [A | I] without pivoting
+// (SPD), both systems in one 16 x 16 tile: rows 0..7 hold [A1 | I], rows
+// 8..15 [A2 | I], inactive rows and columns identity (decoupled, so every
+// step leaves them unchanged).  Each lane keeps its four entries in
+// registers; a step reads the pivot rows, the pivot column and the pivots
+// from the LDS copy M of the tile.  The inverses, symmetrised as
+// (X + X^T) / 2, go to O1 and O2 (ld R, zero outside the active blocks).
+// Returns false if a pivot of either active block is not positive.
+__device__ __forceinline__ bool wave_spd_inverse_pair(const double *G, int n1, int n2, double *O1, double *O2, int R,
+                                                      double *M, int lane) {
+  const int row0 = lane >> 4, c = lane & 15;
+  d4 t;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = row0 + 4 * v, b = r < QOFF ? 0 : QOFF, i = r - b, n = b ? n2 : n1;
+    if (c < QOFF) t[v] = (i < n && c < n) ? G[r * 16 + b + c] : (i == c ? 1.0 : 0.0);
+    else t[v] = (c - QOFF == i) ? 1.0 : 0.0;
+    M[r * 16 + c] = t[v];
+  }
+  wave_lds_sync();
+  bool bad = false;
+  for (int k = 0; k < QOFF; ++k) {
+    const double p1 = M[k * 16 + k], p2 = M[(QOFF + k) * 16 + k];
+    const double q1 = M[k * 16 + c] * rcp_newton<2>(p1), q2 = M[(QOFF + k) * 16 + c] * rcp_newton<2>(p2);
+    double f[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) f[v] = M[(row0 + 4 * v) * 16 + k];
+    bad = bad || (k < n1 && !(p1 > 0.0 && isfinite(p1))) || (k < n2 && !(p2 > 0.0 && isfinite(p2)));
+    wave_lds_sync();   // every read of this step precedes the writes below
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      const bool lo = r < QOFF;
+      const double q = lo ? q1 : q2;
+      t[v] = (r == (lo ? k : QOFF + k)) ? q : fma(-f[v], q, t[v]);
+      M[r * 16 + c] = t[v];
+    }
+    wave_lds_sync();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = row0 + 4 * v, b = r < QOFF ? 0 : QOFF, i = r - b, jj = c - QOFF, n = b ? n2 : n1;
+    if (c >= QOFF && i < R && jj < R) {
+      const double x = 0.5 * (t[v] + M[(b + jj) * 16 + QOFF + i]);
+      glb(b ? O2 : O1)[i * R + jj] = (i < n && jj < n) ? x : 0.0;
+    }
+  }
+  return !bad;
+}
+
+static size_t gram_wave_lds(const Dev &d) {
+  return sizeof(double) * (size_t)(2 * d.coff[d.m] + d.soff[d.m] + 2 * T16);
+}
+
+__global__ void __launch_bounds__(64) k_gram_wave(const Dev *__restrict__ dt) {
+  extern __shared__ double lds[];
+  const Dev &d = dt[blockIdx.y];
+  if (d.st->done) return;
+  const int lane = threadIdx.x;
+  const int m = d.m, R = d.R, RR = R * R;
+  const int tot = (int)d.coff[m], ns = d.soff[m];
+  double *sT = lds, *sY = lds + tot, *sw = sY + tot;
+  double *G = sw + ns;             // symmetric staging of the two Grams
+  double *inv = G + T16;           // working tile of the inverse pair
+  stage(sT, d.cores, tot, lane);
+  if (d.prec == PREC_MIXED) {
+    stage_f32(sY, (const float *)d.Y, tot, lane);
+  } else {
+    stage(sY, (const double *)d.Y, tot, lane);
+  }
+  for (int e = lane; e < ns; e += 64) sw[e] = glb(d.omega)[e];
+  wave_lds_sync();
+  const int row0 = lane >> 4, col = lane & 15;
+  // where each entry of the lane's tile of P(x) comes from
+  int poff[4];
+  unsigned pl = 0u, ph = 0u;   // bit v: entry of T_{j-1} / of T_{m-j}^T
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = row0 + 4 * v;
+    const bool lo = r < QOFF && col < QOFF && r < R && col < R;
+    const bool hi = r >= QOFF && col >= QOFF && r - QOFF < R && col - QOFF < R;
+    poff[v] = lo ? r * R + col : (hi ? (col - QOFF) * R + (r - QOFF) : 0);
+    pl |= (lo ? 1u : 0u) << v;
+    ph |= (hi ? 1u : 0u) << v;
+  }
+  d4 g;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) g[v] = (row0 + 4 * v == col) ? 1.0 : 0.0;   // GL_0 = H_m = 1
+  for (int j = 1; j <= m - 1; ++j) {
+    const int cl = j - 1, ch = m - j;
+    const int nl = d.n[cl], nh = d.n[ch], nx = nl > nh ? nl : nh;
+    d4 acc = zero4(), th = zero4();
+    for (int x = 0; x < nx; ++x) {
+      const bool xl = x < nl, xh = x < nh;
+      const double *tl = sT + d.coff[cl] + (long long)(xl ? x : 0) * RR;
+      const double *yl = sY + d.coff[cl] + (long long)(xl ? x : 0) * RR;
+      const double *thh = sT + d.coff[ch] + (long long)(xh ? x : 0) * RR;
+      const double wl = xl ? sw[d.soff[cl] + x] : 0.0, wh = xh ? sw[d.soff[ch] + x] : 0.0;
+      d4 pt, yt;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double a = tl[poff[v]], b = thh[poff[v]], y = yl[poff[v]];
+        const bool lo = ((pl >> v) & 1u) && xl, hi = ((ph >> v) & 1u) && xh;
+        pt[v] = lo ? a : (hi ? b : 0.0);
+        yt[v] = lo ? y : 0.0;
+      }
+      d4 n = mm16(g, pt, zero4());
+      n[0] *= wl;   // rows 0..7: the left chain
+      n[1] *= wl;
+      n[2] *= wh;   // rows 8..15: the right chain
+      n[3] *= wh;
+      acc = mm16(pt, n, acc);
+      th = mm16(pt, yt, th);
+    }
+    store_sym(G, 16, acc, lane);
+    const auto GLj = glb(sm_slot(d, j, S_GL)), Hb = glb(sm_slot(d, ch, S_H)), THc = glb(sm_slot(d, cl, S_TH));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      if (r < R && col < R) THc[r * R + col] = th[v];
+    }
+    wave_lds_sync();
+    g = load_tile(G, lane);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      if (r < R && col < R) GLj[r * R + col] = g[v];
+      if (r >= QOFF && col >= QOFF && r - QOFF < R && col - QOFF < R) Hb[(r - QOFF) * R + col - QOFF] = g[v];
+    }
+    const bool ok = wave_spd_inverse_pair(G, d.r[j], d.r[ch], sm_slot(d, j, S_GLI), sm_slot(d, ch, S_HI), R, inv, lane);
+    if (!ok) {
+      breakdown(d, lane);
+      return;
+    }
+    wave_lds_sync();
+  }
+}
+
 // The one-wave sweep applies when every member of the batch has R <= 8, at
 // most 8 slices per core (beyond that the slice-parallel launches win) and
 // cores that fit the LDS of one workgroup next to the work tiles.
@@ -315,6 +489,22 @@ hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, bool &used) {
   if (lds > WAVE_MAX_LDS) return hipSuccess;
   used = true;
   hipLaunchKernelGGL(k_retract_wave, dim3(1, bt.ns), dim3(64), lds, s, bt.dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_wave(const Batch &bt, hipStream_t s, bool &used) {
+  used = false;
+  size_t lds = 0;
+  for (int i = 0; i < bt.ns; ++i) {
+    const Dev &d = bt.host[i];
+    if (d.R > QOFF) return hipSuccess;
+    for (int c = 0; c < d.m; ++c)
+      if (d.n[c] > WAVE_MAX_N) return hipSuccess;
+    lds = std::max(lds, gram_wave_lds(d));
+  }
+  if (lds > WAVE_MAX_LDS) return hipSuccess;
+  used = true;
+  hipLaunchKernelGGL(k_gram_wave, dim3(1, bt.ns), dim3(64), lds, s, bt.dt);
   return hipGetLastError();
 }
 
