@@ -122,32 +122,181 @@ __device__ __forceinline__ d4 c_tile(const double *T, const double *X, const CMa
 
 __device__ __forceinline__ int core_kind(int c, int m) { return c == 0 ? 0 : (c == m - 1 ? 2 : 1); }
 
-// global -> LDS copy of n doubles by one wave, 16 loads in flight per lane
-__device__ __forceinline__ void stage(double *dst, const double *src, int n, int lane) {
+// global -> LDS copy of n doubles by the whole block, 16 loads in flight per
+// thread
+__device__ __forceinline__ void stage(double *dst, const double *src, int n) {
   const auto g = glb(src);
+  const int t = threadIdx.x, nt = blockDim.x;
   int base = 0;
-  for (; base + 16 * 64 <= n; base += 16 * 64) {
+  for (; base + 16 * nt <= n; base += 16 * nt) {
     double v[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = g[base + k * 64 + lane];
+    for (int k = 0; k < 16; ++k) v[k] = g[base + k * nt + t];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) dst[base + k * 64 + lane] = v[k];
+    for (int k = 0; k < 16; ++k) dst[base + k * nt + t] = v[k];
   }
-  for (int e = base + lane; e < n; e += 64) dst[e] = g[e];
+  for (int e = base + t; e < n; e += nt) dst[e] = g[e];
 }
 
 // the same for float data, widened to double
-__device__ __forceinline__ void stage_f32(double *dst, const float *src, int n, int lane) {
+__device__ __forceinline__ void stage_f32(double *dst, const float *src, int n) {
   const auto g = glb(src);
+  const int t = threadIdx.x, nt = blockDim.x;
   int base = 0;
-  for (; base + 16 * 64 <= n; base += 16 * 64) {
+  for (; base + 16 * nt <= n; base += 16 * nt) {
     float v[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) v[k] = g[base + k * 64 + lane];
+    for (int k = 0; k < 16; ++k) v[k] = g[base + k * nt + t];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) dst[base + k * 64 + lane] = (double)v[k];
+    for (int k = 0; k < 16; ++k) dst[base + k * nt + t] = (double)v[k];
   }
-  for (int e = base + lane; e < n; e += 64) dst[e] = (double)g[e];
+  for (int e = base + t; e < n; e += nt) dst[e] = (double)g[e];
+}
+
+// value of v in lane `src` of the wave (src may differ per lane)
+__device__ __forceinline__ double lane_gather(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)b), hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// element k (wave-uniform) of a tile
+__device__ __forceinline__ double tile_elem(d4 a, int k) {
+  return k == 0 ? a[0] : (k == 1 ? a[1] : (k == 2 ? a[2] : a[3]));
+}
+
+// Pivoted Cholesky of a symmetric positive semidefinite n x n matrix (n <=
+// 16) held as a row-layout tile a (zero outside n x n): returns the rank and
+// puts in f (row layout) columns 0..rank-1 of F, F F^T = A up to pivots below
+// n * 2.3e-16 * max diag, the same factor and pivot rule as
+// block_pivoted_cholesky.  Every lane keeps the diagonal entry of its column
+// (each row of 16 lanes a full copy), so the pivot is a maximum within a row
+// of 16 lanes by DPP; the pivot's column and row reach the lanes by two
+// cross-lane gathers (the matrix stays exactly symmetric, so row p serves as
+// column p), with no LDS round trip per step.
+__device__ __forceinline__ int wave_pcholesky16(d4 a, int n, int lane, d4 &f) {
+  const int row0 = lane >> 4, c = lane & 15;
+  // the diagonal entry A(c, c): element c >> 2 of lane 16 (c & 3) + c
+  double dg = lane_gather(tile_elem(a, 0), 16 * (c & 3) + c);
+  {
+    const double d1 = lane_gather(a[1], 16 * (c & 3) + c), d2 = lane_gather(a[2], 16 * (c & 3) + c),
+                 d3 = lane_gather(a[3], 16 * (c & 3) + c);
+    const int e = c >> 2;
+    dg = e == 0 ? dg : (e == 1 ? d1 : (e == 2 ? d2 : d3));
+    dg = c < n ? dg : 0.0;
+  }
+  double dm = dg;
+  dm = fmax(dm, dpp_f64<0xB1>(dm));
+  dm = fmax(dm, dpp_f64<0x4E>(dm));
+  dm = fmax(dm, dpp_f64<0x141>(dm));
+  dm = fmax(dm, dpp_f64<0x140>(dm));
+  const double tol = (double)n * 2.3e-16 * lane_value(dm, 0);
+  f = zero4();
+  // 1 while a row (of this lane's four) or this lane's column has not been a
+  // pivot, 0 after and outside n: the factor of a pivoted row is exactly zero
+  double ar[4], ac = c < n ? 1.0 : 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) ar[v] = row0 + 4 * v < n ? 1.0 : 0.0;
+  int rank = 0;
+  bool go = true;   // wave-uniform: no pivot has fallen below the tolerance
+  // a fixed number of steps with no exit: once a pivot fails every later step
+  // updates nothing (its factors are zero), as stopping there would
+  for (int k = 0; k < n; ++k) {
+    const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(fmax(dg, 0.0)) >> 32);
+    unsigned key = ac != 0.0 ? ((hi & ~31u) | (unsigned)(31 - c)) : 0u;
+    key = max(key, (unsigned)__builtin_amdgcn_mov_dpp((int)key, 0xB1, 0xF, 0xF, false));
+    key = max(key, (unsigned)__builtin_amdgcn_mov_dpp((int)key, 0x4E, 0xF, 0xF, false));
+    key = max(key, (unsigned)__builtin_amdgcn_mov_dpp((int)key, 0x141, 0xF, 0xF, false));
+    key = max(key, (unsigned)__builtin_amdgcn_mov_dpp((int)key, 0x140, 0xF, 0xF, false));
+    const unsigned kmax = __builtin_amdgcn_readfirstlane(key);
+    const int p = 31 - (int)(kmax & 31u);
+    // column p of this lane's rows (lane 16 row0 + p, same elements) and row
+    // p of this lane's column (lane 16 (p & 3) + c, element p >> 2)
+    double col_p[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) col_p[v] = lane_gather(a[v], 16 * row0 + (p & 15));
+    const double row_p = lane_gather(tile_elem(a, (p >> 2) & 3), 16 * (p & 3) + c);
+    const double best = lane_value(dg, p & 15);
+    go = go && kmax != 0u && best > tol;
+    rank += go ? 1 : 0;
+    const double rs = go ? rsq_newton<2>(best) : 0.0;
+    const double fc = row_p * (rs * ac);
+    const double sel = c == k ? 1.0 : 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double fr = col_p[v] * (rs * ar[v]);
+      f[v] = fma(fr, sel, f[v]);
+      a[v] = fma(-fr, fc, a[v]);
+      ar[v] = row0 + 4 * v == p ? 0.0 : ar[v];
+    }
+    dg = fma(-fc, fc, dg);
+    ac = c == p ? 0.0 : ac;
+  }
+  return rank;
+}
+
+// block_jacobi_eig for n <= 16 run by one wave (lane = threadIdx.x & 63 of
+// the first wave of the block) with no block barrier: the same sweeps
+// (jacobi_sweeps, one-wave form), set-up and sorting done by the wave.
+// On exit w[0..n) holds the eigenvalues in descending order and V (ld n)
+// the eigenvectors as columns.  A (read, then reused), V, W1, W2: 256
+// doubles each.
+__device__ __forceinline__ void wave_jacobi_eig(double *A, int n, double *V, double *w, double *W1, double *W2,
+                                                int lane) {
+  __shared__ int rank_of[16];
+  const int ne = n + (n & 1);
+  double off = 0.0, dia = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = lane + 64 * q, i = e >> 4, j = e & 15;
+    if (i < ne && j < ne) {
+      const double v = (i < n && j < n) ? A[i * n + j] : 0.0;
+      W1[i * ne + j] = v;
+      if (i == j) dia += v * v;
+      else off += v * v;
+    }
+  }
+  off = wave_sum_uniform(off);
+  dia = wave_sum_uniform(dia);
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = lane + 64 * q, i = e >> 4, j = e & 15;
+    if (i < ne && j < ne) A[i * ne + j] = i == j ? 1.0 : 0.0;
+  }
+  wave_lds_sync();
+  const bool flip = jacobi_sweeps<true>(W1, W2, A, V, ne, off, dia, nullptr);
+  wave_lds_sync();
+  const double *cur = flip ? W2 : W1;
+  double *nxt = flip ? W1 : W2;
+  const double *vc = flip ? V : A;
+  if (vc == V) {   // the eigenvectors sit in V's own area: move them first
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = lane + 64 * q;
+      if (e < ne * ne) nxt[e] = vc[e];
+    }
+    wave_lds_sync();
+    vc = nxt;
+  }
+  // descending order, stable by index
+  if (lane < n) {
+    const double wi = cur[lane * ne + lane];
+    int rk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double wj = cur[j * ne + j];
+      rk += (wj > wi || (wj == wi && j < lane)) ? 1 : 0;
+    }
+    w[rk] = wi;
+    rank_of[lane] = rk;
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = lane + 64 * q, rr = e >> 4, i = e & 15;
+    if (rr < n && i < n) V[rr * n + rank_of[i]] = vc[rr * ne + i];
+  }
+  wave_lds_sync();
 }
 
 __device__ __forceinline__ void breakdown(const Dev &d, int lane) {
@@ -164,60 +313,75 @@ static size_t retract_wave_lds(const Dev &d) {
   return sizeof(double) * (size_t)(2 * d.coff[d.m] + (long long)T16 * (d.m + 7) + 32);
 }
 
-__global__ void __launch_bounds__(64) k_retract_wave(const Dev *__restrict__ dt) {
+constexpr int NWAVE = 8;   // waves of the sweep kernels (the factorisations run in parallel)
+
+__global__ void __launch_bounds__(64 * NWAVE) k_retract_wave(const Dev *__restrict__ dt) {
   extern __shared__ double lds[];
   const Dev &d = dt[blockIdx.y];
   if (d.st->done) return;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m = d.m, R = d.R, RR = R * R;
   const int tot = (int)d.coff[m];
   const double alpha = d.st->alpha_n;
   double *sT = lds, *sX = lds + tot;
-  double *Fst = sX + tot;          // F_b, b = 0..m-1, row-major 16 x 16, zero padded
+  double *Fst = sX + tot;          // GR_b, then F_b, b = 0..m-1, row-major 16 x 16, zero padded
   double *G = Fst + m * T16;       // symmetric staging
-  double *A = G + T16;             // compressed right Gram, then S
+  double *A = G + T16;             // S
   double *Fc = A + T16, *S1 = Fc + T16, *W = S1 + T16, *W1 = W + T16, *W2 = W1 + T16;
   double *w = W2 + T16;            // 32 eigenvalues
   __shared__ int rank_s[MAXM + 1];
-  stage(sT, d.cores, tot, lane);
-  stage(sX, d.X, tot, lane);
-  wave_lds_sync();
+  stage(sT, d.cores, tot);
+  stage(sX, d.X, tot);
+  __syncthreads();
   const int row0 = lane >> 4, col = lane & 15;
-  const CMap qt = c_map<true>(R, lane), qn = c_map<false>(R, lane);
 
-  // right Grams GR_b = C_b (GR_{b+1} C_b^T), b = m-1..1, GR_m = 1, and the
-  // pivoted Cholesky factors F_b of their active parts
-  d4 gn;
+  // right Grams GR_b = C_b (GR_{b+1} C_b^T), b = m-1..1, GR_m = 1 (one
+  // wave: a chain of dependent products)
+  if (wv == 0) {
+    const CMap qt = c_map<true>(R, lane);
+    d4 gn;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) gn[v] = (row0 + 4 * v == col) ? 1.0 : 0.0;
-  for (int b = m - 1; b >= 1; --b) {
-    d4 acc = zero4();
-    const int cb = (int)d.coff[b];
-    const int kb = core_kind(b, m);
-    for (int x = 0; x < d.n[b]; ++x) {
-      const d4 ct = c_tile(sT + cb + x * RR, sX + cb + x * RR, qt, kb, alpha);
-      const d4 mt = mm16(gn, ct, zero4());
-      acc = mm16(ct, mt, acc);
+    for (int v = 0; v < 4; ++v) gn[v] = (row0 + 4 * v == col) ? 1.0 : 0.0;
+    for (int b = m - 1; b >= 1; --b) {
+      d4 acc = zero4();
+      const int cb = (int)d.coff[b];
+      const int kb = core_kind(b, m);
+      for (int x = 0; x < d.n[b]; ++x) {
+        const d4 ct = c_tile(sT + cb + x * RR, sX + cb + x * RR, qt, kb, alpha);
+        const d4 mt = mm16(gn, ct, zero4());
+        acc = mm16(ct, mt, acc);
+      }
+      double *Gb = Fst + b * T16;
+      store_sym(Gb, 16, acc, lane);
+      wave_lds_sync();
+      gn = load_tile(Gb, lane);
     }
-    store_sym(G, 16, acc, lane);
-    wave_lds_sync();
-    gn = load_tile(G, lane);
+  }
+  __syncthreads();
+  // pivoted Cholesky factors F_b of the active parts of the GR_b, one wave
+  // per b (no step of the chain above needs them)
+  for (int b = 1 + wv; b <= m - 1; b += NWAVE) {
+    double *Fb = Fst + b * T16;
     // the active indices [0, r_b) U [R, R + r_b)
     const int rb = d.r[b], na = 2 * rb;
-    for (int e = lane; e < T16; e += 64) {
-      const int i = e >> 4, j = e & 15;
-      const int gi = i < rb ? i : R + i - rb, gj = j < rb ? j : R + j - rb;
-      if (i < na && j < na) A[i * na + j] = G[gi * 16 + gj];
+    d4 ga, fb;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      const int gi = r < rb ? r : R + r - rb, gj = col < rb ? col : R + col - rb;
+      ga[v] = (r < na && col < na) ? Fb[gi * 16 + gj] : 0.0;
     }
+    const int rank = wave_pcholesky16(ga, na, lane, fb);
+    // F_b over GR_b: row i of the factor goes to row gi(i) of the tile
     wave_lds_sync();
-    const int rank = block_pivoted_cholesky(A, na, Fc);
-    double *Fb = Fst + b * T16;
-    for (int e = lane; e < T16; e += 64) {
-      const int gi = e >> 4, c2 = e & 15;
-      int i = -1;
-      if (gi < rb) i = gi;
-      else if (gi >= R && gi < R + rb) i = gi - R + rb;
-      Fb[e] = (i >= 0 && c2 < rank) ? Fc[i * na + c2] : 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Fb[(row0 + 4 * v) * 16 + col] = 0.0;
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      const int gi = r < rb ? r : R + r - rb;
+      if (r < na) Fb[gi * 16 + col] = fb[v];
     }
     if (lane == 0) {
       rank_s[b] = rank;
@@ -225,6 +389,9 @@ __global__ void __launch_bounds__(64) k_retract_wave(const Dev *__restrict__ dt)
     }
     wave_lds_sync();
   }
+  __syncthreads();
+  if (wv != 0) return;   // the left sweep is one wave with no block barrier
+  const CMap qn = c_map<false>(R, lane);
 
   // truncated left sweep, cut i = 1..m-1 on core c = i-1, P_0 = e_0^T
   d4 pt;
@@ -256,18 +423,19 @@ __global__ void __launch_bounds__(64) k_retract_wave(const Dev *__restrict__ dt)
     // eigen-decomposition of S through its pivoted Cholesky factor, which
     // grades the matrix the Jacobi sweeps see (as block_psd_eig does): S =
     // Fc Fc^T, S1 = Fc^T Fc = W diag(w) W^T, eigenvectors Fc W diag(w)^{-1/2}
-    const int rs = block_pivoted_cholesky(A, rk, Fc);   // ld rk, columns >= rs zero
-    d4 fct, fctt;
+    d4 sa, fct;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = row0 + 4 * v;
-      const bool in = r < rk && col < rk;
-      fct[v] = in ? Fc[r * rk + col] : 0.0;
-      fctt[v] = in ? Fc[col * rk + r] : 0.0;
+      sa[v] = (r < rk && col < rk) ? A[r * rk + col] : 0.0;
     }
+    const int rs = wave_pcholesky16(sa, rk, lane, fct);   // Fc, columns >= rs zero
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Fc[(row0 + 4 * v) * 16 + col] = fct[v];
     store_sym(S1, rs, mm16(fct, fct, zero4()), lane);   // S1 = Fc^T Fc (ld rs)
     wave_lds_sync();
-    if (rs > 0) block_jacobi_eig(S1, rs, W, w, W1, W2);
+    const d4 fctt = load_tile_t(Fc, lane);
+    if (rs > 0) wave_jacobi_eig(S1, rs, W, w, W1, W2, lane);
     for (int e = rs + lane; e < rk; e += 64) w[e] = 0.0;
     wave_lds_sync();
     const double s0 = w[0], sr = w[ri - 1];
@@ -383,90 +551,93 @@ __device__ __forceinline__ bool wave_spd_inverse_pair(const double *G, int n1, i
 }
 
 static size_t gram_wave_lds(const Dev &d) {
-  return sizeof(double) * (size_t)(2 * d.coff[d.m] + d.soff[d.m] + 2 * T16);
+  return sizeof(double) * (size_t)(2 * d.coff[d.m] + d.soff[d.m] + (long long)T16 * (d.m + NWAVE));
 }
 
-__global__ void __launch_bounds__(64) k_gram_wave(const Dev *__restrict__ dt) {
+__global__ void __launch_bounds__(64 * NWAVE) k_gram_wave(const Dev *__restrict__ dt) {
   extern __shared__ double lds[];
   const Dev &d = dt[blockIdx.y];
   if (d.st->done) return;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m = d.m, R = d.R, RR = R * R;
   const int tot = (int)d.coff[m], ns = d.soff[m];
   double *sT = lds, *sY = lds + tot, *sw = sY + tot;
-  double *G = sw + ns;             // symmetric staging of the two Grams
-  double *inv = G + T16;           // working tile of the inverse pair
-  stage(sT, d.cores, tot, lane);
-  if (d.prec == PREC_MIXED) {
-    stage_f32(sY, (const float *)d.Y, tot, lane);
-  } else {
-    stage(sY, (const double *)d.Y, tot, lane);
-  }
-  for (int e = lane; e < ns; e += 64) sw[e] = glb(d.omega)[e];
-  wave_lds_sync();
+  double *Gs = sw + ns;              // diag(GL_j, H_{m-j}) of every step j, symmetric
+  double *inv = Gs + m * T16;        // working tile of the inverse pairs, one per wave
+  stage(sT, d.cores, tot);
+  if (d.prec == PREC_MIXED) stage_f32(sY, (const float *)d.Y, tot);
+  else stage(sY, (const double *)d.Y, tot);
+  for (int e = threadIdx.x; e < ns; e += blockDim.x) sw[e] = glb(d.omega)[e];
+  __syncthreads();
   const int row0 = lane >> 4, col = lane & 15;
-  // where each entry of the lane's tile of P(x) comes from
-  int poff[4];
-  unsigned pl = 0u, ph = 0u;   // bit v: entry of T_{j-1} / of T_{m-j}^T
+  if (wv == 0) {   // the two Gram chains: one wave, dependent products
+    // where each entry of the lane's tile of P(x) comes from
+    int poff[4];
+    unsigned pl = 0u, ph = 0u;   // bit v: entry of T_{j-1} / of T_{m-j}^T
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int r = row0 + 4 * v;
-    const bool lo = r < QOFF && col < QOFF && r < R && col < R;
-    const bool hi = r >= QOFF && col >= QOFF && r - QOFF < R && col - QOFF < R;
-    poff[v] = lo ? r * R + col : (hi ? (col - QOFF) * R + (r - QOFF) : 0);
-    pl |= (lo ? 1u : 0u) << v;
-    ph |= (hi ? 1u : 0u) << v;
-  }
-  d4 g;
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      const bool lo = r < QOFF && col < QOFF && r < R && col < R;
+      const bool hi = r >= QOFF && col >= QOFF && r - QOFF < R && col - QOFF < R;
+      poff[v] = lo ? r * R + col : (hi ? (col - QOFF) * R + (r - QOFF) : 0);
+      pl |= (lo ? 1u : 0u) << v;
+      ph |= (hi ? 1u : 0u) << v;
+    }
+    d4 g;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) g[v] = (row0 + 4 * v == col) ? 1.0 : 0.0;   // GL_0 = H_m = 1
-  for (int j = 1; j <= m - 1; ++j) {
-    const int cl = j - 1, ch = m - j;
-    const int nl = d.n[cl], nh = d.n[ch], nx = nl > nh ? nl : nh;
-    d4 acc = zero4(), th = zero4();
-    for (int x = 0; x < nx; ++x) {
-      const bool xl = x < nl, xh = x < nh;
-      const double *tl = sT + d.coff[cl] + (long long)(xl ? x : 0) * RR;
-      const double *yl = sY + d.coff[cl] + (long long)(xl ? x : 0) * RR;
-      const double *thh = sT + d.coff[ch] + (long long)(xh ? x : 0) * RR;
-      const double wl = xl ? sw[d.soff[cl] + x] : 0.0, wh = xh ? sw[d.soff[ch] + x] : 0.0;
-      d4 pt, yt;
+    for (int v = 0; v < 4; ++v) g[v] = (row0 + 4 * v == col) ? 1.0 : 0.0;   // GL_0 = H_m = 1
+    for (int j = 1; j <= m - 1; ++j) {
+      const int cl = j - 1, ch = m - j;
+      const int nl = d.n[cl], nh = d.n[ch], nx = nl > nh ? nl : nh;
+      d4 acc = zero4(), th = zero4();
+      for (int x = 0; x < nx; ++x) {
+        const bool xl = x < nl, xh = x < nh;
+        const double *tl = sT + d.coff[cl] + (long long)(xl ? x : 0) * RR;
+        const double *yl = sY + d.coff[cl] + (long long)(xl ? x : 0) * RR;
+        const double *thh = sT + d.coff[ch] + (long long)(xh ? x : 0) * RR;
+        const double wl = xl ? sw[d.soff[cl] + x] : 0.0, wh = xh ? sw[d.soff[ch] + x] : 0.0;
+        d4 pt, yt;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double a = tl[poff[v]], b = thh[poff[v]], y = yl[poff[v]];
+          const bool lo = ((pl >> v) & 1u) && xl, hi = ((ph >> v) & 1u) && xh;
+          pt[v] = lo ? a : (hi ? b : 0.0);
+          yt[v] = lo ? y : 0.0;
+        }
+        d4 n = mm16(g, pt, zero4());
+        n[0] *= wl;   // rows 0..7: the left chain
+        n[1] *= wl;
+        n[2] *= wh;   // rows 8..15: the right chain
+        n[3] *= wh;
+        acc = mm16(pt, n, acc);
+        th = mm16(pt, yt, th);
+      }
+      double *Gj = Gs + j * T16;
+      store_sym(Gj, 16, acc, lane);
+      const auto GLj = glb(sm_slot(d, j, S_GL)), Hb = glb(sm_slot(d, ch, S_H)), THc = glb(sm_slot(d, cl, S_TH));
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double a = tl[poff[v]], b = thh[poff[v]], y = yl[poff[v]];
-        const bool lo = ((pl >> v) & 1u) && xl, hi = ((ph >> v) & 1u) && xh;
-        pt[v] = lo ? a : (hi ? b : 0.0);
-        yt[v] = lo ? y : 0.0;
+        const int r = row0 + 4 * v;
+        if (r < R && col < R) THc[r * R + col] = th[v];
       }
-      d4 n = mm16(g, pt, zero4());
-      n[0] *= wl;   // rows 0..7: the left chain
-      n[1] *= wl;
-      n[2] *= wh;   // rows 8..15: the right chain
-      n[3] *= wh;
-      acc = mm16(pt, n, acc);
-      th = mm16(pt, yt, th);
-    }
-    store_sym(G, 16, acc, lane);
-    const auto GLj = glb(sm_slot(d, j, S_GL)), Hb = glb(sm_slot(d, ch, S_H)), THc = glb(sm_slot(d, cl, S_TH));
+      wave_lds_sync();
+      g = load_tile(Gj, lane);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = row0 + 4 * v;
-      if (r < R && col < R) THc[r * R + col] = th[v];
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + 4 * v;
+        if (r < R && col < R) GLj[r * R + col] = g[v];
+        if (r >= QOFF && col >= QOFF && r - QOFF < R && col - QOFF < R) Hb[(r - QOFF) * R + col - QOFF] = g[v];
+      }
     }
-    wave_lds_sync();
-    g = load_tile(G, lane);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = row0 + 4 * v;
-      if (r < R && col < R) GLj[r * R + col] = g[v];
-      if (r >= QOFF && col >= QOFF && r - QOFF < R && col - QOFF < R) Hb[(r - QOFF) * R + col - QOFF] = g[v];
-    }
-    const bool ok = wave_spd_inverse_pair(G, d.r[j], d.r[ch], sm_slot(d, j, S_GLI), sm_slot(d, ch, S_HI), R, inv, lane);
-    if (!ok) {
-      breakdown(d, lane);
-      return;
-    }
-    wave_lds_sync();
+  }
+  __syncthreads();
+  // the inverses of GL_j and H_{m-j}, one wave per step (the chains above
+  // need only the Grams themselves)
+  for (int j = 1 + wv; j <= m - 1; j += NWAVE) {
+    const int ch = m - j;
+    const bool ok = wave_spd_inverse_pair(Gs + j * T16, d.r[j], d.r[ch], sm_slot(d, j, S_GLI), sm_slot(d, ch, S_HI), R,
+                                          inv + wv * T16, lane);
+    if (!ok) breakdown(d, lane);
   }
 }
 
@@ -488,7 +659,7 @@ hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, bool &used) {
   }
   if (lds > WAVE_MAX_LDS) return hipSuccess;
   used = true;
-  hipLaunchKernelGGL(k_retract_wave, dim3(1, bt.ns), dim3(64), lds, s, bt.dt);
+  hipLaunchKernelGGL(k_retract_wave, dim3(1, bt.ns), dim3(64 * NWAVE), lds, s, bt.dt);
   return hipGetLastError();
 }
 
@@ -504,7 +675,7 @@ hipError_t launch_gram_wave(const Batch &bt, hipStream_t s, bool &used) {
   }
   if (lds > WAVE_MAX_LDS) return hipSuccess;
   used = true;
-  hipLaunchKernelGGL(k_gram_wave, dim3(1, bt.ns), dim3(64), lds, s, bt.dt);
+  hipLaunchKernelGGL(k_gram_wave, dim3(1, bt.ns), dim3(64 * NWAVE), lds, s, bt.dt);
   return hipGetLastError();
 }
 
