@@ -1045,9 +1045,10 @@ prgd_status prgd_iterate_profiled(prgd_solver s, int32_t iters, double *phase_ms
     chk(hipEventRecord(e[2], s->stream));
     chk(launch_project(s->batch(), s->stream));
     chk(hipEventRecord(e[3], s->stream));
-    chk(launch_retract(s->batch(), s->stream));
+    bool out_done = false;
+    chk(launch_retract(s->batch(), s->stream, 0, out_done));
     chk(hipEventRecord(e[4], s->stream));
-    chk(launch_output(s->batch(), s->stream, 0));
+    if (!out_done) chk(launch_output(s->batch(), s->stream, 0));
     chk(hipEventRecord(e[5], s->stream));
     if (s->has_truth) chk(launch_truth_sweep(s->batch(), s->stream, 0));
     chk(hipEventRecord(e[6], s->stream));

@@ -980,37 +980,13 @@ __device__ __forceinline__ void output_fin_body(const Dev &d, int bx_, int init,
   const int nb = d.blk_off[d.m];
   if (d.st->done) return;
   __shared__ double sbuf[32];
-  State *st = d.st;
-  // the state this thread updates is read before the reduction, so that its
-  // latency overlaps the partial loads
-  const double old = st->tnorm_sq;
-  const int it = st->iter;
   double a0 = 0.0, a1 = 0.0;
   for (int k = threadIdx.x; k < nb; k += blockDim.x) {
     a0 += glb(d.part)[2 * k];
     a1 += glb(d.part)[2 * k + 1];
   }
   block_sum2(a0, a1, sbuf);
-  if (threadIdx.x == 0) {
-    if (init) {
-      st->tnorm_sq = a0;
-    } else {
-      const double diff = fmax(0.0, a0 - 2.0 * a1 + old);
-      const double rc = sqrt(diff) / fmax(1.0, sqrt(old));
-      st->rel_change = rc;
-      st->tnorm_sq = a0;
-      if (it < d.hist_cap) {
-        d.hist[it].rel_change = rc;
-        d.hist[it].flags |= 1;
-      }
-      st->iter = it + 1;
-      st->upd = 1;
-      if (d.stop_rule == STOP_CHANGE && rc <= d.tol) {
-        st->status = 0;
-        st->done = 1;
-      }
-    }
-  }
+  if (threadIdx.x == 0) finish_output(d, init, a0, a1);
 }
 
 __global__ void __launch_bounds__(1024) k_output_fin(const Dev *__restrict__ dt, int init) {
@@ -1268,11 +1244,11 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
 }
 
 // phase 2: retraction sweeps (right Grams of W_l, then the truncated left sweep)
-hipError_t launch_retract(const Batch &bt, hipStream_t s) {
+hipError_t launch_retract(const Batch &bt, hipStream_t s, int init, bool &output_done) {
   const int m = bt.host[0].m, ns = bt.ns;
-  bool wave = false;
-  const hipError_t ew = launch_retract_wave(bt, s, wave);
-  if (wave || ew != hipSuccess) return ew;
+  output_done = false;
+  const hipError_t ew = launch_retract_wave(bt, s, init, output_done);
+  if (output_done || ew != hipSuccess) return ew;
   int gmax = 1;
   for (int b = m - 1; b >= 1; --b)
     gmax = std::max(gmax, max_over(bt, [&](const Dev &d) {
@@ -1319,8 +1295,9 @@ hipError_t launch_output(const Batch &bt, hipStream_t s, int init) {
 hipError_t launch_dense_iteration(const Batch &bt, hipStream_t s, int init) {
   hipError_t e;
   if (!init && (e = launch_project(bt, s)) != hipSuccess) return e;
-  if ((e = launch_retract(bt, s)) != hipSuccess) return e;
-  return launch_output(bt, s, init);
+  bool done = false;
+  if ((e = launch_retract(bt, s, init, done)) != hipSuccess) return e;
+  return done ? hipSuccess : launch_output(bt, s, init);
 }
 
 // relative error against the truth (members without truth cores skip it)

@@ -199,8 +199,8 @@ __device__ __forceinline__ int wave_pcholesky16(d4 a, int n, int lane, d4 &f) {
   for (int v = 0; v < 4; ++v) ar[v] = row0 + 4 * v < n ? 1.0 : 0.0;
   int rank = 0;
   bool go = true;   // wave-uniform: no pivot has fallen below the tolerance
-  // a fixed number of steps with no exit: once a pivot fails every later step
-  // updates nothing (its factors are zero), as stopping there would
+  // the loop leaves at its end, after a step whose pivot failed (that step
+  // updates nothing: its factors are zero), so it has a single exit
   for (int k = 0; k < n; ++k) {
     const unsigned hi = (unsigned)((unsigned long long)__double_as_longlong(fmax(dg, 0.0)) >> 32);
     unsigned key = ac != 0.0 ? ((hi & ~31u) | (unsigned)(31 - c)) : 0u;
@@ -231,6 +231,7 @@ __device__ __forceinline__ int wave_pcholesky16(d4 a, int n, int lane, d4 &f) {
     }
     dg = fma(-fc, fc, dg);
     ac = c == p ? 0.0 : ac;
+    if (!go) break;
   }
   return rank;
 }
@@ -314,8 +315,9 @@ static size_t retract_wave_lds(const Dev &d) {
 }
 
 constexpr int NWAVE = 8;   // waves of the sweep kernels (the factorisations run in parallel)
+constexpr int QOFF = 8;    // second block of rows/columns in a tile (R <= 8)
 
-__global__ void __launch_bounds__(64 * NWAVE) k_retract_wave(const Dev *__restrict__ dt) {
+__global__ void __launch_bounds__(64 * NWAVE) k_retract_wave(const Dev *__restrict__ dt, int init) {
   extern __shared__ double lds[];
   const Dev &d = dt[blockIdx.y];
   if (d.st->done) return;
@@ -390,91 +392,179 @@ __global__ void __launch_bounds__(64 * NWAVE) k_retract_wave(const Dev *__restri
     wave_lds_sync();
   }
   __syncthreads();
-  if (wv != 0) return;   // the left sweep is one wave with no block barrier
-  const CMap qn = c_map<false>(R, lane);
+  __shared__ int bad_s;
+  __shared__ double red_s[2 * NWAVE];
+  if (threadIdx.x == 0) bad_s = 0;
+  __syncthreads();
+  const CMap qt = c_map<true>(R, lane), qn = c_map<false>(R, lane);
+  if (wv == 0) {   // the left sweep: one wave, no block barrier
+    // truncated left sweep, cut i = 1..m-1 on core c = i-1, P_0 = e_0^T
+    d4 pt;
+  #pragma unroll
+    for (int v = 0; v < 4; ++v) pt[v] = (row0 + 4 * v == 0 && col == 0) ? 1.0 : 0.0;
+    for (int i = 1; i <= m - 1; ++i) {
+      const int c = i - 1, cc = (int)d.coff[c];
+      d4 acc = zero4();
+      const int kc = core_kind(c, m);
+      for (int x = 0; x < d.n[c]; ++x) {
+        const d4 cd = c_tile(sT + cc + x * RR, sX + cc + x * RR, qn, kc, alpha);
+        const d4 bm = mm16(pt, cd, zero4());   // B = P_{i-1} C_c(x)
+        acc = mm16(bm, bm, acc);               // G_B += B^T B
+      }
+      store_sym(G, 16, acc, lane);
+      wave_lds_sync();
+      const d4 gb = load_tile(G, lane);
+      const int rk = rank_s[i], ri = d.r[i];
+      if (rk < ri) {
+        breakdown(d, lane);
+        if (lane == 0) bad_s = 1;
+        break;
+      }
+      const double *Fi = Fst + i * T16;
+      const d4 fd = load_tile(Fi, lane);
+      const d4 t1 = mm16(gb, fd, zero4());     // G_B F
+      const d4 sm = mm16(fd, t1, zero4());     // S = F^T G_B F
+      store_sym(A, rk, sm, lane);
+      wave_lds_sync();
+      // eigen-decomposition of S through its pivoted Cholesky factor, which
+      // grades the matrix the Jacobi sweeps see (as block_psd_eig does): S =
+      // Fc Fc^T, S1 = Fc^T Fc = W diag(w) W^T, eigenvectors Fc W diag(w)^{-1/2}
+      d4 sa, fct;
+  #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + 4 * v;
+        sa[v] = (r < rk && col < rk) ? A[r * rk + col] : 0.0;
+      }
+      const int rs = wave_pcholesky16(sa, rk, lane, fct);   // Fc, columns >= rs zero
+  #pragma unroll
+      for (int v = 0; v < 4; ++v) Fc[(row0 + 4 * v) * 16 + col] = fct[v];
+      store_sym(S1, rs, mm16(fct, fct, zero4()), lane);   // S1 = Fc^T Fc (ld rs)
+      wave_lds_sync();
+      const d4 fctt = load_tile_t(Fc, lane);
+      if (rs > 0) wave_jacobi_eig(S1, rs, W, w, W1, W2, lane);
+      for (int e = rs + lane; e < rk; e += 64) w[e] = 0.0;
+      wave_lds_sync();
+      const double s0 = w[0], sr = w[ri - 1];
+      if (!(sr > TRUNC_MIN_EIG_RATIO * s0) || !isfinite(s0)) {
+        breakdown(d, lane);
+        if (lane == 0) bad_s = 1;
+        break;
+      }
+      // Z_r: the first r_i unit eigenvectors of S, Fc W diag(w)^{-1/2}
+      d4 wt;
+  #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + 4 * v;
+        wt[v] = (r < rs && col < rs) ? W[r * rs + col] : 0.0;
+      }
+      d4 vz = mm16(fctt, wt, zero4());
+      {
+        const double wc = col < rs ? w[col] : 0.0;
+        const double sc = (col < ri && wc > 0.0) ? rsq_newton<2>(wc) : 0.0;
+  #pragma unroll
+        for (int v = 0; v < 4; ++v) vz[v] *= sc;
+      }
+      // Tr = F Z_r Sigma_r^{-1}
+      d4 tr = mm16(load_tile_t(Fi, lane), vz, zero4());
+      const double sw = col < ri ? sqrt(w[col]) : 1.0;
+      const auto Tr = glb(sm_slot(d, i, S_TR));
+  #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + 4 * v;
+        tr[v] = col < ri ? tr[v] / sw : 0.0;
+        if (r < 2 * R && col < R) Tr[r * R + col] = tr[v];
+      }
+      pt = mm16(gb, tr, zero4());              // P_i^T = G_B Tr
+      const auto Pn = glb(sm_slot(d, i, S_P));
+  #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + 4 * v;            // column r of P_i, row col
+        if (r < 2 * R && col < R) Pn[col * 2 * R + r] = pt[v];
+      }
+      // Tr_i and P_i^T (2R x R each, ld 8) replace F_i, read for the last
+      // time above, for the output phase
+      wave_lds_sync();
+      double *Ki = Fst + i * T16;
+  #pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = row0 + 4 * v;
+        if (col < QOFF) {
+          Ki[r * QOFF + col] = tr[v];
+          Ki[T16 / 2 + r * QOFF + col] = pt[v];
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+  __syncthreads();
+  if (bad_s) return;
 
-  // truncated left sweep, cut i = 1..m-1 on core c = i-1, P_0 = e_0^T
-  d4 pt;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) pt[v] = (row0 + 4 * v == 0 && col == 0) ? 1.0 : 0.0;
-  for (int i = 1; i <= m - 1; ++i) {
-    const int c = i - 1, cc = (int)d.coff[c];
-    d4 acc = zero4();
-    const int kc = core_kind(c, m);
-    for (int x = 0; x < d.n[c]; ++x) {
-      const d4 cd = c_tile(sT + cc + x * RR, sX + cc + x * RR, qn, kc, alpha);
-      const d4 bm = mm16(pt, cd, zero4());   // B = P_{i-1} C_c(x)
-      acc = mm16(bm, bm, acc);               // G_B += B^T B
-    }
-    store_sym(G, 16, acc, lane);
-    wave_lds_sync();
-    const d4 gb = load_tile(G, lane);
-    const int rk = rank_s[i], ri = d.r[i];
-    if (rk < ri) {
-      breakdown(d, lane);
-      return;
-    }
-    const double *Fi = Fst + i * T16;
-    const d4 fd = load_tile(Fi, lane);
-    const d4 t1 = mm16(gb, fd, zero4());     // G_B F
-    const d4 sm = mm16(fd, t1, zero4());     // S = F^T G_B F
-    store_sym(A, rk, sm, lane);
-    wave_lds_sync();
-    // eigen-decomposition of S through its pivoted Cholesky factor, which
-    // grades the matrix the Jacobi sweeps see (as block_psd_eig does): S =
-    // Fc Fc^T, S1 = Fc^T Fc = W diag(w) W^T, eigenvectors Fc W diag(w)^{-1/2}
-    d4 sa, fct;
+  // new cores T'_c(x) = P_c C_c(x) Tr_{c+1} (c < m-1), P_{m-1} C_{m-1}(x),
+  // slices dealt to the waves in turn; the stopping-test sums ||T'||^2 =
+  // ||T'_{m-1}||^2 and <T', T> come from the last core (the others are
+  // left-orthogonal), <T', T> through Z = the second block of P_{m-1}
+  double nn = 0.0, cr = 0.0;
+  const int nsl = d.soff[m];
+  for (int sidx = wv; sidx < nsl; sidx += NWAVE) {
+    int c = 0;
+    while (c + 1 < m && d.soff[c + 1] <= sidx) ++c;
+    const int x = sidx - d.soff[c];
+    const int off = (int)d.coff[c] + x * RR;
+    const double *Ks = Fst + c * T16;   // Tr_c and P_c^T
+    d4 ptc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = row0 + 4 * v;
-      sa[v] = (r < rk && col < rk) ? A[r * rk + col] : 0.0;
+      ptc[v] = c == 0 ? ((r == 0 && col == 0) ? 1.0 : 0.0) : (col < QOFF ? Ks[T16 / 2 + r * QOFF + col] : 0.0);
     }
-    const int rs = wave_pcholesky16(sa, rk, lane, fct);   // Fc, columns >= rs zero
+    d4 out;
+    if (c < m - 1) {
+      const double *Kn = Fst + (c + 1) * T16;
+      d4 trn;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) Fc[(row0 + 4 * v) * 16 + col] = fct[v];
-    store_sym(S1, rs, mm16(fct, fct, zero4()), lane);   // S1 = Fc^T Fc (ld rs)
-    wave_lds_sync();
-    const d4 fctt = load_tile_t(Fc, lane);
-    if (rs > 0) wave_jacobi_eig(S1, rs, W, w, W1, W2, lane);
-    for (int e = rs + lane; e < rk; e += 64) w[e] = 0.0;
-    wave_lds_sync();
-    const double s0 = w[0], sr = w[ri - 1];
-    if (!(sr > TRUNC_MIN_EIG_RATIO * s0) || !isfinite(s0)) {
-      breakdown(d, lane);
-      return;
+      for (int v = 0; v < 4; ++v) trn[v] = col < QOFF ? Kn[(row0 + 4 * v) * QOFF + col] : 0.0;
+      const d4 ct = c_tile(sT + off, sX + off, qt, core_kind(c, m), alpha);
+      out = mm16(ptc, mm16(ct, trn, zero4()), zero4());
+    } else {
+      out = mm16(ptc, c_tile(sT + off, sX + off, qn, 2, alpha), zero4());
     }
-    // Z_r: the first r_i unit eigenvectors of S, Fc W diag(w)^{-1/2}
-    d4 wt;
+    const auto gc = glb(d.cores);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = row0 + 4 * v;
-      wt[v] = (r < rs && col < rs) ? W[r * rs + col] : 0.0;
+      if (r < R && col < R) {
+        gc[off + r * R + col] = out[v];
+        if (d.prec == PREC_MIXED) glb(d.cores32)[off + r * R + col] = (float)out[v];
+        long long bo = -1;
+        if (c == 0 && r == 0) bo = (long long)x * R + col;
+        if (c == m - 1 && col == 0) bo = (long long)d.n[0] * R + (long long)x * R + r;
+        if (bo >= 0) {
+          if (d.prec == PREC_MIXED) glb((float *)d.bnd)[bo] = (float)out[v];
+          else glb((double *)d.bnd)[bo] = out[v];
+        }
+        if (c == m - 1 && col == 0) {
+          double z = 0.0;
+          for (int k = 0; k < R; ++k) z += Ks[T16 / 2 + (R + k) * QOFF + r] * sT[off + k * R];
+          nn += out[v] * out[v];
+          cr += out[v] * z;
+        }
+      }
     }
-    d4 vz = mm16(fctt, wt, zero4());
-    {
-      const double wc = col < rs ? w[col] : 0.0;
-      const double sc = (col < ri && wc > 0.0) ? rsq_newton<2>(wc) : 0.0;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) vz[v] *= sc;
+  }
+  nn = wave_sum_uniform(nn);
+  cr = wave_sum_uniform(cr);
+  if (lane == 0) {
+    red_s[2 * wv] = nn;
+    red_s[2 * wv + 1] = cr;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = 0; k < NWAVE; ++k) {
+      a0 += red_s[2 * k];
+      a1 += red_s[2 * k + 1];
     }
-    // Tr = F Z_r Sigma_r^{-1}
-    d4 tr = mm16(load_tile_t(Fi, lane), vz, zero4());
-    const double sw = col < ri ? sqrt(w[col]) : 1.0;
-    const auto Tr = glb(sm_slot(d, i, S_TR));
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = row0 + 4 * v;
-      tr[v] = col < ri ? tr[v] / sw : 0.0;
-      if (r < 2 * R && col < R) Tr[r * R + col] = tr[v];
-    }
-    pt = mm16(gb, tr, zero4());              // P_i^T = G_B Tr
-    const auto Pn = glb(sm_slot(d, i, S_P));
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = row0 + 4 * v;            // column r of P_i, row col
-      if (r < 2 * R && col < R) Pn[col * 2 * R + r] = pt[v];
-    }
-    wave_lds_sync();
+    finish_output(d, init, a0, a1);
   }
 }
 
@@ -496,7 +586,6 @@ __global__ void __launch_bounds__(64 * NWAVE) k_retract_wave(const Dev *__restri
 // the A position takes P in row layout).  A core with fewer slices than the
 // other contributes zero tiles past its last slice.
 // ---------------------------------------------------------------------------
-constexpr int QOFF = 8;   // first row and column of the right chain in the tile
 
 // Inverses of the two SPD blocks of the symmetric tile G (ld 16): the left
 // Gram on rows and columns 0..7 (active size n1) and the right one on 8..15
@@ -647,7 +736,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_gram_wave(const Dev *__restrict_
 constexpr int WAVE_MAX_N = 8;
 constexpr size_t WAVE_MAX_LDS = 150 * 1024;
 
-hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, bool &used) {
+hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, int init, bool &used) {
   used = false;
   size_t lds = 0;
   for (int i = 0; i < bt.ns; ++i) {
@@ -659,7 +748,7 @@ hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, bool &used) {
   }
   if (lds > WAVE_MAX_LDS) return hipSuccess;
   used = true;
-  hipLaunchKernelGGL(k_retract_wave, dim3(1, bt.ns), dim3(64 * NWAVE), lds, s, bt.dt);
+  hipLaunchKernelGGL(k_retract_wave, dim3(1, bt.ns), dim3(64 * NWAVE), lds, s, bt.dt, init);
   return hipGetLastError();
 }
 

@@ -233,6 +233,35 @@ __host__ __device__ inline int nblocks_for(int n, int target) {
 // this limit belongs to the Gram form only.
 constexpr double TRUNC_MIN_EIG_RATIO = 1e-12;
 
+// End of an iteration's output step (one thread), from a0 = ||T_{l+1}||^2 and
+// a1 = <T_{l+1}, T_l>: the relative change ||T_{l+1} - T_l|| / max(1,
+// ||T_l||) with ||T_l||^2 kept from the previous iteration, the iteration
+// count, the history record and the change stopping rule (section 5.1).  At
+// the initial rounding (init) only ||T_0||^2 is stored.
+__device__ inline void finish_output(const Dev &d, int init, double a0, double a1) {
+  State *st = d.st;
+  if (init) {
+    st->tnorm_sq = a0;
+    return;
+  }
+  const double old = st->tnorm_sq;
+  const int it = st->iter;
+  const double diff = fmax(0.0, a0 - 2.0 * a1 + old);
+  const double rc = sqrt(diff) / fmax(1.0, sqrt(old));
+  st->rel_change = rc;
+  st->tnorm_sq = a0;
+  if (it < d.hist_cap) {
+    d.hist[it].rel_change = rc;
+    d.hist[it].flags |= 1;
+  }
+  st->iter = it + 1;
+  st->upd = 1;
+  if (d.stop_rule == STOP_CHANGE && rc <= d.tol) {
+    st->status = 0;
+    st->done = 1;
+  }
+}
+
 struct Batch {
   const Dev *dt;     // device array [ns]
   const Dev *host;   // host copies [ns] (grid sizing)

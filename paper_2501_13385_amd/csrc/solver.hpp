@@ -18,10 +18,13 @@ hipError_t launch_eval(int m, int R, long long N, const int *idx, const double *
                        double *out, hipStream_t s);
 hipError_t launch_dense_iteration(const Batch &bt, hipStream_t s, int init);
 hipError_t launch_project(const Batch &bt, hipStream_t s);
-hipError_t launch_retract(const Batch &bt, hipStream_t s);
-// one-wave retraction for small ranks and slices; used = false when it does
-// not apply to the batch (nothing launched)
-hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, bool &used);
+// retraction; output_done = true when the launch also formed the new cores
+// and ran the stopping test (launch_output is then skipped)
+hipError_t launch_retract(const Batch &bt, hipStream_t s, int init, bool &output_done);
+// one-workgroup retraction for small ranks and slices, with the output step
+// and its stopping test; used = false when it does not apply to the batch
+// (nothing launched)
+hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, int init, bool &used);
 // one-wave Gram sweep of the projection under the same conditions
 hipError_t launch_gram_wave(const Batch &bt, hipStream_t s, bool &used);
 hipError_t launch_output(const Batch &bt, hipStream_t s, int init);
