@@ -1221,7 +1221,8 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
   for (int j = 1; j <= m - 1; ++j)
     gmax = std::max(gmax, max_over(bt, [&](const Dev &d) { return nblocks_for(d.n[j - 1], 8) + nblocks_for(d.n[m - j], 8); }));
   bool wave = false;
-  hipError_t ew = launch_gram_wave(bt, s, wave);
+  const bool bf16 = bt.host[0].tangent_bf16 != 0;   // the whole batch shares the variant
+  hipError_t ew = launch_gram_wave(bt, s, bf16 ? 0 : 1, wave);
   if (ew != hipSuccess) return ew;
   if (!wave && gmax <= FUSE_MAX) hipLaunchKernelGGL(k_gram_sweep, dim3(1, ns), dim3(1024), 0, s, bt.dt);
   for (int j = 1; j <= m - 1 && !wave && gmax > FUSE_MAX; ++j) {
@@ -1234,9 +1235,9 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
     }
   }
   const int g = max_over(bt, [&](const Dev &d) { return d.blk_off[m]; });
-  if (bt.host[0].tangent_bf16)   // the whole batch shares the variant
+  if (bf16)
     hipLaunchKernelGGL(k_tangent_bf16, dim3(g, ns), dim3(1024), 0, s, bt.dt);
-  else
+  else if (!wave)   // the one-workgroup sweep formed the tangent itself
     hipLaunchKernelGGL(k_tangent, dim3(g, ns), dim3(1024), 0, s, bt.dt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -595,10 +595,11 @@ __global__ void __launch_bounds__(64 * NWAVE) k_retract_wave(const Dev *__restri
 // step leaves them unchanged).  Each lane keeps its four entries in
 // registers; a step reads the pivot rows, the pivot column and the pivots
 // from the LDS copy M of the tile.  The inverses, symmetrised as
-// (X + X^T) / 2, go to O1 and O2 (ld R, zero outside the active blocks).
+// (X + X^T) / 2, go to O1 and O2 (global) and L1 and L2 (LDS), ld R, zero
+// outside the active blocks.
 // Returns false if a pivot of either active block is not positive.
 __device__ __forceinline__ bool wave_spd_inverse_pair(const double *G, int n1, int n2, double *O1, double *O2, int R,
-                                                      double *M, int lane) {
+                                                      double *M, int lane, double *L1, double *L2) {
   const int row0 = lane >> 4, c = lane & 15;
   d4 t;
 #pragma unroll
@@ -633,17 +634,20 @@ __device__ __forceinline__ bool wave_spd_inverse_pair(const double *G, int n1, i
     const int r = row0 + 4 * v, b = r < QOFF ? 0 : QOFF, i = r - b, jj = c - QOFF, n = b ? n2 : n1;
     if (c >= QOFF && i < R && jj < R) {
       const double x = 0.5 * (t[v] + M[(b + jj) * 16 + QOFF + i]);
-      glb(b ? O2 : O1)[i * R + jj] = (i < n && jj < n) ? x : 0.0;
+      const double o = (i < n && jj < n) ? x : 0.0;
+      glb(b ? O2 : O1)[i * R + jj] = o;
+      (b ? L2 : L1)[i * R + jj] = o;
     }
   }
   return !bad;
 }
 
 static size_t gram_wave_lds(const Dev &d) {
-  return sizeof(double) * (size_t)(2 * d.coff[d.m] + d.soff[d.m] + (long long)T16 * (d.m + NWAVE));
+  const long long RR = (long long)d.R * d.R;
+  return sizeof(double) * (size_t)(2 * d.coff[d.m] + d.soff[d.m] + (long long)T16 * (d.m + NWAVE) + RR * (4 * d.m + 2));
 }
 
-__global__ void __launch_bounds__(64 * NWAVE) k_gram_wave(const Dev *__restrict__ dt) {
+__global__ void __launch_bounds__(64 * NWAVE) k_gram_wave(const Dev *__restrict__ dt, int tangent) {
   extern __shared__ double lds[];
   const Dev &d = dt[blockIdx.y];
   if (d.st->done) return;
@@ -653,10 +657,15 @@ __global__ void __launch_bounds__(64 * NWAVE) k_gram_wave(const Dev *__restrict_
   double *sT = lds, *sY = lds + tot, *sw = sY + tot;
   double *Gs = sw + ns;              // diag(GL_j, H_{m-j}) of every step j, symmetric
   double *inv = Gs + m * T16;        // working tile of the inverse pairs, one per wave
+  double *GIs = inv + NWAVE * T16;   // GL_c^{-1}, c = 0..m (R x R each)
+  double *HIs = GIs + (m + 1) * RR;  // H_c^{-1}, c = 0..m
+  double *THs = HIs + (m + 1) * RR;  // Theta_c, then Psi_c, c = 0..m-1
   stage(sT, d.cores, tot);
   if (d.prec == PREC_MIXED) stage_f32(sY, (const float *)d.Y, tot);
   else stage(sY, (const double *)d.Y, tot);
   for (int e = threadIdx.x; e < ns; e += blockDim.x) sw[e] = glb(d.omega)[e];
+  __shared__ int bad_s;
+  if (threadIdx.x == 0) bad_s = 0;
   __syncthreads();
   const int row0 = lane >> 4, col = lane & 15;
   if (wv == 0) {   // the two Gram chains: one wave, dependent products
@@ -707,7 +716,10 @@ __global__ void __launch_bounds__(64 * NWAVE) k_gram_wave(const Dev *__restrict_
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = row0 + 4 * v;
-        if (r < R && col < R) THc[r * R + col] = th[v];
+        if (r < R && col < R) {
+          THc[r * R + col] = th[v];
+          THs[cl * RR + r * R + col] = th[v];
+        }
       }
       wave_lds_sync();
       g = load_tile(Gj, lane);
@@ -725,8 +737,64 @@ __global__ void __launch_bounds__(64 * NWAVE) k_gram_wave(const Dev *__restrict_
   for (int j = 1 + wv; j <= m - 1; j += NWAVE) {
     const int ch = m - j;
     const bool ok = wave_spd_inverse_pair(Gs + j * T16, d.r[j], d.r[ch], sm_slot(d, j, S_GLI), sm_slot(d, ch, S_HI), R,
-                                          inv + wv * T16, lane);
-    if (!ok) breakdown(d, lane);
+                                          inv + wv * T16, lane, GIs + j * RR, HIs + ch * RR);
+    if (!ok) {
+      breakdown(d, lane);
+      if (lane == 0) bad_s = 1;
+    }
+  }
+  if (!tangent) return;
+  // tangent components (Lemma 3):
+  //   X_c(x) = omega_c(x)^{-1} GL_c^{-1} Y_c(x) H_{c+1}^{-1} - T_c(x) Psi_c,
+  //   Psi_c = GL_{c+1}^{-1} Theta_c H_{c+1}^{-1} (c < m-1), Psi_{m-1} = 0,
+  // and the gradient cleared for the next sampled pass; one entry per lane
+  for (int e = threadIdx.x; e < RR; e += blockDim.x) {   // GL_0^{-1} = H_m^{-1} = 1
+    GIs[e] = (e / R == e % R) ? 1.0 : 0.0;
+    HIs[m * RR + e] = (e / R == e % R) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (bad_s) return;
+  // R x R matrices as 16 x 16 tiles, zero outside R x R (row layout; _t: transposed)
+  auto tile = [&](const double *M, bool tr) {
+    d4 o;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      o[v] = (r < R && col < R) ? M[tr ? col * R + r : r * R + col] : 0.0;
+    }
+    return o;
+  };
+  for (int c = wv; c < m - 1; c += NWAVE) {   // Psi_c = GL_{c+1}^{-1} (Theta_c H_{c+1}^{-1}), over Theta_c
+    const d4 ps = mm16(tile(GIs + (c + 1) * RR, false),
+                       mm16(tile(THs + c * RR, true), tile(HIs + (c + 1) * RR, false), zero4()), zero4());
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      if (r < R && col < R) THs[c * RR + r * R + col] = ps[v];
+    }
+  }
+  __syncthreads();
+  const int nsl = d.soff[m];
+  for (int sidx = wv; sidx < nsl; sidx += NWAVE) {
+    int c = 0;
+    while (c + 1 < m && d.soff[c + 1] <= sidx) ++c;
+    const int x = sidx - d.soff[c];
+    const int off = (int)d.coff[c] + x * RR;
+    const double iw = 1.0 / sw[d.soff[c] + x];
+    // GL_c^{-1} (Y H_{c+1}^{-1}) omega^{-1} - T Psi_c
+    const d4 yh = mm16(tile(sY + off, true), tile(HIs + (c + 1) * RR, false), zero4());
+    d4 xt = mm16(tile(GIs + c * RR, false), yh, zero4());
+    const d4 tp = c < m - 1 ? mm16(tile(sT + off, true), tile(THs + c * RR, false), zero4()) : zero4();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      if (r < R && col < R) {
+        glb(d.X)[off + r * R + col] = xt[v] * iw - tp[v];
+        if (d.prec == PREC_MIXED) glb((float *)d.Y)[off + r * R + col] = 0.0f;
+        else glb((double *)d.Y)[off + r * R + col] = 0.0;
+      }
+    }
   }
 }
 
@@ -752,7 +820,7 @@ hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, int init, bool &u
   return hipGetLastError();
 }
 
-hipError_t launch_gram_wave(const Batch &bt, hipStream_t s, bool &used) {
+hipError_t launch_gram_wave(const Batch &bt, hipStream_t s, int tangent, bool &used) {
   used = false;
   size_t lds = 0;
   for (int i = 0; i < bt.ns; ++i) {
@@ -764,7 +832,7 @@ hipError_t launch_gram_wave(const Batch &bt, hipStream_t s, bool &used) {
   }
   if (lds > WAVE_MAX_LDS) return hipSuccess;
   used = true;
-  hipLaunchKernelGGL(k_gram_wave, dim3(1, bt.ns), dim3(64 * NWAVE), lds, s, bt.dt);
+  hipLaunchKernelGGL(k_gram_wave, dim3(1, bt.ns), dim3(64 * NWAVE), lds, s, bt.dt, tangent);
   return hipGetLastError();
 }
 

@@ -25,8 +25,9 @@ hipError_t launch_retract(const Batch &bt, hipStream_t s, int init, bool &output
 // and its stopping test; used = false when it does not apply to the batch
 // (nothing launched)
 hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, int init, bool &used);
-// one-wave Gram sweep of the projection under the same conditions
-hipError_t launch_gram_wave(const Batch &bt, hipStream_t s, bool &used);
+// one-workgroup Gram sweep of the projection under the same conditions, with
+// the tangent components when `tangent` is set
+hipError_t launch_gram_wave(const Batch &bt, hipStream_t s, int tangent, bool &used);
 hipError_t launch_output(const Batch &bt, hipStream_t s, int init);
 hipError_t launch_truth_sweep(const Batch &bt, hipStream_t s, int mode);
 // Stable grouping of Omega by one mode; perm (if not null) receives, for each
