@@ -236,6 +236,76 @@ __device__ __forceinline__ int wave_pcholesky16(d4 a, int n, int lane, d4 &f) {
   return rank;
 }
 
+// The sweeps of jacobi_sweeps<true> (same slots, tournament moves, rotation
+// formula, stop rule and results, bit for bit) with each rotation computed
+// once: lane (P, Q) forms the rotation of pair Q from the diagonal block
+// (Q, Q) and takes that of pair P from lane (P, P) by a cross-lane gather,
+// instead of computing both.  The gather needs every lane, so all lanes
+// compute (the idle ones on block (0, 0)) and only the working ones store.
+__device__ __forceinline__ bool wave_jacobi_sweeps(double *W1, double *W2, double *A, double *V, int ne, double off,
+                                                   double dia, int lane) {
+  const int np = ne / 2, m1 = ne - 1;
+  const bool act = lane < np * np;
+  const int P = act ? lane / np : 0, Q = act ? lane - P * np : 0;
+  const int r1 = 2 * P * ne, r2 = r1 + ne, c1 = 2 * Q, c2 = c1 + 1;
+  const int q1 = 2 * Q * (ne + 1);
+  const int lp = P * np + P;   // the lane that owns diagonal block (P, P)
+  const int nr1 = tournament_next(2 * P, np) * ne, nr2 = tournament_next(2 * P + 1, np) * ne;
+  const int nc1 = tournament_next(c1, np), nc2 = tournament_next(c2, np);
+  auto one_round = [&](const double *src, double *dst, const double *vsrc, double *vdst, bool last) {
+    const double q11 = src[q1], q12 = src[q1 + 1], q22 = src[q1 + ne + 1];
+    const double a11 = src[r1 + c1], a12 = src[r1 + c2];
+    const double a21 = src[r2 + c1], a22 = src[r2 + c2];
+    const double v11 = vsrc[r1 + c1], v12 = vsrc[r1 + c2];
+    const double v21 = vsrc[r2 + c1], v22 = vsrc[r2 + c2];
+    double cQ, sQ;
+    jacobi_rotation(q11, q22, q12, cQ, sQ);
+    const double cP = lane_gather(cQ, lp), sP = lane_gather(sQ, lp);
+    // M = A J_Q, then J_P^T M
+    const double m11 = cQ * a11 - sQ * a12, m12 = sQ * a11 + cQ * a12;
+    const double m21 = cQ * a21 - sQ * a22, m22 = sQ * a21 + cQ * a22;
+    const double b11 = cP * m11 - sP * m21, b12 = cP * m12 - sP * m22;
+    const double b21 = sP * m11 + cP * m21, b22 = sP * m12 + cP * m22;
+    if (act) {
+      dst[nr1 + nc1] = b11;
+      dst[nr1 + nc2] = b12;
+      dst[nr2 + nc1] = b21;
+      dst[nr2 + nc2] = b22;
+      // V J_Q on rows 2P, 2P+1 (V's rows stay; its columns move with A's)
+      vdst[r1 + nc1] = cQ * v11 - sQ * v12;
+      vdst[r1 + nc2] = sQ * v11 + cQ * v12;
+      vdst[r2 + nc1] = cQ * v21 - sQ * v22;
+      vdst[r2 + nc2] = sQ * v21 + cQ * v22;
+      if (last) {
+        if (P == Q) {   // b11, b22 on the diagonal
+          dia += b11 * b11 + b22 * b22;
+          off += b12 * b12 + b21 * b21;
+        } else {
+          off += b11 * b11 + b12 * b12 + b21 * b21 + b22 * b22;
+        }
+      }
+    }
+    wave_lds_sync();
+  };
+  double prev = 0.0;   // off-diagonal mass before the last sweep
+  bool flip = false;   // data in (W2, V) rather than (W1, A)
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (!(off > 1e-30 * (dia + off)) || (sweep > 0 && off >= prev)) break;
+    prev = off;
+    off = 0.0;
+    dia = 0.0;
+    for (int rd = 0; rd < m1; ++rd) {
+      const bool last = rd == m1 - 1;
+      if (flip) one_round(W2, W1, V, A, last);
+      else one_round(W1, W2, A, V, last);
+      flip = !flip;
+    }
+    off = wave_sum_uniform(off);
+    dia = wave_sum_uniform(dia);
+  }
+  return flip;
+}
+
 // block_jacobi_eig for n <= 16 run by one wave (lane = threadIdx.x & 63 of
 // the first wave of the block) with no block barrier: the same sweeps
 // (jacobi_sweeps, one-wave form), set-up and sorting done by the wave.
@@ -266,7 +336,7 @@ __device__ __forceinline__ void wave_jacobi_eig(double *A, int n, double *V, dou
     if (i < ne && j < ne) A[i * ne + j] = i == j ? 1.0 : 0.0;
   }
   wave_lds_sync();
-  const bool flip = jacobi_sweeps<true>(W1, W2, A, V, ne, off, dia, nullptr);
+  const bool flip = wave_jacobi_sweeps(W1, W2, A, V, ne, off, dia, lane);
   wave_lds_sync();
   const double *cur = flip ? W2 : W1;
   double *nxt = flip ? W1 : W2;
