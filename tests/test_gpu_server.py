@@ -41,7 +41,7 @@ def observed(pb):
 
 
 def mix():
-    """Problems of several orders, ranks, sizes and both precisions; two share a batch group."""
+    """Problems of several orders, ranks, sizes and both precisions; the two order-6 ones share a batch group."""
     out = []
     out.append((wl.named("c1"), dict(step=1.001, stop_rule="residual", tol=1e-10, max_iter=500)))
     out.append((wl.named("c2_small"), dict(step=0.8, stop_rule="change", tol=1e-6, max_iter=200)))
@@ -56,6 +56,10 @@ def mix():
                 dict(step=0.8, stop_rule="none", max_iter=15)))
     out.append((wl.named("c2_small", seed=4), dict(step=0.8, stop_rule="change", tol=1e-6, max_iter=200,
                                                    precision="mixed")))
+    # a second order-6 problem of the same ranks: the two share a launch of the
+    # one-workgroup dense kernels (mode sizes <= 8, padded rank 4)
+    out.append((wl.problem(shape, wl.feasible_ranks(shape, 4), 1300, 16, name="order6b", init_rel=0.1),
+                dict(step=0.8, stop_rule="none", max_iter=15)))
     return out
 
 
