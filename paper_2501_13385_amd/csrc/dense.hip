@@ -39,6 +39,7 @@
 #include "block_ops.hpp"
 #include "small_la.hpp"
 #include "solver.hpp"
+#include "tiles.hpp"
 
 namespace prgd {
 
@@ -615,6 +616,110 @@ __device__ __forceinline__ void rgram_body(const Dev &d, int bx_, int b, double 
     if (a > bb) continue;
     double v = 0.0;
     for (int g = 0; g < q.G; ++g) v += red[g * NE + t];
+    mypart[sym_index(a, bb, R2)] = v;
+  }
+}
+
+// Slice blocks of a right-Gram step on the matrix cores, for 2R <= 16 NT:
+// the 2R x 2R matrices as NT x NT tiles of 16 x 16 (row layout of tiles.hpp),
+// four waves each taking every fourth slice of the block:
+//   M^T = GR_{b+1} C^T,   GR += C M^T
+// tile by tile, (C^T)'s tiles serving both as the B operand of the first
+// product and, transposed in place of C, as the A operand of the second
+// (GR_{b+1} is symmetric).  Only the upper triangle's tiles of the sum are
+// formed.  The waves' sums are added in wave order and the block's partial
+// is written as rgram_body writes it (packed upper triangle), so the finish
+// is shared.  The block's slices of T and X are staged in LDS four at a time.
+template <int NT>
+__global__ void __launch_bounds__(256) k_rgram_tiles(const Dev *__restrict__ dt, int b) {
+  constexpr int NW = 4, W = 16 * NT;
+  __shared__ double sTX[NW * 2 * 256];
+  __shared__ double red[NW * W * W];
+  const Dev &d = dt[blockIdx.y];
+  const int bx_ = blockIdx.x, m = d.m;
+  const int nb = nblocks_for(d.n[b], 4);
+  if (d.st->done) return;
+  if (bx_ >= nb) {
+    const int lb = bx_ - nb;
+    if (b == m - 1 && lb < nblocks_for(d.n[0], 4)) gram_first_cut(d, lb);
+    return;
+  }
+  const int R = d.R, R2 = 2 * R, RR = R * R;
+  const int per = (d.n[b] + nb - 1) / nb;
+  const int x0 = bx_ * per, x1 = min(d.n[b], x0 + per);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, row0 = lane >> 4, col = lane & 15;
+  const double alpha = d.st->alpha_n;
+  // tiles of GR_{b+1} (the identity for the last core)
+  d4 g[NT][NT];
+  {
+    const auto gn = glb((const double *)sm_slot(d, b + 1, S_GR));
+#pragma unroll
+    for (int P = 0; P < NT; ++P)
+#pragma unroll
+      for (int Q = 0; Q < NT; ++Q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * P + row0 + 4 * v, j = 16 * Q + col;
+          g[P][Q][v] = (i < R2 && j < R2) ? (b == m - 1 ? (i == j ? 1.0 : 0.0) : gn[i * R2 + j]) : 0.0;
+        }
+  }
+  d4 acc[NT][NT];
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int J = 0; J < NT; ++J) acc[I][J] = zero4();
+  for (int base = x0; base < x1; base += NW) {
+    __syncthreads();   // the previous group's slices have been read
+    const int cnt = min(NW, x1 - base);
+    for (int e = threadIdx.x; e < cnt * RR; e += blockDim.x) {
+      const int q = e / RR, t = e - q * RR;
+      const long long off = d.coff[b] + (long long)(base + q) * RR + t;
+      sTX[q * 2 * 256 + t] = glb(d.cores)[off];
+      sTX[q * 2 * 256 + 256 + t] = glb(d.X)[off];
+    }
+    __syncthreads();
+    if (w < cnt) {
+      const double *T = sTX + w * 2 * 256, *X = T + 256;
+      d4 ct[NT][NT];   // tile (K, J) of C^T: entry (r, c) = C(16 J + c, 16 K + r)
+#pragma unroll
+      for (int K = 0; K < NT; ++K)
+#pragma unroll
+        for (int J = 0; J < NT; ++J)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            ct[K][J][v] = block_core_entry(T, X, R, b, m, alpha, 16 * J + col, 16 * K + row0 + 4 * v);
+      d4 mt[NT][NT];   // M^T = GR_{b+1} C^T
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = 0; J < NT; ++J) {
+          d4 t = zero4();
+#pragma unroll
+          for (int K = 0; K < NT; ++K) t = mm16(g[K][I], ct[K][J], t);
+          mt[I][J] = t;
+        }
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = I; J < NT; ++J)
+#pragma unroll
+          for (int K = 0; K < NT; ++K) acc[I][J] = mm16(ct[K][I], mt[K][J], acc[I][J]);
+    }
+  }
+  // the waves' sums, added in wave order, as the packed upper triangle
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int J = I; J < NT; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w * W * W + (16 * I + row0 + 4 * v) * W + 16 * J + col] = acc[I][J][v];
+  __syncthreads();
+  auto mypart = glb(d.part) + (long long)bx_ * (R2 * (R2 + 1) / 2);
+  for (int t = threadIdx.x; t < R2 * R2; t += blockDim.x) {
+    const int a = t / R2, bb = t - a * R2;
+    if (a > bb) continue;
+    double v = 0.0;
+    for (int q = 0; q < NW; ++q) v += red[q * W * W + a * W + bb];
     mypart[sym_index(a, bb, R2)] = v;
   }
 }
@@ -1268,7 +1373,10 @@ hipError_t launch_retract(const Batch &bt, hipStream_t s, int init, bool &output
     if (g <= FUSE_MAX) {   // b = 1 also truncates cut 1
       hipLaunchKernelGGL(k_rgram_fused, dim3(1, ns), dim3(1024), 0, s, bt.dt, b, g);
     } else {
-      hipLaunchKernelGGL(k_rgram, dim3(g, ns), dim3(1024), 0, s, bt.dt, b);
+      const int rmax = max_over(bt, [&](const Dev &d) { return d.R; });
+      if (rmax <= 8) hipLaunchKernelGGL(k_rgram_tiles<1>, dim3(g, ns), dim3(256), 0, s, bt.dt, b);
+      else if (rmax <= 16) hipLaunchKernelGGL(k_rgram_tiles<2>, dim3(g, ns), dim3(256), 0, s, bt.dt, b);
+      else hipLaunchKernelGGL(k_rgram, dim3(g, ns), dim3(1024), 0, s, bt.dt, b);
       hipLaunchKernelGGL(k_rgram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, b);
     }
   }

@@ -30,25 +30,11 @@
 #include "prgd_internal.hpp"
 #include "small_la.hpp"
 #include "solver.hpp"
+#include "tiles.hpp"
 
 namespace prgd {
 
 namespace {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-constexpr int T16 = 256;   // doubles of one 16 x 16 tile
-
-// A B from A^T and B in row layout, added to acc
-__device__ __forceinline__ d4 mm16(d4 at, d4 b, d4 acc) {
-  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(at[0], b[0], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(at[1], b[1], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(at[2], b[2], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(at[3], b[3], acc, 0, 0, 0);
-  return acc;
-}
-
-__device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
 
 // row-layout tile from a row-major 16 x 16 LDS matrix, or its transpose
 __device__ __forceinline__ d4 load_tile(const double *M, int lane) {
