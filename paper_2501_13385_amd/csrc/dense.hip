@@ -195,6 +195,101 @@ __device__ __forceinline__ void gram_body(const Dev &d, int bx_, int j, double *
   }
 }
 
+// Slice blocks of a weighted Gram step on the matrix cores, for R <= 16 (one
+// 16 x 16 tile, row layout of tiles.hpp), four waves each taking every fourth
+// slice of the block:
+//   left blocks (core j-1):  GL += omega T^T (GL_{j-1} T),  Theta += T^T Y
+//   right blocks (core m-j): H  += omega T (H_{m-j+1} T^T)
+// The Gram of the previous step enters transposed (as the A operand's
+// transpose), T as itself or transposed as each product needs.  The waves'
+// sums are added in wave order and written in gram_body's partial layout.
+__global__ void __launch_bounds__(256) k_gram_tiles(const Dev *__restrict__ dt, int j) {
+  constexpr int NW = 4;
+  __shared__ double sTY[NW * 2 * 256];
+  __shared__ double sw[NW];
+  __shared__ double red[NW * 2 * 256];
+  const Dev &d = dt[blockIdx.y];
+  const int bx_ = blockIdx.x;
+  const int R = d.R, RR = R * R, m = d.m;
+  const int nbL = nblocks_for(d.n[j - 1], 8), nbH = nblocks_for(d.n[m - j], 8);
+  if (bx_ >= nbL + nbH || d.st->done) return;
+  const bool left = bx_ < nbL;
+  const int c = left ? j - 1 : m - j;
+  const int lb = left ? bx_ : bx_ - nbL;
+  const int nbk = left ? nbL : nbH;
+  const int per = (d.n[c] + nbk - 1) / nbk;
+  const int x0 = lb * per, x1 = min(d.n[c], x0 + per);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, row0 = lane >> 4, col = lane & 15;
+  // the previous Gram, transposed: tile entry (r, c) = G(c, r)
+  d4 gt;
+  {
+    const auto gsrc = glb((const double *)(left ? sm_slot(d, j - 1, S_GL) : sm_slot(d, m - j + 1, S_H)));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      gt[v] = (r < R && col < R) ? gsrc[col * R + r] : 0.0;
+    }
+  }
+  auto tile = [&](const double *M, bool tr) {
+    d4 o;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = row0 + 4 * v;
+      o[v] = (r < R && col < R) ? M[tr ? col * R + r : r * R + col] : 0.0;
+    }
+    return o;
+  };
+  d4 acc = zero4(), th = zero4();
+  for (int base = x0; base < x1; base += NW) {
+    __syncthreads();   // the previous group's slices have been read
+    const int cnt = min(NW, x1 - base);
+    for (int e = threadIdx.x; e < cnt * RR; e += blockDim.x) {
+      const int q = e / RR, t = e - q * RR;
+      const long long off = d.coff[c] + (long long)(base + q) * RR + t;
+      sTY[q * 512 + t] = glb(d.cores)[off];
+      if (left) sTY[q * 512 + 256 + t] = load_grad(d, off);
+    }
+    if ((int)threadIdx.x < cnt) sw[threadIdx.x] = glb(d.omega)[d.soff[c] + base + threadIdx.x];
+    __syncthreads();
+    if (w < cnt) {
+      const double *T = sTY + w * 512, *Y = T + 256;
+      const double om = sw[w];
+      if (left) {
+        const d4 tt = tile(T, false);
+        d4 n = mm16(gt, tt, zero4());   // GL_{j-1} T
+#pragma unroll
+        for (int v = 0; v < 4; ++v) n[v] *= om;
+        acc = mm16(tt, n, acc);         // T^T (omega GL T)
+        th = mm16(tt, tile(Y, false), th);
+      } else {
+        const d4 ttr = tile(T, true);
+        d4 n = mm16(gt, ttr, zero4());  // H_{m-j+1} T^T
+#pragma unroll
+        for (int v = 0; v < 4; ++v) n[v] *= om;
+        acc = mm16(ttr, n, acc);        // T (omega H T^T)
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = row0 + 4 * v;
+    red[w * 512 + r * 16 + col] = acc[v];
+    red[w * 512 + 256 + r * 16 + col] = th[v];
+  }
+  __syncthreads();
+  auto mypart = glb(d.part) + (left ? (long long)lb * 2 * RR : (long long)nbL * 2 * RR + (long long)lb * RR);
+  for (int t = threadIdx.x; t < RR; t += blockDim.x) {
+    const int a = t / R, bcol = t - a * R;
+    double a0 = 0.0, a1 = 0.0;
+    for (int q = 0; q < NW; ++q) {
+      a0 += red[q * 512 + a * 16 + bcol];
+      a1 += red[q * 512 + 256 + a * 16 + bcol];
+    }
+    mypart[t] = a0;
+    if (left) mypart[RR + t] = a1;
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_gram(const Dev *__restrict__ dt, int j) {
   __shared__ double smem[SMEM];
   gram_body(dt[blockIdx.y], (int)blockIdx.x, j, smem);
@@ -1335,7 +1430,10 @@ hipError_t launch_project(const Batch &bt, hipStream_t s) {
     if (g <= FUSE_MAX) {
       hipLaunchKernelGGL(k_gram_fused, dim3(1, ns), dim3(1024), 0, s, bt.dt, j, g);
     } else {
-      hipLaunchKernelGGL(k_gram, dim3(g, ns), dim3(1024), 0, s, bt.dt, j);
+      if (max_over(bt, [&](const Dev &d) { return d.R; }) <= 16)
+        hipLaunchKernelGGL(k_gram_tiles, dim3(g, ns), dim3(256), 0, s, bt.dt, j);
+      else
+        hipLaunchKernelGGL(k_gram, dim3(g, ns), dim3(1024), 0, s, bt.dt, j);
       hipLaunchKernelGGL(k_gram_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, j);
     }
   }
