@@ -953,6 +953,91 @@ __device__ __forceinline__ void left_body(const Dev &d, int bx_, int i, double *
   }
 }
 
+// Slice blocks of a left-sweep cut on the matrix cores, for 2R <= 16 NT: B =
+// P_{i-1} C_c(x) has only R <= 16 nonzero rows, so it is one row of NT tiles,
+// and G_B = sum_x B^T B is formed on the upper triangle's tiles, four waves
+// each taking every fourth slice of the block.  P enters transposed (the A
+// operand's transpose), C and B as themselves.  Partials as left_body's.
+template <int NT>
+__global__ void __launch_bounds__(256) k_left_tiles(const Dev *__restrict__ dt, int i) {
+  constexpr int NW = 4, W = 16 * NT;
+  __shared__ double sTX[NW * 2 * 256];
+  __shared__ double red[NW * W * W];
+  const Dev &d = dt[blockIdx.y];
+  const int bx_ = blockIdx.x, m = d.m, c = i - 1;
+  const int nb = nblocks_for(d.n[c], 4);
+  if (bx_ >= nb || d.st->done) return;
+  const int R = d.R, R2 = 2 * R, RR = R * R;
+  const int per = (d.n[c] + nb - 1) / nb;
+  const int x0 = bx_ * per, x1 = min(d.n[c], x0 + per);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, row0 = lane >> 4, col = lane & 15;
+  const double alpha = d.st->alpha_n;
+  // tiles (K, 0) of P^T: entry (r, q) = P(q, 16 K + r), P = e_0^T for the first core
+  d4 ptr[NT];
+  {
+    const auto ps = glb((const double *)sm_slot(d, c, S_P));
+#pragma unroll
+    for (int K = 0; K < NT; ++K)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * K + row0 + 4 * v;
+        ptr[K][v] = (col < R && r < R2) ? (c == 0 ? (col == 0 && r == 0 ? 1.0 : 0.0) : ps[col * R2 + r]) : 0.0;
+      }
+  }
+  d4 acc[NT][NT];
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int J = 0; J < NT; ++J) acc[I][J] = zero4();
+  for (int base = x0; base < x1; base += NW) {
+    __syncthreads();   // the previous group's slices have been read
+    const int cnt = min(NW, x1 - base);
+    for (int e = threadIdx.x; e < cnt * RR; e += blockDim.x) {
+      const int q = e / RR, t = e - q * RR;
+      const long long off = d.coff[c] + (long long)(base + q) * RR + t;
+      sTX[q * 2 * 256 + t] = glb(d.cores)[off];
+      sTX[q * 2 * 256 + 256 + t] = glb(d.X)[off];
+    }
+    __syncthreads();
+    if (w < cnt) {
+      const double *T = sTX + w * 2 * 256, *X = T + 256;
+      d4 bt[NT];   // tiles (0, J) of B = P C
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        d4 t = zero4();
+#pragma unroll
+        for (int K = 0; K < NT; ++K) {
+          d4 ck;   // tile (K, J) of C
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            ck[v] = block_core_entry(T, X, R, c, m, alpha, 16 * K + row0 + 4 * v, 16 * J + col);
+          t = mm16(ptr[K], ck, t);
+        }
+        bt[J] = t;
+      }
+#pragma unroll
+      for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = I; J < NT; ++J) acc[I][J] = mm16(bt[I], bt[J], acc[I][J]);
+    }
+  }
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int J = I; J < NT; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w * W * W + (16 * I + row0 + 4 * v) * W + 16 * J + col] = acc[I][J][v];
+  __syncthreads();
+  auto mypart = glb(d.part) + (long long)bx_ * (R2 * (R2 + 1) / 2);
+  for (int t = threadIdx.x; t < R2 * R2; t += blockDim.x) {
+    const int a = t / R2, bb = t - a * R2;
+    if (a > bb) continue;
+    double v = 0.0;
+    for (int q = 0; q < NW; ++q) v += red[q * W * W + a * W + bb];
+    mypart[sym_index(a, bb, R2)] = v;
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_left(const Dev *__restrict__ dt, int i) {
   __shared__ double smem[SMEM];
   left_body(dt[blockIdx.y], (int)blockIdx.x, i, smem);
@@ -1483,7 +1568,10 @@ hipError_t launch_retract(const Batch &bt, hipStream_t s, int init, bool &output
     if (g <= FUSE_MAX) {
       hipLaunchKernelGGL(k_left_fused, dim3(1, ns), dim3(1024), 0, s, bt.dt, i, g);
     } else {
-      hipLaunchKernelGGL(k_left, dim3(g, ns), dim3(1024), 0, s, bt.dt, i);
+      const int rmax = max_over(bt, [&](const Dev &d) { return d.R; });
+      if (rmax <= 8) hipLaunchKernelGGL(k_left_tiles<1>, dim3(g, ns), dim3(256), 0, s, bt.dt, i);
+      else if (rmax <= 16) hipLaunchKernelGGL(k_left_tiles<2>, dim3(g, ns), dim3(256), 0, s, bt.dt, i);
+      else hipLaunchKernelGGL(k_left, dim3(g, ns), dim3(1024), 0, s, bt.dt, i);
       hipLaunchKernelGGL(k_left_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, i);
     }
   }
