@@ -1253,6 +1253,108 @@ __device__ __forceinline__ void output_body(const Dev &d, int bx_, int init, dou
   }
 }
 
+// New cores on the matrix cores, for 2R <= 16 NT: T'_c(x) = P_c (C_c(x)
+// Tr_{c+1}) (c < m-1) or P_{m-1} C_{m-1}(x), with C Tr formed first so that
+// every operand is a tile as stored (C^T's tiles as the A operand of C Tr;
+// P^T and Tr loaded as their tiles), four waves each taking every fourth
+// slice of the block.  Writes and stopping-test partials as output_body's.
+template <int NT>
+__global__ void __launch_bounds__(256) k_output_tiles(const Dev *__restrict__ dt, int init) {
+  constexpr int NW = 4;
+  __shared__ double sTX[NW * 2 * 256];
+  __shared__ double sbuf[16];
+  (void)init;
+  const Dev &d = dt[blockIdx.y];
+  const int bx_ = blockIdx.x;
+  if (bx_ >= d.blk_off[d.m] || d.st->done) return;
+  int c, x0, x1;
+  block_core(d, bx_, c, x0, x1);
+  const int R = d.R, R2 = 2 * R, m = d.m, RR = R * R;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, row0 = lane >> 4, col = lane & 15;
+  const double alpha = d.st->alpha_n;
+  const auto ps = glb((const double *)sm_slot(d, c, S_P));
+  const auto trs = glb((const double *)sm_slot(d, c + 1, S_TR));
+  // tiles (K, 0) of P^T (entry (r, q) = P(q, 16 K + r)) and (L, 0) of Tr
+  d4 ptr[NT], trt[NT];
+#pragma unroll
+  for (int K = 0; K < NT; ++K)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * K + row0 + 4 * v;
+      ptr[K][v] = (col < R && r < R2) ? (c == 0 ? (col == 0 && r == 0 ? 1.0 : 0.0) : ps[col * R2 + r]) : 0.0;
+      trt[K][v] = (c < m - 1 && col < R && r < R2) ? trs[r * R + col] : 0.0;
+    }
+  double nn = 0.0, cr = 0.0;
+  for (int base = x0; base < x1; base += NW) {
+    __syncthreads();   // the previous group's slices have been read
+    const int cnt = min(NW, x1 - base);
+    for (int e = threadIdx.x; e < cnt * RR; e += blockDim.x) {
+      const int q = e / RR, t = e - q * RR;
+      const long long off = d.coff[c] + (long long)(base + q) * RR + t;
+      sTX[q * 2 * 256 + t] = glb(d.cores)[off];
+      sTX[q * 2 * 256 + 256 + t] = glb(d.X)[off];
+    }
+    __syncthreads();
+    if (w < cnt) {
+      const int x = base + w;
+      const double *T = sTX + w * 2 * 256, *X = T + 256;
+      d4 out = zero4();
+      if (c < m - 1) {
+#pragma unroll
+        for (int K = 0; K < NT; ++K) {
+          d4 ctr = zero4();   // tile (K, 0) of C Tr
+#pragma unroll
+          for (int L = 0; L < NT; ++L) {
+            d4 ctl;   // tile (L, K) of C^T: entry (r, q) = C(16 K + q, 16 L + r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              ctl[v] = block_core_entry(T, X, R, c, m, alpha, 16 * K + col, 16 * L + row0 + 4 * v);
+            ctr = mm16(ctl, trt[L], ctr);
+          }
+          out = mm16(ptr[K], ctr, out);
+        }
+      } else {
+#pragma unroll
+        for (int K = 0; K < NT; ++K) {
+          d4 ck;   // tile (K, 0) of C
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            ck[v] = block_core_entry(T, X, R, c, m, alpha, 16 * K + row0 + 4 * v, col);
+          out = mm16(ptr[K], ck, out);
+        }
+      }
+      const long long off = d.coff[c] + (long long)x * RR;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = row0 + 4 * v;
+        if (a < R && col < R) {
+          glb(d.cores)[off + a * R + col] = out[v];
+          if (d.prec == PREC_MIXED) glb(d.cores32)[off + a * R + col] = (float)out[v];
+          long long bo = -1;
+          if (c == 0 && a == 0) bo = (long long)x * R + col;
+          if (c == m - 1 && col == 0) bo = (long long)d.n[0] * R + (long long)x * R + a;
+          if (bo >= 0) {
+            if (d.prec == PREC_MIXED) glb((float *)d.bnd)[bo] = (float)out[v];
+            else glb((double *)d.bnd)[bo] = out[v];
+          }
+          if (c == m - 1 && col == 0) {
+            double z = 0.0;   // (Z T_{m-1}(x))_a, Z the second block of P_{m-1}
+            for (int k = 0; k < R; ++k) z += ps[a * R2 + R + k] * T[k * R];
+            nn += out[v] * out[v];
+            cr += out[v] * z;
+          }
+        }
+      }
+    }
+  }
+  nn = block_sum(nn, sbuf);
+  cr = block_sum(cr, sbuf);
+  if (threadIdx.x == 0) {
+    glb(d.part)[2 * bx_] = nn;
+    glb(d.part)[2 * bx_ + 1] = cr;
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_output(const Dev *__restrict__ dt, int init) {
   __shared__ double smem[SMEM];
   output_body(dt[blockIdx.y], (int)blockIdx.x, init, smem);
@@ -1582,7 +1684,10 @@ hipError_t launch_retract(const Batch &bt, hipStream_t s, int init, bool &output
 hipError_t launch_output(const Batch &bt, hipStream_t s, int init) {
   const int m = bt.host[0].m, ns = bt.ns;
   const int g = max_over(bt, [&](const Dev &d) { return d.blk_off[m]; });
-  hipLaunchKernelGGL(k_output, dim3(g, ns), dim3(1024), 0, s, bt.dt, init);
+  const int rmax = max_over(bt, [&](const Dev &d) { return d.R; });
+  if (rmax <= 8) hipLaunchKernelGGL(k_output_tiles<1>, dim3(g, ns), dim3(256), 0, s, bt.dt, init);
+  else if (rmax <= 16) hipLaunchKernelGGL(k_output_tiles<2>, dim3(g, ns), dim3(256), 0, s, bt.dt, init);
+  else hipLaunchKernelGGL(k_output, dim3(g, ns), dim3(1024), 0, s, bt.dt, init);
   hipLaunchKernelGGL(k_output_fin, dim3(1, ns), dim3(1024), 0, s, bt.dt, init);
   return hipGetLastError();
 }
