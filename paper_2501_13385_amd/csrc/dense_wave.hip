@@ -1,22 +1,23 @@
-// One-wave retraction sweep for padded ranks R <= 8 and few slices per core.
+// The dense stage in one workgroup per solve, for padded ranks R <= 8 and at
+// most 8 slices per core: the weighted Gram sweep with the tangent components
+// (k_gram_wave) and the retraction with the new cores and the stopping test
+// (k_retract_wave).
 //
 // The retraction of Algorithm 1 on the rank-2r block TT W_l (see the notes at
 // the top of dense.hip for C_c, GR_b, F_b, S, Tr_i and P_i) is a chain of
 // 2(m-1) dependent steps on 2R x 2R matrices.  For R <= 8 every such matrix
-// fits one 16 x 16 tile, so one wave runs the whole chain: the cores T and the
-// tangent components X are copied into LDS once, every product is four
-// float64 16x16x4 MFMAs, and the state passed from step to step (GR_{b+1},
-// F_b, P_{i-1}) stays in registers or LDS, with no workgroup barrier and no
-// trip through global memory inside the chain.  The small factorisations
-// (pivoted Cholesky, Jacobi) are the one-wave routines of small_la.hpp.
+// fits one 16 x 16 tile, so one wave runs each chain: the cores T and the
+// tangent components X (or the gradient Y) are copied into LDS once, every
+// product is four float64 16x16x4 MFMAs, and the state passed from step to
+// step (GR_{b+1}, F_b, P_{i-1}) stays in registers or LDS, with no trip
+// through global memory inside the chain.  The factorisations that the chain
+// itself does not need (the Cholesky factors of the right Grams, the Gram
+// inverses) run on the other waves of the workgroup in parallel; those on
+// the chain (each cut's graded eigen-solve) are one-wave routines.
 //
-// Register layout of a 16 x 16 matrix M ("row layout"): element v of lane l
-// holds M((l >> 4) + 4 v, l & 15).  The float64 16x16x4 MFMA takes in step s
-// the operand A(l & 15, 4 s + (l >> 4)) and the operand B(4 s + (l >> 4),
-// l & 15): the first is element s of A^T in row layout, the second element s
-// of B, and the product comes back in row layout.  So A B needs A^T and B in
-// row layout; for symmetric A (the Grams) A^T is A, which is why the chain
-// of products below needs no transposes:
+// Tiles use the row layout of tiles.hpp: A B needs A^T and B as tiles, and
+// for symmetric A (the Grams) A^T is A, which is why the chains of products
+// below need no transposes:
 //   GR_b   = C (GR_{b+1} C^T)      operands GR_{b+1}, C^T, then C^T, (GR C^T)
 //   G_B    = B^T B, B = P C        operands P^T, C, then B, B
 //   S      = F^T (G_B F)           operands G_B, F, then F, (G_B F)
@@ -365,7 +366,7 @@ __device__ __forceinline__ void breakdown(const Dev &d, int lane) {
 
 }  // namespace
 
-// bytes of dynamic LDS the one-wave retraction needs for solve d
+// bytes of dynamic LDS the one-workgroup retraction needs for solve d
 static size_t retract_wave_lds(const Dev &d) {
   return sizeof(double) * (size_t)(2 * d.coff[d.m] + (long long)T16 * (d.m + 7) + 32);
 }
@@ -625,7 +626,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_retract_wave(const Dev *__restri
 }
 
 // ---------------------------------------------------------------------------
-// One-wave Gram sweep of the preconditioned projection (Lemma 3): step
+// One-workgroup Gram sweep of the preconditioned projection (Lemma 3): step
 // j = 1..m-1 forms
 //   GL_j       = sum_x omega_{j-1}(x) T_{j-1}(x)^T GL_{j-1} T_{j-1}(x)
 //   H_{m-j}    = sum_x omega_{m-j}(x) T_{m-j}(x) H_{m-j+1} T_{m-j}(x)^T
@@ -854,7 +855,7 @@ __global__ void __launch_bounds__(64 * NWAVE) k_gram_wave(const Dev *__restrict_
   }
 }
 
-// The one-wave sweep applies when every member of the batch has R <= 8, at
+// The one-workgroup sweeps apply when every member of the batch has R <= 8, at
 // most 8 slices per core (beyond that the slice-parallel launches win) and
 // cores that fit the LDS of one workgroup next to the work tiles.
 constexpr int WAVE_MAX_N = 8;
