@@ -63,6 +63,8 @@ def make_case(name):
         return wl.problem([9, 300, 11], [1, 2, 2, 1], 200, 9, name=name, init_rel=0.1)
     if name == "o3_rank16":            # order 3: largest supported rank, several tiles and a ragged tail
         return wl.problem([33, 47, 29], [1, 16, 16, 1], 30001, 10, name=name, init_rel=0.1)
+    if name == "o4_rank12":            # order 4, padded rank 12: 2R = 24 over two 16 x 16 tiles, two middle cores
+        return wl.problem([12, 14, 13, 11], [1, 10, 12, 9, 1], 20000, 12, name=name, init_rel=0.1)
     if name == "order6":
         shape = [3, 4, 3, 5, 3, 4]
         return wl.problem(shape, wl.feasible_ranks(shape, 4), 1200, 6, name="order6", init_rel=0.1)
@@ -117,7 +119,7 @@ def test_eval_matches_reference(L):
 
 @pytest.mark.parametrize("name,c,iters", [("c1", 1.001, 25), ("c2_small", 0.8, 12), ("ragged", 0.8, 10),
                                           ("order2", 0.8, 10), ("order6", 0.8, 8), ("o3_many_segments", 0.5, 5),
-                                          ("o3_rank16", 0.8, 5)])
+                                          ("o3_rank16", 0.8, 5), ("o4_rank12", 0.8, 6)])
 def test_fp64_iterates_match_reference_each_iteration(L, name, c, iters):
     pb = make_case(name)
     say("case", name, "iters", iters)
