@@ -207,6 +207,13 @@ __host__ __device__ inline int chain_part_width(int m, int u, int R) {
   return nc * 256 + nc * chain_nx(R) + u * R * R;
 }
 __host__ __device__ inline int chain_nslots(int nc) { return nc - 2 > 1 ? nc - 2 : 1; }
+// LDS elements of one wave's region: the parking slots, and with all of them
+// granted also room for the wave's end-of-chunk sums (wr elements); with fewer
+// slots the sums share the regions of all waves
+__host__ __device__ inline int chain_region(int nslots, int nfull, int wr, int slotw) {
+  const int sl = nslots * slotw;
+  return nslots < nfull ? sl : (sl > wr ? sl : wr);
+}
 
 // Blocks of a slice-parallel reduction kernel over n slices: at least
 // `target` slices per block and at most 128 blocks, so that the finishing

@@ -343,7 +343,7 @@ __device__ __forceinline__ F slice_finish(F v, int lane) {
 }
 
 template <typename F, int R, int MAXC, int NW>
-__global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, int diag) {
+__global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, int diag, int nsl) {
   const Dev &d = dt[blockIdx.y];
   if ((int)blockIdx.x >= d.ch_nchunks || (!diag && d.st->done)) return;
   typedef MmaC<F> M;
@@ -370,10 +370,13 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
     if (c < nc) lo += d.n[u + c] * SL;
   }
   const int lo_last = lo - d.n[m - 1] * SL;
-  const int nslots = chain_nslots(nc);
+  // parking slots per wave: one per generic core when the launch grants them
+  // all, else nsl (>= 2) and the right interfaces are parked in segments
+  const int nfull = chain_nslots(nc);
+  const int nslots = min(nfull, max(nsl, 2));
   const int WT = nc * 256, WS = nc * NX;
   const int WR = WT + WS;                                   // end-of-chunk sums per wave
-  const int region = nslots * SLOTW > WR ? nslots * SLOTW : WR;
+  const int region = chain_region(nslots, nfull, WR, SLOTW);
   F *wsl = lc + lo + (long long)w * region;
   F *wss = lc + lo + (long long)NW * region + (long long)w * WS;   // this wave's slice sums
   F *lamu_s = lc + lo + (long long)NW * region + (long long)NW * WS;   // l_{u+1}, shared
@@ -443,8 +446,6 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
   const F *tlast = lc + lo_last;
   const int lo_pen = nc >= 2 ? lo_last - d.n[m - 2] * SL : 0;
   const int ng = nc - 2;                  // generic cores (may be <= 0)
-  const int stgP = nc - 2 >= 1 ? (nc - 3 < nslots - 1 ? nc - 3 : nslots - 1) : 0;   // staging slot of core nc-2
-  const int stgL = nc - 1 >= 1 ? (nc - 2 < nslots - 1 ? nc - 2 : nslots - 1) : 0;   // of core nc-1
   const int nbt = (cl + 63) >> 6;
   for (int bt = w; bt < nbt; bt += NW) {
     const int jj = bt * 64 + lane;
@@ -466,9 +467,11 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
 #pragma unroll
     for (int c = MG - 1; c >= 0; --c) {
       if (c < ng) {
-        F *dst = wsl + c * SLOTW + lane + (lane >> 4);
+        if (c < nslots) {   // the first segment's interfaces
+          F *dst = wsl + c * SLOTW + lane + (lane >> 4);
 #pragma unroll
-        for (int a = 0; a < R; ++a) dst[a * 68] = rho[a];
+          for (int a = 0; a < R; ++a) dst[a * 68] = rho[a];
+        }
         chain_right_step<F, R>(rho, lc + loff[c] + xk[c] * SL);
       }
     }
@@ -499,30 +502,62 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
       const F v = slice_finish<F, NX>(slice_scatter<F, NX>(r2, xl, lane), lane);
       if (lead) wss[(nc - 1) * NX + xs] += v;
     }
-    // left sweep with the gradient tiles
+    // left sweep with the gradient tiles, generic cores in segments: the
+    // cores [s0, s0 + sl) find r_{k+1} at slots 0 .. sl-1.  The first segment
+    // was parked by the sweep above; a later one is parked by a second right
+    // sweep from the last core down (its first core's staged R_j l_k goes to
+    // slot sl, so a later segment holds at most nslots - 1 cores).
     chain_wave_order();   // the parked r_{k+1} before the tiles read them
+    int s0 = 0, sl = ng < nslots ? ng : nslots;
+    int slast = 0;        // slot of the last generic core's r_{k+1}
+    while (s0 < ng) {
+      if (s0 > 0) {
+        F rr[R];
 #pragma unroll
-    for (int c = 0; c < MG; ++c) {
-      if (c < ng) {
-        // l_{k+1} is formed alongside core k's MFMA steps (independent work
-        // for the scheduler to interleave); core k's A operand is the staged l_k
-        if (c == 0) {
-          chain_left_step<F, R>(lam, lc + loff[c] + xk[c] * SL);
-          chain_mfma<F, R, 0, 0>(acc[c], xk[c], xl, res, lamA, wsl, wsl + c * SLOTW, tlast, SL, bE, lane,
-                                 std::make_integer_sequence<int, 16>{});
-        } else {
-          F *stg = wsl + (c - 1) * SLOTW;   // r_{u+c} there was read by core c - 1
-          F *dst = stg + lane + (lane >> 4);
+        for (int a = 0; a < R; ++a) rr[a] = tlast[xl * SL + a * R];
+        if (nc >= 2) chain_right_step<F, R>(rr, lc + lo_pen + xp * SL);
 #pragma unroll
-          for (int a = 0; a < R; ++a) dst[a * 68] = res * lam[a];
-          chain_wave_order();
-          chain_left_step<F, R>(lam, lc + loff[c] + xk[c] * SL);
-          chain_mfma<F, R, 1, 0>(acc[c], xk[c], xl, res, lamA, stg, wsl + c * SLOTW, tlast, SL, bE, lane,
-                                 std::make_integer_sequence<int, 16>{});
+        for (int c = MG - 1; c >= 1; --c) {
+          if (c < ng && c >= s0) {
+            if (c < s0 + sl) {
+              F *dst = wsl + (c - s0) * SLOTW + lane + (lane >> 4);
+#pragma unroll
+              for (int a = 0; a < R; ++a) dst[a * 68] = rr[a];
+            }
+            if (c > s0) chain_right_step<F, R>(rr, lc + loff[c] + xk[c] * SL);
+          }
         }
         chain_wave_order();
       }
+#pragma unroll
+      for (int c = 0; c < MG; ++c) {
+        if (c >= s0 && c < s0 + sl) {
+          const int sb = c - s0;
+          // l_{k+1} is formed alongside core k's MFMA steps (independent work
+          // for the scheduler to interleave); core k's A operand is the staged l_k
+          if (c == 0) {
+            chain_left_step<F, R>(lam, lc + loff[c] + xk[c] * SL);
+            chain_mfma<F, R, 0, 0>(acc[c], xk[c], xl, res, lamA, wsl, wsl, tlast, SL, bE, lane,
+                                   std::make_integer_sequence<int, 16>{});
+          } else {
+            // a slot whose r_{k+1} the previous core has read, or the one past the segment's
+            F *stg = wsl + (sb == 0 ? sl : sb - 1) * SLOTW;
+            F *dst = stg + lane + (lane >> 4);
+#pragma unroll
+            for (int a = 0; a < R; ++a) dst[a * 68] = res * lam[a];
+            chain_wave_order();
+            chain_left_step<F, R>(lam, lc + loff[c] + xk[c] * SL);
+            chain_mfma<F, R, 1, 0>(acc[c], xk[c], xl, res, lamA, stg, wsl + sb * SLOTW, tlast, SL, bE, lane,
+                                   std::make_integer_sequence<int, 16>{});
+          }
+          chain_wave_order();
+        }
+      }
+      slast = ng - 1 - s0;
+      s0 += sl;
+      sl = ng - s0 < nslots - 1 ? ng - s0 : nslots - 1;
     }
+    const int stgP = slast, stgL = slast;   // staging of cores m-2 and m-1
     if (nc >= 2) {   // core m-2
       F *stg = wsl + stgP * SLOTW;
       if (ng >= 1) {
@@ -571,26 +606,37 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
       const int x = idx[(long long)k * N + cs];
       pre_sl2[t] = gcores[d.coff[k] + (long long)x * RR + e];
     }
-  F *red = lc + lo;                              // reuses the slots: per wave tiles then slice sums
-  auto put_core = [&](int c, const typename M::acc_t &tile) {
+  // the waves' tiles and slice sums, summed in wave order: nr regions of WR
+  // in the slot area; waves w < nr write region w, the rest add into region
+  // w mod nr in rounds, then the regions are summed in order
+  F *red = lc + lo;
+  const int nr = min(NW, (NW * region) / WR);
+  for (int t = 0; t < NW; t += nr) {
+    if (w >= t && w < t + nr) {
+      F *dst = red + (long long)(w - t) * WR;
+      auto put_core = [&](int c, const typename M::acc_t &tile) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[w * region + c * 256 + M::row(lane, v) * 16 + (lane & 15)] = tile[v];
-  };
+        for (int v = 0; v < 4; ++v) {
+          F &o = dst[c * 256 + M::row(lane, v) * 16 + (lane & 15)];
+          o = t == 0 ? tile[v] : o + tile[v];
+        }
+      };
 #pragma unroll
-  for (int c = 0; c < MG; ++c)
-    if (c < ng) put_core(c, acc[c]);
-  if (nc >= 2) put_core(nc - 2, accP);
-  put_core(nc - 1, accL);
-  for (int i = lane; i < WS; i += 64) red[w * region + WT + i] = wss[i];
-  __syncthreads();
+      for (int c = 0; c < MG; ++c)
+        if (c < ng) put_core(c, acc[c]);
+      if (nc >= 2) put_core(nc - 2, accP);
+      put_core(nc - 1, accL);
+      for (int i = lane; i < WS; i += 64) dst[WT + i] = t == 0 ? wss[i] : dst[WT + i] + wss[i];
+    }
+    __syncthreads();
+  }
   const int W = chain_part_width(m, u, R);
   const auto part = glb((F *)d.ch_part) + (long long)blockIdx.x * W;
-  // waves summed in wave order; core u+1's tile holds G_x (A = e_1) and is
-  // written as l_{u+1}[a] G_x[b] below, the rest as it is
+  // core u+1's tile holds G_x (A = e_1) and is written as l_{u+1}[a] G_x[b]
+  // below, the rest as it is
   for (int e = threadIdx.x; e < WR; e += NT) {
     F v = red[e];
-#pragma unroll
-    for (int ww = 1; ww < NW; ++ww) v += red[ww * region + e];
+    for (int rg = 1; rg < nr; ++rg) v += red[(long long)rg * WR + e];
     red[e] = v;
     if (e >= 256) part[e] = v;
   }
@@ -753,35 +799,67 @@ __global__ void __launch_bounds__(256) k_chain_reduce2(const Dev *__restrict__ d
 
 hipError_t launch_sampled_fin(const Batch &bt, int diag, hipStream_t s);
 
-size_t chain_lds_bytes(int m, int u, const int *n, int R, int prec) {
+// Waves per workgroup: eight for float64 at R = 8 (two per SIMD; the
+// parking slots per wave are then cut to what fits, see chain_wave_slots),
+// four otherwise (their full slots already leave two workgroups per CU).
+int chain_waves(int R, int prec) { return (prec != PREC_MIXED && R == 8) ? 8 : 4; }
+
+// dynamic LDS of one solve with at most nsl parking slots per wave
+static size_t chain_bytes_at(int m, int u, const int *n, int R, int prec, int nsl) {
   const size_t f = prec == PREC_MIXED ? 4 : 8;
-  const int nc = m - u;
+  const int nc = m - u, nw = chain_waves(R, prec);
   size_t cores = 0;
   for (int k = u; k < m; ++k) cores += (size_t)n[k] * chain_slice_stride(R, (int)f);
-  const size_t slots = (size_t)chain_nslots(nc) * chain_slot_width(R);
-  const size_t red = (size_t)nc * (256 + chain_nx(R));
+  const int nfull = chain_nslots(nc);
+  const int ns = std::min(nfull, std::max(nsl, 2));
+  const int wr = nc * (256 + chain_nx(R));
+  const size_t region = (size_t)chain_region(ns, nfull, wr, chain_slot_width(R));
   const size_t wss = (size_t)nc * chain_nx(R);
   const size_t prefix = (size_t)u * R;   // the chunk's prefix interfaces
-  return (cores + 4 * std::max(slots, red) + 4 * wss + R + prefix) * f;
+  return (cores + nw * region + nw * wss + R + prefix) * f;
+}
+
+constexpr size_t CHAIN_LDS_BUDGET = (size_t)159 * 1024;
+
+// Parking slots per wave: all (one per generic core) when they fit in LDS;
+// with eight waves otherwise the most that fit, at least 2 (the later cores'
+// interfaces are then recomputed by a second right sweep).
+int chain_wave_slots(int m, int u, const int *n, int R, int prec) {
+  const int nfull = chain_nslots(m - u);
+  if (chain_waves(R, prec) == 4) return nfull;
+  for (int s = nfull; s > 2; --s)
+    if (chain_bytes_at(m, u, n, R, prec, s) <= CHAIN_LDS_BUDGET) return s;
+  return std::min(nfull, 2);
+}
+
+size_t chain_lds_bytes(int m, int u, const int *n, int R, int prec) {
+  return chain_bytes_at(m, u, n, R, prec, chain_wave_slots(m, u, n, R, prec));
 }
 
 int chain_maxc(int nc) { return nc <= 4 ? 4 : (nc <= 8 ? 8 : (nc <= 10 ? 10 : (nc <= 12 ? 12 : 16))); }
 
 template <typename F, int R, int MAXC>
 static hipError_t launch_chain_c(const Batch &bt, int diag, hipStream_t st, hipEvent_t after_main) {
-  constexpr int NW = 4;
+  constexpr int NW = (sizeof(F) == 8 && R == 8) ? 8 : 4;
+  if (chain_waves(R, bt.host[0].prec) != NW) return hipErrorInvalidValue;
   int g = 1;
   size_t lds = 0;
   long long nout = 1;
   int ng = 1;
+  int nsl = 1 << 20;   // parking slots per wave, common to the solves of the launch
+  for (int i = 0; i < bt.ns; ++i) {
+    const Dev &h = bt.host[i];
+    nsl = std::min(nsl, chain_wave_slots(h.m, h.ch_u, h.n, R, h.prec));
+  }
   for (int i = 0; i < bt.ns; ++i) {
     const Dev &h = bt.host[i];
     g = std::max(g, h.ch_nchunks);
-    lds = std::max(lds, chain_lds_bytes(h.m, h.ch_u, h.n, R, h.prec));
+    lds = std::max(lds, chain_bytes_at(h.m, h.ch_u, h.n, R, h.prec, nsl));
     nout = std::max<long long>(nout, (long long)h.soff[h.m] * (R * R + 1));
     ng = std::max(ng, (h.ch_nchunks + CHAIN_GROUP - 1) / CHAIN_GROUP);
   }
-  hipLaunchKernelGGL((k_chain<F, R, MAXC, NW>), dim3(g, bt.ns), dim3(NW * 64), lds, st, bt.dt, diag);
+  if (lds > CHAIN_LDS_BUDGET) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_chain<F, R, MAXC, NW>), dim3(g, bt.ns), dim3(NW * 64), lds, st, bt.dt, diag, nsl);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (after_main && (e = hipEventRecord(after_main, st)) != hipSuccess) return e;

@@ -5,7 +5,9 @@ The chain kernel applies when every core from some split u on has a mode size
 within one MFMA tile's slice range; the modes before u are shared by a whole
 chunk of samples.  The cases cover u = 0, 1, 2 and 3, padded ranks 2, 4 and 8,
 a first mode larger than the tile range (shared, so allowed), prefixes cut
-into several chunks, and a single partial batch.
+into several chunks, a single partial batch, and float64 rank-8 chains of 8,
+12 and 16 unshared cores, whose right interfaces do not all fit the per-wave
+LDS slots and are parked in segments.
 
 Bars: sampled pass in float64 within 1e-12 of the reference (sums in another
 order); iterates within 1e-10 per iteration; the pass repeats bit for bit
@@ -60,6 +62,15 @@ def chain_case(name):
     if name == "u3_split":       # prefixes of ~1560 samples cut into several chunks
         shape = [4] * 9
         return wl.problem(shape, wl.feasible_ranks(shape, 8), 100000, 26, name=name, init_rel=0.1)
+    if name == "u1_r8_o9":       # order 9, n = 4, ranks 8, u = 1: eight unshared cores, the
+        shape = [4] * 9          # right interfaces parked in two segments
+        return wl.problem(shape, wl.feasible_ranks(shape, 8), 9000, 31, name=name, init_rel=0.1)
+    if name == "u0_r8_o12":      # order 12, u = 0: three segments
+        shape = [4] * 12
+        return wl.problem(shape, wl.feasible_ranks(shape, 8), 2000, 32, name=name, init_rel=0.1)
+    if name == "u0_r8_o16":      # order 16, u = 0: sixteen unshared cores, five segments
+        shape = [4] * 16
+        return wl.problem(shape, wl.feasible_ranks(shape, 8), 3000, 33, name=name, init_rel=0.1)
     if name == "tiny":           # fewer samples than one wave
         shape = [4, 3, 4, 3]
         return wl.problem(shape, [1, 3, 4, 3, 1], 20, 27, name=name, init_rel=0.1)
@@ -69,7 +80,8 @@ def chain_case(name):
     raise KeyError(name)
 
 
-CASES = ["u0_r8", "u1_r8", "u2_r4", "u1_r2_n16", "u1_wide_first", "u3_split", "tiny", "ragged_r4"]
+CASES = ["u0_r8", "u1_r8", "u2_r4", "u1_r2_n16", "u1_wide_first", "u3_split", "tiny", "ragged_r4", "u1_r8_o9",
+         "u0_r8_o12", "u0_r8_o16"]
 
 
 def observed(pb):
@@ -127,7 +139,8 @@ def test_chain_sampled_pass_mixed(L, name):
         np.testing.assert_allclose(ss[k], ref_s[k], rtol=1e-5 * pb.order, atol=1e-12 * ref_s[k].max())
 
 
-@pytest.mark.parametrize("name,iters", [("u1_r8", 6), ("u2_r4", 6), ("u1_wide_first", 5), ("ragged_r4", 6)])
+@pytest.mark.parametrize("name,iters", [("u1_r8", 6), ("u2_r4", 6), ("u1_wide_first", 5), ("ragged_r4", 6),
+                                        ("u1_r8_o9", 5), ("u0_r8_o12", 4)])
 def test_chain_iterates_match_reference(L, name, iters):
     pb = chain_case(name)
     say("case", name)
