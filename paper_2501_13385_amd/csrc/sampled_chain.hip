@@ -20,7 +20,10 @@
 //   * Lane = sample.  A right sweep forms r_m, ..., r_{u+1} (slices of the
 //     cores u+1..m staged in LDS, rows of a slice read as 16-byte vectors) and
 //     parks r_{k+1} in LDS for the gradient; the residual follows from l_{u+1}
-//     and r_{u+1}; a left sweep then carries l_k.
+//     and r_{u+1}; a left sweep then carries l_k.  When a wave's LDS slots do
+//     not hold every parked interface (float64 at R = 8, eight waves per
+//     workgroup), the sweep parks the first cores' ones and the left sweep
+//     parks the rest in segments, each by a second right sweep from core m.
 //   * Gradient of core k >= u+1: a 16x16 MFMA tile whose rows are (x_hi, a)
 //     and columns (x_lo, b), x_k = x_hi * (16/R) + x_lo, holds the whole
 //     n_k x R x R gradient (n_k <= (16/R)^2).  A K-step takes the four samples
