@@ -352,6 +352,9 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
   typedef MmaC<F> M;
   constexpr int RR = R * R;
   constexpr int NT = NW * 64;
+  // eight waves: the launch may grant fewer parking slots than generic cores
+  // (segments); four waves: always all of them
+  constexpr bool SEG = NW > 4;
   constexpr int NX = ChainShape<R>::NX;
   constexpr int SLOTW = ChainShape<R>::SLOTW;
   constexpr int SL = RR + 16 / (int)sizeof(F);
@@ -376,7 +379,7 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
   // parking slots per wave: one per generic core when the launch grants them
   // all, else nsl (>= 2) and the right interfaces are parked in segments
   const int nfull = chain_nslots(nc);
-  const int nslots = min(nfull, max(nsl, 2));
+  const int nslots = SEG ? min(nfull, max(nsl, 2)) : nfull;
   const int WT = nc * 256, WS = nc * NX;
   const int WR = WT + WS;                                   // end-of-chunk sums per wave
   const int region = chain_region(nslots, nfull, WR, SLOTW);
@@ -470,7 +473,7 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
 #pragma unroll
     for (int c = MG - 1; c >= 0; --c) {
       if (c < ng) {
-        if (c < nslots) {   // the first segment's interfaces
+        if (!SEG || c < nslots) {   // the first segment's interfaces
           F *dst = wsl + c * SLOTW + lane + (lane >> 4);
 #pragma unroll
           for (int a = 0; a < R; ++a) dst[a * 68] = rho[a];
@@ -511,10 +514,10 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
     // sweep from the last core down (its first core's staged R_j l_k goes to
     // slot sl, so a later segment holds at most nslots - 1 cores).
     chain_wave_order();   // the parked r_{k+1} before the tiles read them
-    int s0 = 0, sl = ng < nslots ? ng : nslots;
+    int s0 = 0, sl = SEG ? (ng < nslots ? ng : nslots) : ng;
     int slast = 0;        // slot of the last generic core's r_{k+1}
     while (s0 < ng) {
-      if (s0 > 0) {
+      if (SEG && s0 > 0) {
         F rr[R];
 #pragma unroll
         for (int a = 0; a < R; ++a) rr[a] = tlast[xl * SL + a * R];
@@ -557,6 +560,7 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
         }
       }
       slast = ng - 1 - s0;
+      if constexpr (!SEG) break;
       s0 += sl;
       sl = ng - s0 < nslots - 1 ? ng - s0 : nslots - 1;
     }
@@ -613,7 +617,7 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
   // in the slot area; waves w < nr write region w, the rest add into region
   // w mod nr in rounds, then the regions are summed in order
   F *red = lc + lo;
-  const int nr = min(NW, (NW * region) / WR);
+  const int nr = SEG ? min(NW, (NW * region) / WR) : NW;
   for (int t = 0; t < NW; t += nr) {
     if (w >= t && w < t + nr) {
       F *dst = red + (long long)(w - t) * WR;
@@ -621,7 +625,7 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           F &o = dst[c * 256 + M::row(lane, v) * 16 + (lane & 15)];
-          o = t == 0 ? tile[v] : o + tile[v];
+          o = (SEG && t > 0) ? o + tile[v] : tile[v];
         }
       };
 #pragma unroll
@@ -629,7 +633,7 @@ __global__ void __launch_bounds__(NW * 64) k_chain(const Dev *__restrict__ dt, i
         if (c < ng) put_core(c, acc[c]);
       if (nc >= 2) put_core(nc - 2, accP);
       put_core(nc - 1, accL);
-      for (int i = lane; i < WS; i += 64) dst[WT + i] = t == 0 ? wss[i] : dst[WT + i] + wss[i];
+      for (int i = lane; i < WS; i += 64) dst[WT + i] = (SEG && t > 0) ? dst[WT + i] + wss[i] : wss[i];
     }
     __syncthreads();
   }
@@ -814,7 +818,8 @@ static size_t chain_bytes_at(int m, int u, const int *n, int R, int prec, int ns
   size_t cores = 0;
   for (int k = u; k < m; ++k) cores += (size_t)n[k] * chain_slice_stride(R, (int)f);
   const int nfull = chain_nslots(nc);
-  const int ns = std::min(nfull, std::max(nsl, 2));
+  // as in the kernel: four-wave launches always park every interface
+  const int ns = nw > 4 ? std::min(nfull, std::max(nsl, 2)) : nfull;
   const int wr = nc * (256 + chain_nx(R));
   const size_t region = (size_t)chain_region(ns, nfull, wr, chain_slot_width(R));
   const size_t wss = (size_t)nc * chain_nx(R);
