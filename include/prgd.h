@@ -199,7 +199,7 @@ prgd_status prgd_iterate(prgd_solver s, int32_t iters);
      1 sampled pass, reduction of the partials and the weights/step finish
      2 metric-weighted Gram sweeps and tangent components (projection)
      3 retraction sweeps (right Grams of W_l, truncated left sweep); for
-       padded ranks <= 8 with at most 8 slices per core one launch also
+       padded ranks <= 8 with at most 16 slices per core one launch also
        forms the new cores and runs the stopping test, so phase 4 is then
        part of phase 3
      4 new cores and stopping-test reductions

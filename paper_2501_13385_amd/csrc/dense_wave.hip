@@ -1,5 +1,5 @@
 // The dense stage in one workgroup per solve, for padded ranks R <= 8 and at
-// most 8 slices per core: the weighted Gram sweep with the tangent components
+// most 16 slices per core: the weighted Gram sweep with the tangent components
 // (k_gram_wave) and the retraction with the new cores and the stopping test
 // (k_retract_wave).
 //
@@ -856,9 +856,10 @@ __global__ void __launch_bounds__(64 * NWAVE) k_gram_wave(const Dev *__restrict_
 }
 
 // The one-workgroup sweeps apply when every member of the batch has R <= 8, at
-// most 8 slices per core (beyond that the slice-parallel launches win) and
+// most 16 slices per core (one wave walks each core's slices in turn, so for
+// long cores the slice-parallel launches win) and
 // cores that fit the LDS of one workgroup next to the work tiles.
-constexpr int WAVE_MAX_N = 8;
+constexpr int WAVE_MAX_N = 16;
 constexpr size_t WAVE_MAX_LDS = 150 * 1024;
 
 hipError_t launch_retract_wave(const Batch &bt, hipStream_t s, int init, bool &used) {
