@@ -5,9 +5,10 @@ The chain kernel applies when every core from some split u on has a mode size
 within one MFMA tile's slice range; the modes before u are shared by a whole
 chunk of samples.  The cases cover u = 0, 1, 2 and 3, padded ranks 2, 4 and 8,
 a first mode larger than the tile range (shared, so allowed), prefixes cut
-into several chunks, a single partial batch, and float64 rank-8 chains of 8,
-12 and 16 unshared cores, whose right interfaces do not all fit the per-wave
-LDS slots and are parked in segments.
+into several chunks, a single partial batch, and float64 rank-8 chains of 4
+unshared cores (the fewest the plan gives at rank 8) and of 8, 12 and 16,
+whose right interfaces do not all fit the per-wave LDS slots and are parked
+in segments.
 
 Bars: sampled pass in float64 within 1e-12 of the reference (sums in another
 order); iterates within 1e-10 per iteration; the pass repeats bit for bit
@@ -71,6 +72,9 @@ def chain_case(name):
     if name == "u0_r8_o16":      # order 16, u = 0: sixteen unshared cores, five segments
         shape = [4] * 16
         return wl.problem(shape, wl.feasible_ranks(shape, 8), 3000, 33, name=name, init_rel=0.1)
+    if name == "u0_r8_o4":       # order 4, rank 8, u = 0: the fewest unshared cores the plan
+        shape = [4] * 4          # can give at rank 8 (two generic cores)
+        return wl.problem(shape, wl.feasible_ranks(shape, 8), 200, 34, name=name, init_rel=0.1)
     if name == "tiny":           # fewer samples than one wave
         shape = [4, 3, 4, 3]
         return wl.problem(shape, [1, 3, 4, 3, 1], 20, 27, name=name, init_rel=0.1)
@@ -81,7 +85,7 @@ def chain_case(name):
 
 
 CASES = ["u0_r8", "u1_r8", "u2_r4", "u1_r2_n16", "u1_wide_first", "u3_split", "tiny", "ragged_r4", "u1_r8_o9",
-         "u0_r8_o12", "u0_r8_o16"]
+         "u0_r8_o12", "u0_r8_o16", "u0_r8_o4"]
 
 
 def observed(pb):
