@@ -4,6 +4,11 @@
 
 Every HIP source under csrc/ is compiled to an object in _build/ and linked
 into paper_2501_13385_amd/libprgd.so.  Sources are always recompiled.
+
+build_host_sanitized(out_dir) makes a checking variant in out_dir: the same
+sources with AddressSanitizer and UndefinedBehaviorSanitizer on the host code
+only (device code is built as usual), linked against the shared sanitizer
+runtime, which the loading process must preload.
 """
 
 from __future__ import annotations
@@ -43,9 +48,14 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
+# host-side sanitizers: each flag applies to the host compilation only
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src: str, obj_dir: str = BUILD, extra=()) -> str:
+    obj = os.path.join(obj_dir, os.path.basename(src)[:-4] + ".o")
+    cmd = [hipcc(), *COMMON, *extra, "-c", src, "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
@@ -74,24 +84,44 @@ def _runtime_stub() -> str:
     return d
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def _build_into(lib: str, obj_dir: str, extra=(), link_extra=()) -> str:
+    os.makedirs(obj_dir, exist_ok=True)
     stub = _runtime_stub()
     srcs = sources()
     jobs = min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, obj_dir, extra), srcs))
+    tmp = lib + ".tmp"
     rocm_lib = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(hipcc()))), "lib")
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", f"-L{stub}", "-Wl,--no-as-needed",
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *link_extra, f"-L{stub}", "-Wl,--no-as-needed",
            f"-Wl,-rpath,{rocm_lib}", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    _build_into(LIB, BUILD)
     if verbose:
         print(f"built {LIB}")
     return LIB
+
+
+def build_host_sanitized(out_dir: str) -> str:
+    """libprgd.so with host-side ASan + UBSan in out_dir (a checking build)."""
+    link = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-shared-libsan"]
+    return _build_into(os.path.join(out_dir, "libprgd.so"), os.path.join(out_dir, "obj"), HOST_SANITIZE, link)
+
+
+def sanitizer_runtime() -> str:
+    """Path of the shared ASan runtime of the compiler that builds the library."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "lib", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    res = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    return res.stdout.strip()
 
 
 if __name__ == "__main__":
